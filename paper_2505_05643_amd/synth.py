@@ -1,0 +1,337 @@
+"""Seeded synthetic workloads for the probe-plane rasterizer.
+
+This module only draws inputs: Gaussian sets in the paper's triangular
+precision parameterization (Section 4.2, Eq. 11) and probe-plane poses with
+pixel grids (Section 4.1, Eq. 8-9).  It contains none of the rendering
+arithmetic, so both the FP64 reference in ``oracle/`` and the HIP path can be
+fed from it without sharing any of the method's code.
+
+Conventions (shared by every consumer of these arrays):
+
+* ``means``      float32 [N, 3]  world coordinates.
+* ``lraw``       float32 [N, 6]  raw entries (l11, l21, l31, l22, l32, l33) of
+  the lower-triangular precision factor; the diagonal entries are activated
+  as ``l**2 + beta`` (Eq. 11; the repeated ``L12`` printed at position (3,2)
+  is read as an independent ``L32``).
+* ``intensity``  float32 [N]     grey level c_i.
+* ``opacity``    float32 [N]     logit a_i, alpha_i = sigmoid(a_i).
+* ``rot``        float32 [P, 9]  row-major 3x3 whose columns are the in-plane
+  axes e1, e2 and the normal n (probe -> world, right-handed).
+* ``origin``     float32 [P, 3]  world position of the image centre.
+* ``spacing``    float32 [P, 2]  world units per pixel along e1, e2.
+* ``wh``         int32   [P, 2]  (W, H) pixels.
+
+Pixel (u, v) sits at in-plane coordinates
+((u + 1/2 - W/2) sx, (v + 1/2 - H/2) sy); images are packed plane after
+plane, row-major (index v*W + u).
+
+Covariances are drawn as scales + rotations (the form the workload
+descriptions use) and converted once, in FP64, to the factor L with
+L L^T = R diag(s^-2) R^T; the raw diagonal is sqrt(L_kk - beta).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+DEFAULT_BETA = 1e-4
+
+
+@dataclasses.dataclass
+class Gaussians:
+    means: np.ndarray
+    lraw: np.ndarray
+    intensity: np.ndarray
+    opacity: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    def subset(self, idx) -> "Gaussians":
+        return Gaussians(self.means[idx], self.lraw[idx], self.intensity[idx],
+                         self.opacity[idx])
+
+
+@dataclasses.dataclass
+class Planes:
+    rot: np.ndarray
+    origin: np.ndarray
+    spacing: np.ndarray
+    wh: np.ndarray
+
+    @property
+    def p(self) -> int:
+        return int(self.rot.shape[0])
+
+    @property
+    def npix(self) -> int:
+        return int(np.sum(self.wh[:, 0].astype(np.int64) * self.wh[:, 1]))
+
+    def pixel_offsets(self) -> np.ndarray:
+        sizes = self.wh[:, 0].astype(np.int64) * self.wh[:, 1]
+        return np.concatenate([[0], np.cumsum(sizes)])
+
+    def subset(self, idx) -> "Planes":
+        idx = np.atleast_1d(idx)
+        return Planes(self.rot[idx], self.origin[idx], self.spacing[idx],
+                      self.wh[idx])
+
+
+# ---------------------------------------------------------------- rotations
+def quat_to_rot(q: np.ndarray) -> np.ndarray:
+    """Unit quaternions (w, x, y, z) [N, 4] -> rotation matrices [N, 3, 3]."""
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    r = np.empty((q.shape[0], 3, 3))
+    r[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    r[:, 0, 1] = 2 * (x * y - w * z)
+    r[:, 0, 2] = 2 * (x * z + w * y)
+    r[:, 1, 0] = 2 * (x * y + w * z)
+    r[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    r[:, 1, 2] = 2 * (y * z - w * x)
+    r[:, 2, 0] = 2 * (x * z - w * y)
+    r[:, 2, 1] = 2 * (y * z + w * x)
+    r[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return r
+
+
+def axis_angle(axis, angle: float) -> np.ndarray:
+    """Rodrigues rotation about a (not necessarily unit) axis."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    k = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(angle) * k + (1 - math.cos(angle)) * (k @ k)
+
+
+# ---------------------------------------------------------------- Gaussians
+def scales_rots_to_lraw(scales: np.ndarray, rots: np.ndarray,
+                        beta: float = DEFAULT_BETA) -> np.ndarray:
+    """(s [N,3], R [N,3,3]) -> raw triangular parameters [N,6] (FP64).
+
+    Precision R diag(s^-2) R^T, its lower Cholesky factor L, then the raw
+    diagonal sqrt(L_kk - beta).  Requires L_kk > beta (true whenever
+    1/max(s) > beta, since every Cholesky pivot is at least the smallest
+    eigenvalue's square root).
+    """
+    prec = rots @ (np.eye(3)[None] * (scales[:, None, :] ** -2)) @ np.transpose(rots, (0, 2, 1))
+    prec = 0.5 * (prec + np.transpose(prec, (0, 2, 1)))
+    lf = np.linalg.cholesky(prec)
+    diag = np.stack([lf[:, 0, 0], lf[:, 1, 1], lf[:, 2, 2]], axis=1)
+    if np.any(diag <= beta):
+        raise ValueError("scale too large for beta: L_kk <= beta")
+    raw = np.stack([np.sqrt(lf[:, 0, 0] - beta), lf[:, 1, 0], lf[:, 2, 0],
+                    np.sqrt(lf[:, 1, 1] - beta), lf[:, 2, 1],
+                    np.sqrt(lf[:, 2, 2] - beta)], axis=1)
+    return raw
+
+
+def random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    return quat_to_rot(rng.standard_normal((n, 4)))
+
+
+def make_gaussians(n: int, seed: int, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
+                   scale_range=(0.005, 0.05), aniso_max: float | None = None,
+                   intensity: str = "uniform", opacity="paper",
+                   beta: float = DEFAULT_BETA) -> Gaussians:
+    """Means uniform in the box [lo, hi]; scales log-uniform per axis.
+
+    ``aniso_max``: if given, the smallest scale is drawn log-uniform in
+    ``scale_range`` and the other two are that times an independent
+    log-uniform factor in [1, aniso_max].
+    ``intensity``: "uniform" -> U(0,1); "gamma" -> Gamma(shape 2, scale 0.25).
+    ``opacity``: "paper" -> logit 1 (alpha = 0.731); "random" -> U(-2, 2);
+    or a float logit.
+    """
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    means = lo + (hi - lo) * rng.random((n, 3))
+    ls0, ls1 = math.log(scale_range[0]), math.log(scale_range[1])
+    if aniso_max is None:
+        scales = np.exp(rng.uniform(ls0, ls1, size=(n, 3)))
+    else:
+        smin = np.exp(rng.uniform(ls0, ls1, size=(n, 1)))
+        ratio = np.exp(rng.uniform(0.0, math.log(aniso_max), size=(n, 2)))
+        scales = np.concatenate([smin, smin * ratio], axis=1)
+        # shuffle which axis is the thin one
+        perm = np.argsort(rng.random((n, 3)), axis=1)
+        scales = np.take_along_axis(scales, perm, axis=1)
+    rots = random_rotations(rng, n)
+    lraw = scales_rots_to_lraw(scales, rots, beta)
+    if intensity == "uniform":
+        c = rng.random(n)
+    elif intensity == "gamma":
+        c = rng.gamma(2.0, 0.25, size=n)
+    else:
+        raise ValueError(intensity)
+    if isinstance(opacity, str):
+        if opacity == "paper":
+            a = np.ones(n)
+        elif opacity == "random":
+            a = rng.uniform(-2.0, 2.0, size=n)
+        else:
+            raise ValueError(opacity)
+    else:
+        a = np.full(n, float(opacity))
+    f = np.float32
+    return Gaussians(means.astype(f), lraw.astype(f), c.astype(f), a.astype(f))
+
+
+# ---------------------------------------------------------------- planes
+def frame_from_normal(normal, angle: float) -> np.ndarray:
+    """Right-handed frame [e1 e2 n] with the given normal and in-plane angle."""
+    n = np.asarray(normal, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    helper = np.array([1.0, 0.0, 0.0]) if abs(n[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(helper, n)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(n, e1)
+    c, s = math.cos(angle), math.sin(angle)
+    e1r = c * e1 + s * e2
+    e2r = -s * e1 + c * e2
+    return np.stack([e1r, e2r, n], axis=1)
+
+
+def pack_planes(frames, origins, spacings, whs) -> Planes:
+    frames = np.asarray(frames, dtype=np.float64)
+    rot = frames.reshape(-1, 9)
+    return Planes(rot.astype(np.float32),
+                  np.asarray(origins, dtype=np.float32).reshape(-1, 3),
+                  np.asarray(spacings, dtype=np.float32).reshape(-1, 2),
+                  np.asarray(whs, dtype=np.int32).reshape(-1, 2))
+
+
+def random_planes(p: int, seed: int, wh=(128, 128), spacing=1.0 / 128,
+                  centre_lo=0.25, centre_hi=0.75) -> Planes:
+    """Normals uniform on the sphere, in-plane angle U[0, 2pi), centres
+    uniform in [centre_lo, centre_hi]^3."""
+    rng = np.random.default_rng(seed)
+    frames, origins = [], []
+    for _ in range(p):
+        nrm = rng.standard_normal(3)
+        frames.append(frame_from_normal(nrm, rng.uniform(0, 2 * math.pi)))
+        origins.append(rng.uniform(centre_lo, centre_hi, size=3))
+    whs = np.tile(np.asarray(wh, dtype=np.int32), (p, 1))
+    sp = np.full((p, 2), spacing)
+    return pack_planes(frames, origins, sp, whs)
+
+
+def sweep_frames(axis, tilt_axis, steps: int, centre, length: float,
+                 tilt_deg: float = 30.0):
+    """A smooth sweep: the normal starts along ``axis`` tilted by -tilt about
+    ``tilt_axis`` and ends tilted by +tilt; the centre moves linearly over
+    ``length`` along ``axis`` through ``centre``."""
+    axis = np.asarray(axis, dtype=np.float64)
+    axis = axis / np.linalg.norm(axis)
+    t_axis = np.asarray(tilt_axis, dtype=np.float64)
+    t_axis = t_axis - axis * (t_axis @ axis)
+    t_axis /= np.linalg.norm(t_axis)
+    base = np.stack([t_axis, np.cross(axis, t_axis), axis], axis=1)
+    frames, origins = [], []
+    for k in range(steps):
+        t = k / max(steps - 1, 1)
+        ang = math.radians(-tilt_deg + 2 * tilt_deg * t)
+        frames.append(axis_angle(t_axis, ang) @ base)
+        origins.append(np.asarray(centre, dtype=np.float64) + (t - 0.5) * length * axis)
+    return frames, origins
+
+
+# ---------------------------------------------------------------- configs
+CONFIG_NAMES = {
+    0: "c0: 1k Gaussians, 4 random 128^2 planes (unit cube)",
+    1: "c1: 50k Gaussians, 16-plane 160^2 sweep (160^3 voxels)",
+    2: "c2: 200k anisotropic (<=50:1) Gaussians, 64-plane 160^2 sweep",
+    3: "c3: 500k Gaussians, 128 ragged planes from 4 interleaved sweeps (256^3)",
+    4: "c4: 1M Gaussians, 256^3 volume extraction as 256 axial 256^2 planes",
+}
+
+RAGGED_SIZES = ((128, 128), (192, 160), (256, 256), (320, 240))
+
+
+def _c1_sweep(steps: int) -> Planes:
+    frames, origins = [], []
+    for k in range(steps):
+        t = k / max(steps - 1, 1)
+        frames.append(axis_angle((1, 0, 0), math.radians(-30 + 60 * t)))
+        origins.append((80.0, 80.0, 8.0 + 144.0 * t))
+    return pack_planes(frames, origins, np.ones((steps, 2)),
+                       np.tile([160, 160], (steps, 1)))
+
+
+_SWEEP_AXES = (((0, 0, 1), (1, 0, 0)), ((1, 0, 0), (0, 1, 0)),
+               ((0, 1, 0), (0, 0, 1)), ((1, 1, 1), (1, -1, 0)),
+               ((1, -1, 1), (1, 1, 0)), ((-1, 1, 1), (1, 1, 0)),
+               ((1, 1, -1), (1, -1, 0)), ((1, 1, 0), (0, 0, 1)))
+
+
+def interleaved_sweeps(n_sweeps: int, steps: int, centre=(128.0, 128.0, 128.0),
+                       length: float = 240.0):
+    per = [sweep_frames(a, t, steps, centre, length) for a, t in _SWEEP_AXES[:n_sweeps]]
+    frames, origins = [], []
+    for k in range(n_sweeps * steps):
+        f, o = per[k % n_sweeps]
+        frames.append(f[k // n_sweeps])
+        origins.append(o[k // n_sweeps])
+    return frames, origins
+
+
+def config_planes(k: int, seed: int | None = None) -> Planes:
+    seed = 300 + k if seed is None else seed
+    if k == 0:
+        return random_planes(4, seed, (128, 128), 1.0 / 128, 0.25, 0.75)
+    if k == 1:
+        return _c1_sweep(16)
+    if k == 2:
+        return _c1_sweep(64)
+    if k == 3:
+        rng = np.random.default_rng(seed)
+        frames, origins = interleaved_sweeps(4, 32)
+        whs = [RAGGED_SIZES[i] for i in rng.integers(0, 4, size=128)]
+        return pack_planes(frames, origins, np.ones((128, 2)), whs)
+    if k == 4:
+        frames = [np.eye(3)] * 256
+        origins = [(128.0, 128.0, z + 0.5) for z in range(256)]
+        return pack_planes(frames, origins, np.ones((256, 2)), np.tile([256, 256], (256, 1)))
+    raise ValueError(k)
+
+
+def config4_training_pool() -> Planes:
+    """2,048 planes of 256^2: 8 interleaved sweeps x 256 steps."""
+    frames, origins = interleaved_sweeps(8, 256)
+    return pack_planes(frames, origins, np.ones((2048, 2)), np.tile([256, 256], (2048, 1)))
+
+
+def config_gaussians(k: int, seed: int | None = None, target: bool = False) -> Gaussians:
+    seed = (200 if target else 100) + k if seed is None else seed
+    if k == 0:
+        return make_gaussians(1000, seed, (0, 0, 0), (1, 1, 1), (0.005, 0.05))
+    if k == 1:
+        return make_gaussians(50_000, seed, (0, 0, 0), (160, 160, 160), (0.5, 8.0))
+    if k == 2:
+        return make_gaussians(200_000, seed, (0, 0, 0), (160, 160, 160), (0.3, 2.0),
+                              aniso_max=50.0)
+    if k == 3:
+        return make_gaussians(500_000, seed, (0, 0, 0), (256, 256, 256), (0.5, 8.0))
+    if k == 4:
+        return make_gaussians(1_000_000, seed, (0, 0, 0), (256, 256, 256), (0.5, 8.0),
+                              intensity="gamma")
+    raise ValueError(k)
+
+
+def make_config(k: int):
+    """(gaussians, planes, target_gaussians) for workload k."""
+    return config_gaussians(k), config_planes(k), config_gaussians(k, target=True)
+
+
+def sample_pixels(planes: Planes, count: int, seed: int) -> np.ndarray:
+    """Seeded (plane, u, v) triples, uniform over all pixels of the launch."""
+    rng = np.random.default_rng(seed)
+    offs = planes.pixel_offsets()
+    flat = np.sort(rng.choice(offs[-1], size=min(count, int(offs[-1])), replace=False))
+    p = np.searchsorted(offs, flat, side="right") - 1
+    local = flat - offs[p]
+    w = planes.wh[p, 0].astype(np.int64)
+    return np.stack([p, local % w, local // w], axis=1)
