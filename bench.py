@@ -1,0 +1,287 @@
+"""Benchmark: forward + backward planes/s of the probe-plane rasterizer.
+
+One step = one pass of the whole hot path over one batch of planes: the
+culling/record pass, key emission, the radix sort by tile, the per-tile
+accumulation (forward), the MSE gradient against a target image, the
+per-key adjoint, the per-record reduction and the per-Gaussian adjoint.
+Inputs are seeded synthetic workloads already resident in device memory.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
+
+Prints ONE JSON line.  Extra keys: in-support pair evaluations per second,
+the plain per-plane form on the same GPU, per-stage times, a roofline for
+the dominant kernel (timed with HIP events on its launch stream inside the
+timed region) and the FP64 oracle's rate on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd planes/s and Gaussian-pixel evals/s vs plain per-plane, at 1e-4 err"
+
+# Algorithmic FP32 work per in-support (Gaussian, pixel) pair, counted on
+# the conic form of Eq. 8 restricted to the plane:
+#   forward: du, dv (2), t1 = T11 du + T12 dv (3), t2 = T22 dv (1),
+#            s = t1^2 + t2^2 (3), e = e0 - s (1), cut-off compare (1),
+#            exp2 (1), D += w (1), N += w c (2)                        = 16
+#   adjoint: the forward's first 13 plus dL/dw = gamma (c - c_hat) (2),
+#            w dL/dw (1), dc += gamma w (2), de0 (1), dT11 (3), dT12 (2),
+#            dT22 (3), du0 (1), dv0 (4)                                = 32
+FLOPS_PER_PAIR = {"accum": 16, "accum_bwd": 32}
+# Peak of the scalar (non-packed) FP32 vector ALU: 256 CUs x 4 SIMDs x 16
+# lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32 is not used by this build.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(k: int, n_px: int) -> dict:
+    """The FP64 oracle, forward + adjoint, on a seeded pixel sample of plane 0
+    with every Gaussian, in a single-threaded child process."""
+    code = f"""
+import json, sys, time
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+import oracle
+from paper_2505_05643_amd import synth
+g, pl, _ = synth.make_config({k})
+one = pl.subset(0)
+pix = synth.sample_pixels(one, {n_px}, 901)
+X = oracle.plane_points(one, pix)
+t0 = time.perf_counter()
+out, _ = oracle.render_points(g, X)
+gr = oracle.grad_points(g, X, np.ones(len(X)))
+dt = time.perf_counter() - t0
+print(json.dumps({{"seconds": dt, "pix": pix.tolist(), "values": out.tolist(),
+                  "plane_px": int(one.wh[0, 0] * one.wh[0, 1])}}))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError("oracle baseline failed:\n" + r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--tile", type=str, default=None, help="WxH[xPPL], e.g. 16x16x1")
+    ap.add_argument("--lds-batch", type=int, default=None)
+    ap.add_argument("--box", type=int, default=None, help="0 paper, 1 conic, 2 rows")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-plane comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-px", type=int, default=640)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU (plane-sharded) path is a design, "
+              "not an implementation. Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2505_05643_amd import synth
+    from paper_2505_05643_amd import raster as R
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    k = args.config
+    g, pl, tg = synth.make_config(k)
+    gd, pd, tgd = R.to_device(g, dev), R.to_device(pl, dev), R.to_device(tg, dev)
+
+    params = R.Params()
+    try:
+        from paper_2505_05643_amd import autotune
+        params = autotune.cached_params(k) or params
+    except Exception:
+        pass
+    if args.tile:
+        parts = [int(x) for x in args.tile.lower().split("x")]
+        params.tile_w, params.tile_h = parts[0], parts[1]
+        params.px_per_lane = parts[2] if len(parts) > 2 else 0
+    if args.lds_batch:
+        params.lds_batch = args.lds_batch
+    if args.box is not None:
+        params.box_mode = args.box
+
+    # target image: the second seeded Gaussian set rendered on the same planes
+    tplan = R.Plan(tg.n, pl.wh, params, device=dev)
+    tplan.fit(tgd, pd)
+    target = tplan.render(tgd, pd).clone()
+    del tplan
+
+    plan = R.Plan(g.n, pl.wh, params, device=dev)
+    n_rec, n_key = plan.fit(gd, pd)
+    image = torch.empty(plan.num_pixels, device=dev)
+    d_image = torch.empty_like(image)
+    loss_buf = torch.empty(1025, device=dev)
+    grads = R.GaussianTensors(torch.empty_like(gd.means), torch.empty_like(gd.lraw),
+                              torch.empty_like(gd.intensity), torch.empty_like(gd.opacity))
+
+    def step(p=plan, gg=gd, pp=pd, img=image, dimg=d_image, gr=grads, tgt=target):
+        p.render(gg, pp, img, check_status=False)
+        R.mse_grad(img, tgt, dimg, loss_buf)
+        p.backward(gg, pp, img, dimg, gr)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    code = plan.status()
+    assert code == 0, f"render status {code}"
+
+    # ---- timed region (per-stage events on the launch stream) ----
+    plan.profile_begin(max_launches=args.steps * 16 + 16)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_total = t0.elapsed_time(t1)
+    stages = plan.profile_read()
+    ms_step = ms_total / args.steps
+    planes_s = pl.p * args.steps / (ms_total / 1e3)
+
+    # in-support pairs of one forward, counted by the kernel itself
+    cparams = R.Params(**{**params.__dict__, "flags": 1})
+    cplan = R.Plan(g.n, pl.wh, cparams, device=dev)
+    cplan.fit(gd, pd)
+    cimg = cplan.render(gd, pd)
+    _, _, _, n_eval = cplan.status(counts=True)
+    assert torch.equal(cimg, image), "counting variant must render the same image"
+    del cplan
+    tpx = params.tile_w * params.tile_h
+    evals_s = n_eval * args.steps / (ms_total / 1e3)
+
+    # ---- plain per-plane form: the same library, one plan per plane ----
+    plain = None
+    if not args.no_plain:
+        per = []
+        for i in range(pl.p):
+            one = pl.subset(i)
+            pdi = R.to_device(one, dev)
+            pli = R.Plan(g.n, one.wh, params, device=dev)
+            pli.fit(gd, pdi)
+            off = int(pl.pixel_offsets()[i])
+            npx = int(one.wh[0, 0] * one.wh[0, 1])
+            per.append((pli, pdi, image[off:off + npx], d_image[off:off + npx], target[off:off + npx]))
+        gsum = R.GaussianTensors(*(torch.zeros_like(t) for t in grads))
+
+        def plain_step():
+            for j, (pli, pdi, img, dimg, tgt) in enumerate(per):
+                pli.render(gd, pdi, img, check_status=False)
+            R.mse_grad(image, target, d_image, loss_buf)
+            for j, (pli, pdi, img, dimg, tgt) in enumerate(per):
+                pli.backward(gd, pdi, img, dimg, gsum, accumulate=j > 0)
+
+        for _ in range(max(2, args.warmup // 2)):
+            plain_step()
+        torch.cuda.synchronize()
+        psteps = max(3, args.steps // 4)
+        t0.record()
+        for _ in range(psteps):
+            plain_step()
+        t1.record()
+        torch.cuda.synchronize()
+        pms = t0.elapsed_time(t1) / psteps
+        plain = {"planes_per_s": pl.p / (pms / 1e3), "ms_per_step": pms,
+                 "batched_speedup": (pl.p / (ms_step / 1e3)) / (pl.p / (pms / 1e3))}
+        del per
+
+    # ---- roofline of the dominant kernel ----
+    dom = max(stages.items(), key=lambda kv: kv[1][0])
+    dom_name, (dom_ms, dom_n) = dom
+    avg_ms = dom_ms / max(dom_n, 1)
+    if dom_name in FLOPS_PER_PAIR:
+        ach = n_eval * FLOPS_PER_PAIR[dom_name] / (avg_ms / 1e3) / 1e12
+        roof = {"bound": "alu", "kernel": dom_name, "achieved": ach, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / ALU_PEAK_TFLOPS, "traffic": None,
+                "work": f"{FLOPS_PER_PAIR[dom_name]} flop x {n_eval} in-support pairs per launch",
+                "avg_launch_ms": avg_ms}
+    else:
+        nbytes = {"sort": n_key * 20 * ((plan_bits(plan) + 7) // 8), "cull": g.n * 44,
+                  "write": n_rec * 56 + g.n * 44, "emit": n_key * 8 + n_rec * 24}.get(dom_name, 0)
+        ach = nbytes / (avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom_name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms}
+    # the accumulate kernels are reported either way
+    acc = {}
+    for nm in ("accum", "accum_bwd"):
+        if nm in stages:
+            ms, n = stages[nm]
+            a = n_eval * FLOPS_PER_PAIR[nm] / (ms / n / 1e3) / 1e12
+            acc[nm] = {"avg_launch_ms": ms / n, "tflops": a, "frac": a / ALU_PEAK_TFLOPS,
+                       "executed_pairs_per_launch": n_key * tpx}
+
+    out = {
+        "metric": METRIC,
+        "value": planes_s,
+        "unit": "planes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": synth.CONFIG_NAMES[k], "gaussians": g.n, "planes": pl.p,
+                   "pixels": int(pl.npix), "tile": f"{params.tile_w}x{params.tile_h}",
+                   "px_per_lane": plan_ppl(params), "lds_batch": params.lds_batch, "box_mode": params.box_mode,
+                   "step": "render + mse grad + backward"},
+        "evals_per_s": evals_s,
+        "in_support_pairs": n_eval,
+        "records": n_rec,
+        "keys": n_key,
+        "tile_efficiency": n_eval / max(n_key * tpx, 1),
+        "plain_per_plane": plain,
+        "stage_ms_per_step": {nm: v[0] / args.steps for nm, v in stages.items()},
+        "accumulate_kernels": acc,
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(k, args.cpu_px)
+        frac_plane = len(cb["pix"]) / cb["plane_px"]
+        pix = np.asarray(cb["pix"])
+        img0 = image[: cb["plane_px"]].cpu().numpy().astype(np.float64)
+        w0 = int(pl.wh[0, 0])
+        gpu_vals = img0[pix[:, 2] * w0 + pix[:, 1]]
+        ref = np.asarray(cb["values"])
+        out["cpu_baseline"] = {"value": frac_plane / cb["seconds"], "unit": "planes/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{len(cb['pix'])} seeded pixels of plane 0 x all {g.n} Gaussians, "
+                                         f"FP64 forward + adjoint, {cb['seconds']:.1f} s, scaled to one plane"}
+        out["parity_sample_max_rel"] = float(np.abs(gpu_vals - ref).max() / max(np.abs(ref).max(), 1e-30))
+    print(json.dumps(out), flush=True)
+
+
+def plan_bits(plan) -> int:
+    t = max(plan.num_tiles, 2)
+    return int(np.ceil(np.log2(t)))
+
+
+def plan_ppl(params) -> int:
+    if params.px_per_lane:
+        return params.px_per_lane
+    px = params.tile_w * params.tile_h
+    return px // 256 if px >= 512 else 1
+
+
+if __name__ == "__main__":
+    main()

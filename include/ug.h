@@ -1,0 +1,206 @@
+/*
+ * ug.h - C ABI of the UltraGauss probe-plane rasterizer for AMD MI355X (gfx950).
+ *
+ * The operation (UltraGauss, Section 4.1-4.4):
+ *   For every probe plane p and pixel x of its grid, lift x to 3D (Section 4.1),
+ *   evaluate every Gaussian i by its 3D squared Mahalanobis distance d^2
+ *   (Eq. 8, after the rigid world->probe transform of Eq. 9), keep the pair
+ *   only if d^2 <= chi^2 (Eq. 12), weight it by alpha_i exp(-d^2/2), and
+ *   normalise with a background component (Eq. 5-7):
+ *       c(x) = (sum_i w_i c_i + a_BG c_BG) / (sum_i w_i + a_BG).
+ *   Precisions use the lower-triangular factor of Eq. 11 (Section 4.2):
+ *   Sigma^-1 = L L^T, L = [[l11^2+b, 0, 0], [l21, l22^2+b, 0], [l31, l32, l33^2+b]]
+ *   (the entry printed at (3,2) is read as an independent l32).
+ *   Gaussians are culled per plane and binned to tiles with the bounding box
+ *   of Eq. 13 (Section 4.3-4.4; the matrix there is read as the precision).
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers to float32, C-contiguous, owned
+ *     by the caller, unless marked "host".  Nothing is freed or retained.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously; render and backward never synchronise
+ *     and never allocate, so they can be captured in a hipGraph.
+ *   - Arguments are validated on the host before anything is enqueued; an
+ *     invalid call returns a negative UG_ERR_* code and enqueues nothing.
+ *   - Conditions only the device can see (capacity overflow, non-finite
+ *     inputs) are recorded in the workspace and read with ug_plan_status.
+ *     On a capacity overflow the render draws background only and the
+ *     backward writes zero gradients; re-plan with larger capacities.
+ *   - Thread safety: a plan may be used from one host thread at a time;
+ *     concurrent calls that share a workspace race.
+ */
+#ifndef UG_H
+#define UG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define UG_OK 0
+#define UG_ERR_INVALID_ARG (-1) /* bad pointer, size or parameter            */
+#define UG_ERR_CAPACITY (-2)    /* records or keys exceeded the plan's capacity */
+#define UG_ERR_NONFINITE (-3)   /* a Gaussian or plane held NaN/Inf (it was skipped) */
+#define UG_ERR_HIP (-4)         /* a HIP runtime call failed                 */
+#define UG_ERR_NO_DEVICE (-5)   /* no usable gfx950 device                   */
+#define UG_ERR_INTERNAL (-6)    /* a device-side consistency check failed    */
+
+/* ---- binning boxes (all give identical images) ------------------------ */
+#define UG_BOX_PAPER 0 /* Eq. 13 box of the chi^2 ellipsoid, in-plane part b_{1:2} */
+#define UG_BOX_CONIC 1 /* bounding box of the ellipse cut by the plane (tighter)  */
+#define UG_BOX_ROWS 2  /* exact extent of that ellipse per row of tiles (tightest) */
+
+/* ---- params.flags bits ------------------------------------------------ */
+#define UG_FLAG_COUNT_EVALS 1 /* forward also counts in-support (Gaussian, pixel) pairs */
+
+/* ---- pipeline stages (measurement hooks) ------------------------------- */
+#define UG_STAGE_SETUP 0     /* plane pose set-up                              */
+#define UG_STAGE_CULL 1      /* Phase-1 cull and per-Gaussian counts (Sec. 4.4) */
+#define UG_STAGE_SCAN 2      /* offsets of records and keys                     */
+#define UG_STAGE_WRITE 3     /* record (in-plane conic) construction            */
+#define UG_STAGE_EMIT 4      /* key emission: one key per (record, tile)        */
+#define UG_STAGE_SORT 5      /* radix sort of the keys by tile (all passes)     */
+#define UG_STAGE_RANGES 6    /* per-tile key ranges                             */
+#define UG_STAGE_ACCUM 7     /* per-tile accumulation, Eq. 5-8 and 12           */
+#define UG_STAGE_BWD_PREP 8  /* per-pixel adjoint inputs                        */
+#define UG_STAGE_ACCUM_BWD 9 /* per-key adjoint of the accumulation             */
+#define UG_STAGE_REDUCE 10   /* per-record sums of the key adjoints             */
+#define UG_STAGE_PREP_BWD 11 /* per-Gaussian adjoint of the record construction */
+#define UG_NUM_STAGES 12
+
+typedef struct ug_plan ug_plan; /* opaque, host-side */
+
+/* Gaussians, Section 4.2 and 4.5.  Device pointers. */
+typedef struct {
+  const float *means;     /* [n][3] world-space centres mu_i                  */
+  const float *lraw;      /* [n][6] raw (l11, l21, l31, l22, l32, l33), Eq. 11 */
+  const float *intensity; /* [n]    grey level c_i                            */
+  const float *opacity;   /* [n]    logit a_i; alpha_i = 1/(1+exp(-a_i))      */
+  int32_t n;
+} ug_gaussians;
+
+/* Probe planes, Section 4.1 / Eq. 9.  Device pointers.
+ * rot is row-major 3x3 with columns (e1, e2, n): the probe->world rotation
+ * (the inverse of W's rotation part), right-handed.  Pixel (u, v) of a W x H
+ * plane lies at world point origin + x1 e1 + x2 e2 with
+ * x1 = (u + 1/2 - W/2) sx, x2 = (v + 1/2 - H/2) sy. */
+typedef struct {
+  const float *rot;     /* [p][9] */
+  const float *origin;  /* [p][3] world position of the image centre */
+  const float *spacing; /* [p][2] (sx, sy) world units per pixel     */
+  int32_t p;
+} ug_planes;
+
+typedef struct {
+  float beta;      /* Eq. 11 diagonal shift, > 0 (default 1e-4)                  */
+  float chi2;      /* Eq. 12 bound on d^2, > 0, may be +inf (default 7.815)      */
+  float bg_alpha;  /* Eq. 5 background coefficient, > 0 (default 1e-2)           */
+  float bg_color;  /* Eq. 6 background colour (default 0)                         */
+  int32_t tile_w;  /* tile width in pixels: 8, 16 or 32 (default 16)              */
+  int32_t tile_h;  /* tile height in pixels: 8 or 16 (default 16)                 */
+  int32_t px_per_lane; /* forward pixels per lane along a row: 1, 2, 4 or 8, with
+                          tile_w*tile_h/px_per_lane a multiple of 64 (0 = auto)    */
+  int32_t lds_batch; /* records staged in LDS per batch: 32, 64, 128 or 256 (default 64) */
+  int32_t box_mode;  /* UG_BOX_* (default UG_BOX_PAPER)                           */
+  int32_t flags;     /* UG_FLAG_* bits (default 0)                                */
+} ug_params;
+
+/* Fills *out with the defaults listed above. */
+void ug_params_default(ug_params *out);
+
+/* Creates a plan for n Gaussians and p planes whose sizes are
+ * wh_host[p][2] = (W, H) (host memory, copied).  record_capacity bounds the
+ * accepted (Gaussian, plane) pairs, key_capacity the (pair, tile) keys of one
+ * render; ug_plan_measure returns the exact numbers for given inputs.
+ * Allocates the plan's small device tables on the current device.
+ * Errors: UG_ERR_INVALID_ARG (n < 0, p < 1, W or H outside [1, 32767],
+ * bad params, capacities < 0 or >= 2^31, null out), UG_ERR_HIP. */
+int ug_plan_create(int32_t n, int32_t p, const int32_t *wh_host, const ug_params *params,
+                   int64_t record_capacity, int64_t key_capacity, ug_plan **out);
+
+/* Changes the capacities (the workspace size changes with them). */
+int ug_plan_reserve(ug_plan *plan, int64_t record_capacity, int64_t key_capacity);
+
+/* Bytes of device workspace a render/backward pair needs (256-byte aligned
+ * base required).  With zero capacities this is the size ug_plan_measure needs. */
+size_t ug_plan_workspace_bytes(const ug_plan *plan);
+
+/* Total pixels of the plan (sum of W*H): the length of image buffers. */
+int64_t ug_plan_num_pixels(const ug_plan *plan);
+
+/* Number of tiles of the plan's tile grid over all planes. */
+int64_t ug_plan_num_tiles(const ug_plan *plan);
+
+/* Runs the culling pass only and returns, synchronously, out_host[0] = the
+ * accepted (Gaussian, plane) records and out_host[1] = the (record, tile)
+ * keys that ug_render_planes would produce for these inputs.
+ * The workspace must hold ug_plan_workspace_bytes() of a zero-capacity plan. */
+int ug_plan_measure(const ug_plan *plan, const ug_gaussians *g, const ug_planes *planes,
+                    void *workspace, int64_t *out_host, void *stream);
+
+/* Forward render (Section 4.1-4.4).  image: [num_pixels] float32, packed
+ * plane after plane, row-major (index v*W + u).  Fills the workspace with the
+ * state the backward needs (records, sorted keys, per-pixel denominators). */
+int ug_render_planes(const ug_plan *plan, const ug_gaussians *g, const ug_planes *planes,
+                     float *image, void *workspace, void *stream);
+
+/* Adjoint of ug_render_planes for an upstream gradient d_image (same layout
+ * as image).  image and workspace must be those the matching forward wrote,
+ * unchanged.  Gradients are with respect to the raw parameters:
+ * d_means [n][3], d_lraw [n][6], d_intensity [n], d_opacity [n] (logits).
+ * accumulate = 0 overwrites them, 1 adds to them.  The cut-off set of Eq. 12
+ * is held fixed (the map is piecewise smooth).  Deterministic: no atomics. */
+int ug_render_planes_backward(const ug_plan *plan, const ug_gaussians *g,
+                              const ug_planes *planes, const float *image,
+                              const float *d_image, void *workspace, float *d_means,
+                              float *d_lraw, float *d_intensity, float *d_opacity,
+                              int32_t accumulate, void *stream);
+
+/* Reads the device-side status the last render left in the workspace
+ * (synchronises the stream): UG_OK, UG_ERR_CAPACITY, UG_ERR_NONFINITE or
+ * UG_ERR_INTERNAL.  counts_host (may be NULL) receives [records, keys,
+ * in-support pairs] of that render; the third is 0 unless the plan was
+ * created with UG_FLAG_COUNT_EVALS. */
+int ug_plan_status(const ug_plan *plan, const void *workspace, int64_t *counts_host,
+                   void *stream);
+
+/* Measurement hooks (not for use under graph capture).  ug_profile_begin
+ * makes the plan record a pair of HIP events on the launch stream around
+ * each kernel launch of the stages whose bit is set in stage_mask
+ * (bit UG_STAGE_*), for at most max_launches launches; the events are
+ * created here.  ug_profile_read synchronises on the last event, writes the
+ * summed milliseconds and launch counts per stage (arrays of UG_NUM_STAGES,
+ * either may be NULL), and turns recording off. */
+int ug_profile_begin(ug_plan *plan, uint32_t stage_mask, int32_t max_launches);
+int ug_profile_read(ug_plan *plan, float *ms_host, int32_t *launches_host);
+
+/* Mean squared error over m pixels: loss_dev[0] = mean((image - target)^2)
+ * and d_image = 2 (image - target) / m (the training loss; the paper trains
+ * the Gaussians by gradient descent on rendered slices, Section 4.5).
+ * loss_dev must hold UG_MSE_SCRATCH_FLOATS floats: [0] receives the loss,
+ * the rest is scratch for the deterministic two-level reduction. */
+#define UG_MSE_SCRATCH_FLOATS 1025
+int ug_mse_grad(const float *image, const float *target, int64_t m, float *d_image,
+                float *loss_dev, void *stream);
+
+/* One Adam step over `count` parameters (Section 4.5 trains with Adam):
+ *   mo = b1 mo + (1-b1) g;  ve = b2 ve + (1-b2) g^2;
+ *   p -= lr * (mo / (1 - b1^t)) / (sqrt(ve / (1 - b2^t)) + eps).
+ * step_t >= 1 is the 1-based step number. */
+int ug_adam_step(float *param, const float *grad, float *mo, float *ve, int64_t count,
+                 float lr, float beta1, float beta2, float eps, int32_t step_t, void *stream);
+
+/* Human-readable text for a status code (static storage). */
+const char *ug_status_string(int status);
+
+/* Frees the plan and its device tables.  NULL is ignored. */
+void ug_plan_destroy(ug_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UG_H */

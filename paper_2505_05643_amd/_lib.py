@@ -1,0 +1,97 @@
+"""ctypes loader of libug.so (include/ug.h).  Argument marshalling only.
+
+The library is built in-tree by ``paper_2505_05643_amd.build``.  There is no
+fallback: if it is missing or cannot be loaded, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libug.so")
+
+UG_OK = 0
+UG_ERR_INVALID_ARG = -1
+UG_ERR_CAPACITY = -2
+UG_ERR_NONFINITE = -3
+UG_ERR_HIP = -4
+UG_ERR_NO_DEVICE = -5
+UG_ERR_INTERNAL = -6
+
+UG_BOX_PAPER = 0
+UG_BOX_CONIC = 1
+UG_BOX_ROWS = 2
+
+UG_MSE_SCRATCH_FLOATS = 1025
+UG_FLAG_COUNT_EVALS = 1
+
+STAGES = ("setup", "cull", "scan", "write", "emit", "sort", "ranges", "accum", "bwd_prep", "accum_bwd",
+          "reduce", "prep_bwd")
+UG_NUM_STAGES = len(STAGES)
+
+c_i32, c_i64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
+
+
+class UgGaussians(ctypes.Structure):
+    _fields_ = [("means", c_vp), ("lraw", c_vp), ("intensity", c_vp), ("opacity", c_vp), ("n", c_i32)]
+
+
+class UgPlanes(ctypes.Structure):
+    _fields_ = [("rot", c_vp), ("origin", c_vp), ("spacing", c_vp), ("p", c_i32)]
+
+
+class UgParams(ctypes.Structure):
+    _fields_ = [("beta", c_f32), ("chi2", c_f32), ("bg_alpha", c_f32), ("bg_color", c_f32),
+                ("tile_w", c_i32), ("tile_h", c_i32), ("px_per_lane", c_i32),
+                ("lds_batch", c_i32), ("box_mode", c_i32), ("flags", c_i32)]
+
+
+# name -> (restype, argtypes); mirrors include/ug.h
+SIGNATURES = {
+    "ug_params_default": (None, [ctypes.POINTER(UgParams)]),
+    "ug_plan_create": (c_i32, [c_i32, c_i32, ctypes.POINTER(c_i32), ctypes.POINTER(UgParams),
+                               c_i64, c_i64, ctypes.POINTER(c_vp)]),
+    "ug_plan_reserve": (c_i32, [c_vp, c_i64, c_i64]),
+    "ug_plan_workspace_bytes": (ctypes.c_size_t, [c_vp]),
+    "ug_plan_num_pixels": (c_i64, [c_vp]),
+    "ug_plan_num_tiles": (c_i64, [c_vp]),
+    "ug_plan_measure": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp,
+                                ctypes.POINTER(c_i64), c_vp]),
+    "ug_render_planes": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp, c_vp, c_vp]),
+    "ug_render_planes_backward": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp,
+                                          c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "ug_plan_status": (c_i32, [c_vp, c_vp, ctypes.POINTER(c_i64), c_vp]),
+    "ug_mse_grad": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "ug_adam_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_f32, c_f32, c_f32, c_f32, c_i32, c_vp]),
+    "ug_profile_begin": (c_i32, [c_vp, ctypes.c_uint32, c_i32]),
+    "ug_profile_read": (c_i32, [c_vp, ctypes.POINTER(c_f32), ctypes.POINTER(c_i32)]),
+    "ug_status_string": (ctypes.c_char_p, [c_i32]),
+    "ug_plan_destroy": (None, [c_vp]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_05643_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class UgError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {lib.ug_status_string(code).decode()} ({code})")
+
+
+def check(code: int, what: str) -> int:
+    if code != UG_OK:
+        raise UgError(code, what)
+    return code

@@ -1,0 +1,521 @@
+// Host side of the C ABI (include/ug.h): plans, workspace layout, argument
+// validation and the enqueue order of the render and backward passes.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ug_kernels.h"
+
+using namespace ug;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  // culling pass (ug_plan_measure needs only these)
+  size_t ctrl, pconst, cnt_rec, cnt_key, blk_rec, blk_key, blk_rec_off, blk_key_off;
+  size_t measure_end;
+  // render state
+  size_t off_rec, tile_start, dsave, gq, hist;
+  size_t racc, rgeo, rec_pid, rec_koff, drec;
+  size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, partial;
+  size_t total;
+};
+
+}  // namespace
+
+struct ug_plan {
+  int32_t n = 0, p = 0;
+  ug_params prm{};
+  int ppl = 1;
+  uint32_t num_tiles = 0;
+  uint64_t num_pixels = 0;
+  int bits = 1;
+  int final_buf = 0;
+  uint32_t rec_cap = 0, key_cap = 0;
+  uint32_t sort_blocks = 1;
+  int nblk = 0;
+  int device = 0;
+  PlaneInt* d_pint = nullptr;
+  uint32_t* d_tile_plane = nullptr;
+  Layout lay{};
+  // Measurement hooks: event pairs around the launches of selected stages.
+  struct Prof {
+    bool on = false;
+    uint32_t mask = 0;
+    int cap = 0, used = 0;
+    std::vector<hipEvent_t> ev;  // 2 * cap
+    std::vector<int> stage;      // cap
+  };
+  mutable Prof prof;
+};
+
+namespace {
+
+void compute_layout(ug_plan* pl) {
+  Layout& L = pl->lay;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + (bytes ? bytes : 1));
+    return at;
+  };
+  const size_t n = (size_t)pl->n, P = (size_t)pl->p, nblk = (size_t)(pl->nblk > 0 ? pl->nblk : 1);
+  L.ctrl = take(sizeof(Ctrl));
+  L.pconst = take(P * sizeof(PlaneConst));
+  L.cnt_rec = take(n * 4);
+  L.cnt_key = take(n * 4);
+  L.blk_rec = take(nblk * 4);
+  L.blk_key = take(nblk * 4);
+  L.blk_rec_off = take(nblk * 8);
+  L.blk_key_off = take(nblk * 8);
+  L.measure_end = o;
+  const size_t T = pl->num_tiles, R = pl->rec_cap, K = pl->key_cap;
+  const size_t tpx = (size_t)pl->prm.tile_w * pl->prm.tile_h;
+  L.off_rec = take(n * 4);
+  L.tile_start = take((T + 1) * 4);
+  L.dsave = take(pl->num_pixels * 4);
+  L.gq = take(T * tpx * 8);
+  L.hist = take((size_t)256 * pl->sort_blocks * 4);
+  L.racc = take(R * sizeof(RecAcc));
+  L.rgeo = take(R * sizeof(RecGeo));
+  L.rec_pid = take(R * 4);
+  L.rec_koff = take((R + 1) * 4);
+  L.drec = take(R * 32);
+  L.key_tile0 = take(K * 4);
+  L.key_tile1 = take(K * 4);
+  L.key_val0 = take(K * 4);
+  L.key_val1 = take(K * 4);
+  L.rec_of_key = take(K * 4);
+  L.srec = take(K * 4);
+  L.partial = take(K * 32);
+  L.total = o;
+}
+
+template <typename T>
+inline T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+bool valid_params(const ug_params& p) {
+  if (!(p.beta > 0.f) || !std::isfinite(p.beta)) return false;
+  if (!(p.chi2 > 0.f)) return false;  // +inf allowed, NaN rejected
+  if (!(p.bg_alpha > 0.f) || !std::isfinite(p.bg_alpha)) return false;
+  if (!std::isfinite(p.bg_color)) return false;
+  if (p.box_mode != UG_BOX_PAPER && p.box_mode != UG_BOX_CONIC && p.box_mode != UG_BOX_ROWS) return false;
+  if ((p.flags & ~UG_FLAG_COUNT_EVALS) != 0) return false;
+  const int ppl = p.px_per_lane ? p.px_per_lane : accum_default_ppl(p.tile_w, p.tile_h);
+  return accum_config_supported(p.tile_w, p.tile_h, ppl, p.lds_batch);
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? UG_OK : UG_ERR_HIP; }
+
+// Records a begin/end event pair around one launch when the stage is profiled.
+class StageScope {
+ public:
+  StageScope(const ug_plan* pl, int stage, hipStream_t s) : pl_(pl), s_(s) {
+    ug_plan::Prof& P = pl->prof;
+    if (P.on && ((P.mask >> stage) & 1u) && P.used < P.cap) {
+      slot_ = P.used++;
+      P.stage[(size_t)slot_] = stage;
+      (void)hipEventRecord(P.ev[2 * (size_t)slot_], s_);
+    }
+  }
+  ~StageScope() {
+    if (slot_ >= 0) (void)hipEventRecord(pl_->prof.ev[2 * (size_t)slot_ + 1], s_);
+  }
+  StageScope(const StageScope&) = delete;
+  StageScope& operator=(const StageScope&) = delete;
+
+ private:
+  const ug_plan* pl_;
+  hipStream_t s_;
+  int slot_ = -1;
+};
+
+void prof_release(ug_plan* pl) {
+  for (hipEvent_t e : pl->prof.ev) (void)hipEventDestroy(e);
+  pl->prof.ev.clear();
+  pl->prof.stage.clear();
+  pl->prof.cap = pl->prof.used = 0;
+  pl->prof.on = false;
+}
+
+RenderParams make_rp(const ug_plan* pl) {
+  RenderParams rp;
+  rp.beta = pl->prm.beta;
+  rp.chi2 = pl->prm.chi2;
+  rp.bg_alpha = pl->prm.bg_alpha;
+  rp.bg_color = pl->prm.bg_color;
+  rp.tile_w = pl->prm.tile_w;
+  rp.tile_h = pl->prm.tile_h;
+  rp.box_mode = pl->prm.box_mode;
+  rp.n = pl->n;
+  rp.p = pl->p;
+  rp.num_tiles = pl->num_tiles;
+  rp.rec_cap = pl->rec_cap;
+  rp.key_cap = pl->key_cap;
+  return rp;
+}
+
+int check_inputs(const ug_plan* plan, const ug_gaussians* g, const ug_planes* pl, const void* ws) {
+  if (!plan || !g || !pl || !ws) return UG_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return UG_ERR_INVALID_ARG;
+  if (g->n != plan->n || pl->p != plan->p) return UG_ERR_INVALID_ARG;
+  if (g->n > 0 && (!g->means || !g->lraw || !g->intensity || !g->opacity)) return UG_ERR_INVALID_ARG;
+  if (!pl->rot || !pl->origin || !pl->spacing) return UG_ERR_INVALID_ARG;
+  return UG_OK;
+}
+
+// Culling pass shared by measure and render: plane set-up, count, top scan.
+hipError_t enqueue_cull(const ug_plan* plan, const ug_gaussians& g, const ug_planes& pl, void* ws,
+                        const RenderParams& rp, uint32_t* rec_koff, hipStream_t s) {
+  const Layout& L = plan->lay;
+  Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+  hipError_t e;
+  {
+    StageScope sc(plan, UG_STAGE_SETUP, s);
+    e = launch_init(pl, plan->d_pint, at<PlaneConst>(ws, L.pconst), ctrl, s);
+  }
+  if (e != hipSuccess) return e;
+  {
+    StageScope sc(plan, UG_STAGE_CULL, s);
+    e = launch_count(g, at<PlaneConst>(ws, L.pconst), plan->d_pint, rp, at<uint32_t>(ws, L.cnt_rec),
+                     at<uint32_t>(ws, L.cnt_key), at<uint32_t>(ws, L.blk_rec), at<uint32_t>(ws, L.blk_key), ctrl, s);
+  }
+  if (e != hipSuccess) return e;
+  StageScope sc(plan, UG_STAGE_SCAN, s);
+  return launch_top_scan(at<uint32_t>(ws, L.blk_rec), at<uint32_t>(ws, L.blk_key),
+                         at<unsigned long long>(ws, L.blk_rec_off), at<unsigned long long>(ws, L.blk_key_off),
+                         plan->nblk, ctrl, rp.rec_cap, rp.key_cap, rec_koff, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+void ug_params_default(ug_params* out) {
+  if (!out) return;
+  out->beta = 1e-4f;
+  out->chi2 = 7.815f;
+  out->bg_alpha = 1e-2f;
+  out->bg_color = 0.f;
+  out->tile_w = 16;
+  out->tile_h = 16;
+  out->px_per_lane = 0;
+  out->lds_batch = 64;
+  out->box_mode = UG_BOX_PAPER;
+  out->flags = 0;
+}
+
+int ug_plan_create(int32_t n, int32_t p, const int32_t* wh_host, const ug_params* params, int64_t record_capacity,
+                   int64_t key_capacity, ug_plan** out) {
+  if (!out) return UG_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n < 0 || p < 1 || !wh_host || !params) return UG_ERR_INVALID_ARG;
+  if (record_capacity < 0 || key_capacity < 0 || record_capacity >= (int64_t(1) << 31) ||
+      key_capacity >= (int64_t(1) << 31))
+    return UG_ERR_INVALID_ARG;
+  if (!valid_params(*params)) return UG_ERR_INVALID_ARG;
+  const int TW = params->tile_w, TH = params->tile_h;
+  std::vector<PlaneInt> pint((size_t)p);
+  uint64_t tiles = 0, pix = 0;
+  for (int32_t i = 0; i < p; ++i) {
+    const int32_t W = wh_host[2 * i], H = wh_host[2 * i + 1];
+    if (W < 1 || H < 1 || W > 32767 || H > 32767) return UG_ERR_INVALID_ARG;
+    PlaneInt& q = pint[(size_t)i];
+    q.W = W;
+    q.H = H;
+    q.ntx = (W + TW - 1) / TW;
+    q.nty = (H + TH - 1) / TH;
+    q.tile_off = (uint32_t)tiles;
+    q.pix_off_lo = (uint32_t)(pix & 0xffffffffu);
+    q.pix_off_hi = (uint32_t)(pix >> 32);
+    q.pad = 0;
+    tiles += (uint64_t)q.ntx * q.nty;
+    pix += (uint64_t)W * H;
+    if (tiles >= (uint64_t(1) << 31)) return UG_ERR_INVALID_ARG;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return UG_ERR_NO_DEVICE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return UG_ERR_NO_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return UG_ERR_NO_DEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return UG_ERR_NO_DEVICE;
+
+  ug_plan* pl = new (std::nothrow) ug_plan();
+  if (!pl) return UG_ERR_HIP;
+  pl->n = n;
+  pl->p = p;
+  pl->prm = *params;
+  pl->ppl = params->px_per_lane ? params->px_per_lane : accum_default_ppl(TW, TH);
+  pl->num_tiles = (uint32_t)tiles;
+  pl->num_pixels = pix;
+  int bits = 1;
+  while (bits < 32 && (uint64_t(1) << bits) < tiles) ++bits;
+  pl->bits = bits;
+  pl->final_buf = ((bits + 7) / 8) % 2;
+  pl->nblk = (n + 255) / 256;
+  pl->device = dev;
+  pl->rec_cap = (uint32_t)record_capacity;
+  pl->key_cap = (uint32_t)key_capacity;
+  pl->sort_blocks = sort_blocks_for(pl->key_cap);
+  std::vector<uint32_t> tile_plane((size_t)tiles);
+  for (int32_t i = 0; i < p; ++i) {
+    const uint32_t nt = (uint32_t)(pint[(size_t)i].ntx * pint[(size_t)i].nty);
+    for (uint32_t t = 0; t < nt; ++t) tile_plane[pint[(size_t)i].tile_off + t] = (uint32_t)i;
+  }
+  if (hipMalloc(&pl->d_pint, sizeof(PlaneInt) * (size_t)p) != hipSuccess ||
+      hipMalloc(&pl->d_tile_plane, sizeof(uint32_t) * (size_t)tiles) != hipSuccess ||
+      hipMemcpy(pl->d_pint, pint.data(), sizeof(PlaneInt) * (size_t)p, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pl->d_tile_plane, tile_plane.data(), sizeof(uint32_t) * (size_t)tiles, hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    ug_plan_destroy(pl);
+    return UG_ERR_HIP;
+  }
+  compute_layout(pl);
+  *out = pl;
+  return UG_OK;
+}
+
+int ug_plan_reserve(ug_plan* plan, int64_t record_capacity, int64_t key_capacity) {
+  if (!plan || record_capacity < 0 || key_capacity < 0 || record_capacity >= (int64_t(1) << 31) ||
+      key_capacity >= (int64_t(1) << 31))
+    return UG_ERR_INVALID_ARG;
+  plan->rec_cap = (uint32_t)record_capacity;
+  plan->key_cap = (uint32_t)key_capacity;
+  plan->sort_blocks = sort_blocks_for(plan->key_cap);
+  compute_layout(plan);
+  return UG_OK;
+}
+
+size_t ug_plan_workspace_bytes(const ug_plan* plan) { return plan ? plan->lay.total : 0; }
+
+int64_t ug_plan_num_pixels(const ug_plan* plan) { return plan ? (int64_t)plan->num_pixels : -1; }
+
+int64_t ug_plan_num_tiles(const ug_plan* plan) { return plan ? (int64_t)plan->num_tiles : -1; }
+
+int ug_plan_measure(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes, void* workspace,
+                    int64_t* out_host, void* stream) {
+  const int st = check_inputs(plan, g, planes, workspace);
+  if (st != UG_OK) return st;
+  if (!out_host) return UG_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RenderParams rp = make_rp(plan);
+  rp.rec_cap = 0xffffffffu;
+  rp.key_cap = 0xffffffffu;
+  hipError_t e = enqueue_cull(plan, *g, *planes, workspace, rp, nullptr, s);
+  if (e != hipSuccess) return UG_ERR_HIP;
+  Ctrl c;
+  if (hipMemcpyAsync(&c, at<Ctrl>(workspace, plan->lay.ctrl), sizeof(Ctrl), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return UG_ERR_HIP;
+  out_host[0] = (int64_t)c.n_rec;
+  out_host[1] = (int64_t)c.n_key;
+  return (c.flags & kFlagNonfinite) ? UG_ERR_NONFINITE : UG_OK;
+}
+
+int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes, float* image,
+                     void* workspace, void* stream) {
+  const int st = check_inputs(plan, g, planes, workspace);
+  if (st != UG_OK) return st;
+  if (!image) return UG_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = plan->lay;
+  void* ws = workspace;
+  const RenderParams rp = make_rp(plan);
+  Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+  uint32_t* rec_koff = at<uint32_t>(ws, L.rec_koff);
+  hipError_t e = enqueue_cull(plan, *g, *planes, ws, rp, rec_koff, s);
+  if (e != hipSuccess) return UG_ERR_HIP;
+  {
+    StageScope sc(plan, UG_STAGE_WRITE, s);
+    e = launch_write(*g, at<PlaneConst>(ws, L.pconst), plan->d_pint, rp, at<uint32_t>(ws, L.cnt_rec),
+                     at<uint32_t>(ws, L.cnt_key), at<unsigned long long>(ws, L.blk_rec_off),
+                     at<unsigned long long>(ws, L.blk_key_off), at<uint32_t>(ws, L.off_rec), at<RecAcc>(ws, L.racc),
+                     at<RecGeo>(ws, L.rgeo), at<uint32_t>(ws, L.rec_pid), rec_koff, s);
+  }
+  if (e != hipSuccess) return UG_ERR_HIP;
+  {
+    StageScope sc(plan, UG_STAGE_EMIT, s);
+    e = launch_emit(ctrl, at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<uint32_t>(ws, L.rec_pid), rec_koff,
+                    plan->d_pint, rp, at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.rec_of_key), s);
+  }
+  if (e != hipSuccess) return UG_ERR_HIP;
+  int fb = 0;
+  {
+    StageScope sc(plan, UG_STAGE_SORT, s);
+    e = launch_sort(ctrl, at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.key_tile1),
+                    at<uint32_t>(ws, L.key_val0), at<uint32_t>(ws, L.key_val1), at<uint32_t>(ws, L.rec_of_key),
+                    at<uint32_t>(ws, L.srec), at<uint32_t>(ws, L.hist), plan->sort_blocks, plan->bits, &fb, s);
+  }
+  if (e != hipSuccess) return UG_ERR_HIP;
+  const uint32_t* skeys = at<uint32_t>(ws, fb ? L.key_tile1 : L.key_tile0);
+  {
+    StageScope sc(plan, UG_STAGE_RANGES, s);
+    e = launch_tile_ranges(ctrl, skeys, plan->num_tiles, at<uint32_t>(ws, L.tile_start), s);
+  }
+  if (e != hipSuccess) return UG_ERR_HIP;
+  unsigned long long* n_eval = (plan->prm.flags & UG_FLAG_COUNT_EVALS) ? &ctrl->n_eval : nullptr;
+  StageScope sc(plan, UG_STAGE_ACCUM, s);
+  e = launch_accum_fwd(plan->prm.tile_w, plan->prm.tile_h, plan->ppl, plan->prm.lds_batch, plan->d_pint,
+                       plan->d_tile_plane, at<uint32_t>(ws, L.tile_start), at<uint32_t>(ws, L.srec),
+                       at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), image, at<float>(ws, L.dsave),
+                       plan->prm.bg_alpha, plan->prm.bg_color, plan->num_tiles, n_eval, s);
+  return hip_status(e);
+}
+
+int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes,
+                              const float* image, const float* d_image, void* workspace, float* d_means,
+                              float* d_lraw, float* d_intensity, float* d_opacity, int32_t accumulate,
+                              void* stream) {
+  const int st = check_inputs(plan, g, planes, workspace);
+  if (st != UG_OK) return st;
+  if (!image || !d_image) return UG_ERR_INVALID_ARG;
+  if (plan->n > 0 && (!d_means || !d_lraw || !d_intensity || !d_opacity)) return UG_ERR_INVALID_ARG;
+  if (accumulate != 0 && accumulate != 1) return UG_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = plan->lay;
+  void* ws = workspace;
+  const RenderParams rp = make_rp(plan);
+  const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+  const int fb = plan->final_buf;
+  hipError_t e;
+  {
+    StageScope sc(plan, UG_STAGE_BWD_PREP, s);
+    e = launch_bwd_prep(plan->prm.tile_w, plan->prm.tile_h, plan->d_pint, plan->d_tile_plane, image, d_image,
+                        at<float>(ws, L.dsave), at<float>(ws, L.gq), plan->num_tiles, s);
+  }
+  if (e != hipSuccess) return UG_ERR_HIP;
+  {
+    StageScope sc(plan, UG_STAGE_ACCUM_BWD, s);
+    e = launch_accum_bwd(plan->prm.tile_w, plan->prm.tile_h, ctrl, plan->d_pint, plan->d_tile_plane,
+                         at<uint32_t>(ws, fb ? L.key_tile1 : L.key_tile0),
+                         at<uint32_t>(ws, fb ? L.key_val1 : L.key_val0), at<uint32_t>(ws, L.srec),
+                         at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<float>(ws, L.gq),
+                         at<float>(ws, L.partial), plan->key_cap, s);
+  }
+  if (e != hipSuccess) return UG_ERR_HIP;
+  {
+    StageScope sc(plan, UG_STAGE_REDUCE, s);
+    e = launch_reduce_partials(ctrl, at<uint32_t>(ws, L.rec_koff), at<float>(ws, L.partial),
+                               at<float>(ws, L.drec), plan->rec_cap, s);
+  }
+  if (e != hipSuccess) return UG_ERR_HIP;
+  StageScope sc(plan, UG_STAGE_PREP_BWD, s);
+  e = launch_preprocess_bwd(*g, at<PlaneConst>(ws, L.pconst), rp, ctrl, at<uint32_t>(ws, L.cnt_rec),
+                            at<uint32_t>(ws, L.off_rec), at<uint32_t>(ws, L.rec_pid), at<float>(ws, L.drec), d_means,
+                            d_lraw, d_intensity, d_opacity, accumulate, s);
+  return hip_status(e);
+}
+
+int ug_plan_status(const ug_plan* plan, const void* workspace, int64_t* counts_host, void* stream) {
+  if (!plan || !workspace) return UG_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ctrl c;
+  if (hipMemcpyAsync(&c, static_cast<const char*>(workspace) + plan->lay.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return UG_ERR_HIP;
+  if (counts_host) {
+    counts_host[0] = (int64_t)c.n_rec;
+    counts_host[1] = (int64_t)c.n_key;
+    counts_host[2] = (int64_t)c.n_eval;
+  }
+  if (c.flags & kFlagInternal) return UG_ERR_INTERNAL;
+  if (c.flags & (kFlagRecCap | kFlagKeyCap)) return UG_ERR_CAPACITY;
+  if (c.flags & kFlagNonfinite) return UG_ERR_NONFINITE;
+  return UG_OK;
+}
+
+int ug_mse_grad(const float* image, const float* target, int64_t m, float* d_image, float* loss_dev, void* stream) {
+  if (!image || !target || !d_image || !loss_dev || m < 1) return UG_ERR_INVALID_ARG;
+  return hip_status(launch_mse(image, target, m, d_image, loss_dev, static_cast<hipStream_t>(stream)));
+}
+
+int ug_adam_step(float* param, const float* grad, float* mo, float* ve, int64_t count, float lr, float beta1,
+                 float beta2, float eps, int32_t step_t, void* stream) {
+  if (!param || !grad || !mo || !ve || count < 0 || step_t < 1) return UG_ERR_INVALID_ARG;
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f) || !std::isfinite(lr))
+    return UG_ERR_INVALID_ARG;
+  if (count == 0) return UG_OK;
+  return hip_status(
+      launch_adam(param, grad, mo, ve, count, lr, beta1, beta2, eps, step_t, static_cast<hipStream_t>(stream)));
+}
+
+const char* ug_status_string(int status) {
+  switch (status) {
+    case UG_OK: return "ok";
+    case UG_ERR_INVALID_ARG: return "invalid argument";
+    case UG_ERR_CAPACITY: return "record or key capacity exceeded; re-plan with larger capacities";
+    case UG_ERR_NONFINITE: return "non-finite Gaussian or plane input (skipped)";
+    case UG_ERR_HIP: return "HIP runtime error";
+    case UG_ERR_NO_DEVICE: return "no gfx950 device available";
+    case UG_ERR_INTERNAL: return "internal consistency check failed (please report)";
+    default: return "unknown status";
+  }
+}
+
+int ug_profile_begin(ug_plan* plan, uint32_t stage_mask, int32_t max_launches) {
+  if (!plan || max_launches < 1 || max_launches > (1 << 20)) return UG_ERR_INVALID_ARG;
+  prof_release(plan);
+  ug_plan::Prof& P = plan->prof;
+  P.ev.resize(2 * (size_t)max_launches, nullptr);
+  P.stage.assign((size_t)max_launches, -1);
+  for (auto& e : P.ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      prof_release(plan);
+      return UG_ERR_HIP;
+    }
+  }
+  P.cap = max_launches;
+  P.used = 0;
+  P.mask = stage_mask;
+  P.on = true;
+  return UG_OK;
+}
+
+int ug_profile_read(ug_plan* plan, float* ms_host, int32_t* launches_host) {
+  if (!plan) return UG_ERR_INVALID_ARG;
+  ug_plan::Prof& P = plan->prof;
+  float ms[UG_NUM_STAGES] = {0};
+  int32_t cnt[UG_NUM_STAGES] = {0};
+  int st = UG_OK;
+  if (P.used > 0) {
+    if (hipEventSynchronize(P.ev[2 * (size_t)(P.used - 1) + 1]) != hipSuccess) st = UG_ERR_HIP;
+    for (int i = 0; i < P.used && st == UG_OK; ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, P.ev[2 * (size_t)i], P.ev[2 * (size_t)i + 1]) != hipSuccess) {
+        st = UG_ERR_HIP;
+        break;
+      }
+      const int sg = P.stage[(size_t)i];
+      if (sg >= 0 && sg < UG_NUM_STAGES) {
+        ms[sg] += t;
+        cnt[sg] += 1;
+      }
+    }
+  }
+  if (ms_host)
+    for (int i = 0; i < UG_NUM_STAGES; ++i) ms_host[i] = ms[i];
+  if (launches_host)
+    for (int i = 0; i < UG_NUM_STAGES; ++i) launches_host[i] = cnt[i];
+  prof_release(plan);
+  return st;
+}
+
+void ug_plan_destroy(ug_plan* plan) {
+  if (!plan) return;
+  prof_release(plan);
+  if (plan->d_pint) (void)hipFree(plan->d_pint);
+  if (plan->d_tile_plane) (void)hipFree(plan->d_tile_plane);
+  delete plan;
+}
+
+}  // extern "C"

@@ -1,0 +1,328 @@
+// FP64 per-(Gaussian, plane) geometry: Eq. 9 transform, Eq. 11 factor,
+// Eq. 12/13 culling and boxes, and the in-plane conic of Eq. 8 restricted
+// to the probe plane x3 = 0, plus its adjoint.
+//
+// Derivation (probe frame of one plane, R = [e1 e2 n], m = R^-1 (mu - o)):
+//   d^2(x) = |M (x|0 - m)|^2 with M = L^T R, columns b1, b2, b3.
+//   G = M^-T = L^-1 R^-T has columns g_k = L^-1 (row k of R^-1); the
+//   probe-frame covariance is Sigma'_jk = g_j . g_k, so the Eq. 13 box
+//   half-widths are sqrt(chi^2 Sigma'_kk) (the cofactor-over-determinant of
+//   the probe-frame precision) and the plane misses the ellipsoid iff
+//   r^2 = m3^2 / Sigma'_33 > chi^2.
+//   Restricted to x3 = 0 the quadratic is |R_B (x - c)|^2 + r^2 where
+//   R_B = [[T11, T12], [0, T22]] is the Cholesky factor of B^T B, B = [b1 b2]:
+//   T11 = |b1|, T12 = b1.b2 / T11, T22 = |b1 x b2| / T11 = |det M| |g3| / T11
+//   (b1 x b2 = det(M) g3), and the centre is the conditional mean
+//   c = m12 - m3 (Sigma'_13, Sigma'_23) / Sigma'_33.
+// Everything is evaluated in double precision from the float32 inputs and
+// rounded once into the float32 record.
+#pragma once
+
+#include "ug_internal.h"
+
+namespace ug {
+
+struct GaussIn {
+  double mu[3];
+  double l[6];   // raw (l11, l21, l31, l22, l32, l33)
+  double a, c;
+  double L11, L21, L31, L22, L32, L33;
+  double alpha, log2a;
+  bool finite;
+};
+
+struct Conic {
+  double m1, m2, m3;
+  double g1[3], g2[3], g3[3];
+  double b1[3], b2[3];
+  double S11, S22, S33, S13, S23;
+  double T11, T12, T22, detL, n3;
+  double c1, c2, r2;
+};
+
+__device__ __forceinline__ void load_gauss(const ug_gaussians& g, int i, double beta, GaussIn& G) {
+  bool fin = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    G.mu[k] = (double)g.means[3 * i + k];
+    fin = fin && isfinite_d(G.mu[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    G.l[k] = (double)g.lraw[6 * i + k];
+    fin = fin && isfinite_d(G.l[k]);
+  }
+  G.a = (double)g.opacity[i];
+  G.c = (double)g.intensity[i];
+  fin = fin && isfinite_d(G.a) && isfinite_d(G.c);
+  G.finite = fin;
+  // Eq. 11: diagonal entries squared plus beta.
+  G.L11 = G.l[0] * G.l[0] + beta;
+  G.L21 = G.l[1];
+  G.L31 = G.l[2];
+  G.L22 = G.l[3] * G.l[3] + beta;
+  G.L32 = G.l[4];
+  G.L33 = G.l[5] * G.l[5] + beta;
+  // alpha = sigmoid(a); log2(alpha) = -softplus(-a) / ln 2, stable for any a.
+  const double na = -G.a;
+  const double sp = (na > 0 ? na : 0.0) + log1p(exp(-fabs(na)));
+  G.log2a = -sp / kLn2;
+  G.alpha = 1.0 / (1.0 + exp(na));
+}
+
+// Forward substitution y = L^-1 q.
+__device__ __forceinline__ void fsub(const GaussIn& G, double q0, double q1, double q2, double* y) {
+  y[0] = q0 / G.L11;
+  y[1] = (q1 - G.L21 * y[0]) / G.L22;
+  y[2] = (q2 - G.L31 * y[0] - G.L32 * y[1]) / G.L33;
+}
+
+// Back substitution h = L^-T d.
+__device__ __forceinline__ void bsub(const GaussIn& G, const double* d, double* h) {
+  h[2] = d[2] / G.L33;
+  h[1] = (d[1] - G.L32 * h[2]) / G.L22;
+  h[0] = (d[0] - G.L21 * h[1] - G.L31 * h[2]) / G.L11;
+}
+
+// Phase 1 of Section 4.4: probe coordinates of the mean and the distance of
+// the plane from the ellipsoid.  Returns false if the plane misses the
+// chi^2 ellipsoid (|m3| > sqrt(chi^2 Sigma'_33), i.e. r^2 > chi^2).
+__device__ __forceinline__ bool conic_cull(const GaussIn& G, const PlaneConst& P, double chi2, Conic& k) {
+  const double d0 = G.mu[0] - P.o[0], d1 = G.mu[1] - P.o[1], d2 = G.mu[2] - P.o[2];
+  k.m1 = P.rinv[0] * d0 + P.rinv[1] * d1 + P.rinv[2] * d2;
+  k.m2 = P.rinv[3] * d0 + P.rinv[4] * d1 + P.rinv[5] * d2;
+  k.m3 = P.rinv[6] * d0 + P.rinv[7] * d1 + P.rinv[8] * d2;
+  fsub(G, P.rinv[6], P.rinv[7], P.rinv[8], k.g3);
+  k.S33 = k.g3[0] * k.g3[0] + k.g3[1] * k.g3[1] + k.g3[2] * k.g3[2];
+  k.r2 = k.m3 * k.m3 / k.S33;
+  return k.r2 <= chi2;  // false for NaN as well
+}
+
+// The rest of the conic, after conic_cull accepted the pair.
+__device__ __forceinline__ void conic_full(const GaussIn& G, const PlaneConst& P, Conic& k) {
+  fsub(G, P.rinv[0], P.rinv[1], P.rinv[2], k.g1);
+  fsub(G, P.rinv[3], P.rinv[4], P.rinv[5], k.g2);
+  k.S11 = k.g1[0] * k.g1[0] + k.g1[1] * k.g1[1] + k.g1[2] * k.g1[2];
+  k.S22 = k.g2[0] * k.g2[0] + k.g2[1] * k.g2[1] + k.g2[2] * k.g2[2];
+  k.S13 = k.g1[0] * k.g3[0] + k.g1[1] * k.g3[1] + k.g1[2] * k.g3[2];
+  k.S23 = k.g2[0] * k.g3[0] + k.g2[1] * k.g3[1] + k.g2[2] * k.g3[2];
+  // b_k = L^T e_k
+  k.b1[0] = G.L11 * P.e1[0] + G.L21 * P.e1[1] + G.L31 * P.e1[2];
+  k.b1[1] = G.L22 * P.e1[1] + G.L32 * P.e1[2];
+  k.b1[2] = G.L33 * P.e1[2];
+  k.b2[0] = G.L11 * P.e2[0] + G.L21 * P.e2[1] + G.L31 * P.e2[2];
+  k.b2[1] = G.L22 * P.e2[1] + G.L32 * P.e2[2];
+  k.b2[2] = G.L33 * P.e2[2];
+  k.T11 = sqrt(k.b1[0] * k.b1[0] + k.b1[1] * k.b1[1] + k.b1[2] * k.b1[2]);
+  k.T12 = (k.b1[0] * k.b2[0] + k.b1[1] * k.b2[1] + k.b1[2] * k.b2[2]) / k.T11;
+  k.detL = G.L11 * G.L22 * G.L33;
+  k.n3 = sqrt(k.S33);
+  k.T22 = k.detL * P.absdet * k.n3 / k.T11;
+  k.c1 = k.m1 - k.m3 * k.S13 / k.S33;
+  k.c2 = k.m2 - k.m3 * k.S23 / k.S33;
+}
+
+__device__ __forceinline__ double cross_norm2(const double* a, const double* b) {
+  const double x = a[1] * b[2] - a[2] * b[1];
+  const double y = a[2] * b[0] - a[0] * b[2];
+  const double z = a[0] * b[1] - a[1] * b[0];
+  return x * x + y * y + z * z;
+}
+
+// Inclusive pixel-index range covered by [centre - half, centre + half],
+// padded so float rounding never drops a pixel the record's own test keeps.
+__device__ __forceinline__ bool pixel_range(double centre, double half, int32_t size, int& lo, int& hi) {
+  const double pad = 1e-3 + 1e-5 * half;
+  double a = centre - half - pad, b = centre + half + pad;
+  if (!(a <= b)) return false;  // NaN
+  if (b < 0.0 || a > (double)(size - 1)) return false;
+  a = a > 0.0 ? a : 0.0;
+  b = b < (double)(size - 1) ? b : (double)(size - 1);
+  lo = (int)ceil(a);
+  hi = (int)floor(b);
+  return lo <= hi;
+}
+
+struct Footprint {
+  RecAcc acc;
+  RecGeo geo;
+  uint32_t keys;
+};
+
+// Exact column range of the record's ellipse over the pixel rows [ya, yb],
+// clipped to columns [umin, umax].  Evaluated in double from the float32
+// record with contraction off so every kernel that calls it agrees bit for
+// bit.  The ellipse is (t11 du + t12 dv)^2 + (t22 dv)^2 <= e0 - emin; its
+// right edge is concave in dv and its left edge convex, so the extreme
+// columns over a row band sit at the clamped stationary points.
+__device__ __forceinline__ bool rows_band(const RecAcc& ra, int ub, int vb, int ya, int yb, int umin,
+                                          int umax, int& ua, int& uz) {
+#pragma clang fp contract(off)
+  const double thr = (double)ra.e0 - (double)ra.emin;
+  if (!(thr >= 0.0)) return false;
+  if (__builtin_isinf(thr)) {
+    ua = umin;
+    uz = umax;
+    return umin <= umax;
+  }
+  const double t11 = ra.t11, t12 = ra.t12, t22 = ra.t22;
+  const double u0 = (double)ub + (double)ra.fu, v0 = (double)vb + (double)ra.fv;
+  const double sq = sqrt(thr);
+  const double vext = sq / t22 * (1.0 + 1e-6) + 1e-3;
+  double lo = (double)ya - v0, hi = (double)yb - v0;
+  lo = lo > -vext ? lo : -vext;
+  hi = hi < vext ? hi : vext;
+  if (!(lo <= hi)) return false;
+  const double S = sqrt(t12 * t12 + t22 * t22);
+  double dvr = -t12 * sq / (t22 * S);
+  dvr = dvr < lo ? lo : (dvr > hi ? hi : dvr);
+  double dvl = t12 * sq / (t22 * S);
+  dvl = dvl < lo ? lo : (dvl > hi ? hi : dvl);
+  double qr = thr - t22 * t22 * dvr * dvr;
+  double ql = thr - t22 * t22 * dvl * dvl;
+  qr = qr > 0.0 ? qr : 0.0;
+  ql = ql > 0.0 ? ql : 0.0;
+  const double ur = u0 + (-t12 * dvr + sqrt(qr)) / t11;
+  const double ul = u0 + (-t12 * dvl - sqrt(ql)) / t11;
+  const double pad = 1e-3 + 1e-5 * (ur - ul);
+  double a = ul - pad, b = ur + pad;
+  a = a > (double)umin ? a : (double)umin;
+  b = b < (double)umax ? b : (double)umax;
+  if (!(a <= b)) return false;
+  ua = (int)ceil(a);
+  uz = (int)floor(b);
+  return ua <= uz;
+}
+
+// Key count of a ROWS-mode record over its tile rectangle.
+__device__ __forceinline__ uint32_t rows_count(const RecAcc& ra, const RecGeo& geo, int W, int H, int TW, int TH) {
+  const int umin = geo.tx0 * TW;
+  const int umax = min(geo.tx1 * TW + TW - 1, W - 1);
+  uint32_t keys = 0;
+  for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
+    const int ya = ty * TH, yb = min(ya + TH - 1, H - 1);
+    int ua, uz;
+    if (rows_band(ra, geo.ub, geo.vb, ya, yb, umin, umax, ua, uz)) keys += (uint32_t)(uz / TW - ua / TW + 1);
+  }
+  return keys;
+}
+
+// Record, tile rectangle and key count of an accepted pair (conic_full done).
+// Returns false if the footprint misses the image.
+__device__ __forceinline__ bool make_footprint(const GaussIn& G, const PlaneConst& P, const PlaneInt& PI,
+                                               const Conic& k, double chi2, int box_mode, int TW, int TH,
+                                               Footprint& f) {
+  const double ks = sqrt(kHalfLog2e);
+  const double u0 = k.c1 / P.sx + P.cu;
+  const double v0 = k.c2 / P.sy + P.cv;
+  int ulo, uhi, vlo, vhi;
+  if (box_mode == UG_BOX_PAPER) {
+    // Eq. 13: b_{1:2} = m_{1:2} -/+ sqrt(chi^2 Sigma'_kk).
+    if (!pixel_range(k.m1 / P.sx + P.cu, sqrt(chi2 * k.S11) / P.sx, PI.W, ulo, uhi)) return false;
+    if (!pixel_range(k.m2 / P.sy + P.cv, sqrt(chi2 * k.S22) / P.sy, PI.H, vlo, vhi)) return false;
+  } else {
+    // Box of the ellipse cut by the plane: conditional variances
+    // Sigma'_kk - Sigma'_k3^2 / Sigma'_33 = |g_k x g3|^2 / |g3|^2.
+    double q = chi2 - k.r2;
+    q = q > 0.0 ? q : 0.0;
+    if (!pixel_range(u0, sqrt(q * cross_norm2(k.g1, k.g3) / k.S33) / P.sx, PI.W, ulo, uhi)) return false;
+    if (!pixel_range(v0, sqrt(q * cross_norm2(k.g2, k.g3) / k.S33) / P.sy, PI.H, vlo, vhi)) return false;
+  }
+  double ubd = floor(u0 + 0.5), vbd = floor(v0 + 0.5);
+  ubd = ubd < -1.0e9 ? -1.0e9 : (ubd > 1.0e9 ? 1.0e9 : ubd);
+  vbd = vbd < -1.0e9 ? -1.0e9 : (vbd > 1.0e9 ? 1.0e9 : vbd);
+  f.acc.t11 = (float)(ks * k.T11 * P.sx);
+  f.acc.t12 = (float)(ks * k.T12 * P.sy);
+  f.acc.t22 = (float)(ks * k.T22 * P.sy);
+  f.acc.fu = (float)(u0 - ubd);
+  f.acc.fv = (float)(v0 - vbd);
+  f.acc.e0 = (float)(G.log2a - kHalfLog2e * k.r2);
+  f.acc.emin = (float)(G.log2a - kHalfLog2e * chi2);
+  f.acc.c = (float)G.c;
+  f.geo.ub = (int32_t)ubd;
+  f.geo.vb = (int32_t)vbd;
+  f.geo.tx0 = (uint16_t)(ulo / TW);
+  f.geo.tx1 = (uint16_t)(uhi / TW);
+  f.geo.ty0 = (uint16_t)(vlo / TH);
+  f.geo.ty1 = (uint16_t)(vhi / TH);
+  if (box_mode == UG_BOX_ROWS) {
+    f.keys = rows_count(f.acc, f.geo, PI.W, PI.H, TW, TH);
+  } else {
+    f.keys = (uint32_t)(f.geo.tx1 - f.geo.tx0 + 1) * (uint32_t)(f.geo.ty1 - f.geo.ty0 + 1);
+  }
+  return f.keys > 0;
+}
+
+// Adjoint of make_footprint's float record with respect to the Gaussian's
+// raw parameters, holding the cut-off set fixed.  dr = (dt11, dt12, dt22,
+// dfu, dfv, de0, dc).  Accumulates into dmu[3], dL[6] (L11, L21, L31, L22,
+// L32, L33), da, dc.
+__device__ __forceinline__ void footprint_adjoint(const GaussIn& G, const PlaneConst& P, const Conic& k,
+                                                  const float* dr, double* dmu, double* dL, double& da,
+                                                  double& dc) {
+  const double ks = sqrt(kHalfLog2e);
+  const double dT11 = ks * P.sx * (double)dr[0];
+  const double dT12 = ks * P.sy * (double)dr[1];
+  const double dT22 = ks * P.sy * (double)dr[2];
+  const double dc1 = (double)dr[3] / P.sx;
+  const double dc2 = (double)dr[4] / P.sy;
+  const double de0 = (double)dr[5];
+  dc += (double)dr[6];
+  // e0 = log2(sigmoid(a)) - kHalfLog2e r^2
+  da += de0 * (1.0 - G.alpha) / kLn2;
+  const double dr2 = -kHalfLog2e * de0;
+  // T22 = detM n3 / T11, T12 = b1.b2 / T11, T11 = |b1|
+  const double detM = k.detL * P.absdet;
+  const double dT11t = dT11 - dT12 * k.T12 / k.T11 - dT22 * k.T22 / k.T11;
+  const double ddetL = dT22 * P.absdet * k.n3 / k.T11;
+  const double dn3 = dT22 * detM / k.T11;
+  double db1[3], db2[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    db1[j] = dT11t * k.b1[j] / k.T11 + dT12 * k.b2[j] / k.T11;
+    db2[j] = dT12 * k.b1[j] / k.T11;
+  }
+  // c1 = m1 - m3 S13/S33, c2 = m2 - m3 S23/S33, r2 = m3^2 / S33
+  const double iS = 1.0 / k.S33;
+  double dm[3];
+  dm[0] = dc1;
+  dm[1] = dc2;
+  dm[2] = -dc1 * k.S13 * iS - dc2 * k.S23 * iS + dr2 * 2.0 * k.m3 * iS;
+  const double dS13 = -dc1 * k.m3 * iS;
+  const double dS23 = -dc2 * k.m3 * iS;
+  const double dS33 = (dc1 * k.m3 * k.S13 + dc2 * k.m3 * k.S23 - dr2 * k.m3 * k.m3) * iS * iS;
+  double dg1[3], dg2[3], dg3[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    dg1[j] = dS13 * k.g3[j];
+    dg2[j] = dS23 * k.g3[j];
+    dg3[j] = dS13 * k.g1[j] + dS23 * k.g2[j] + 2.0 * dS33 * k.g3[j] + dn3 * k.g3[j] / k.n3;
+  }
+  // g = L^-1 q  ->  dL_ij -= h_i g_j with h = L^-T dg (lower triangle)
+  double h[3];
+  bsub(G, dg1, h);
+  dL[0] -= h[0] * k.g1[0]; dL[1] -= h[1] * k.g1[0]; dL[2] -= h[2] * k.g1[0];
+  dL[3] -= h[1] * k.g1[1]; dL[4] -= h[2] * k.g1[1]; dL[5] -= h[2] * k.g1[2];
+  bsub(G, dg2, h);
+  dL[0] -= h[0] * k.g2[0]; dL[1] -= h[1] * k.g2[0]; dL[2] -= h[2] * k.g2[0];
+  dL[3] -= h[1] * k.g2[1]; dL[4] -= h[2] * k.g2[1]; dL[5] -= h[2] * k.g2[2];
+  bsub(G, dg3, h);
+  dL[0] -= h[0] * k.g3[0]; dL[1] -= h[1] * k.g3[0]; dL[2] -= h[2] * k.g3[0];
+  dL[3] -= h[1] * k.g3[1]; dL[4] -= h[2] * k.g3[1]; dL[5] -= h[2] * k.g3[2];
+  // b_j = sum_i L_ij e_i  ->  dL_ij += e_i db_j
+  dL[0] += P.e1[0] * db1[0] + P.e2[0] * db2[0];
+  dL[1] += P.e1[1] * db1[0] + P.e2[1] * db2[0];
+  dL[2] += P.e1[2] * db1[0] + P.e2[2] * db2[0];
+  dL[3] += P.e1[1] * db1[1] + P.e2[1] * db2[1];
+  dL[4] += P.e1[2] * db1[1] + P.e2[2] * db2[1];
+  dL[5] += P.e1[2] * db1[2] + P.e2[2] * db2[2];
+  // detL = L11 L22 L33
+  dL[0] += ddetL * G.L22 * G.L33;
+  dL[3] += ddetL * G.L11 * G.L33;
+  dL[5] += ddetL * G.L11 * G.L22;
+  // m = R^-1 (mu - o)  ->  dmu = R^-T dm
+#pragma unroll
+  for (int j = 0; j < 3; ++j) dmu[j] += P.rinv[j] * dm[0] + P.rinv[3 + j] * dm[1] + P.rinv[6 + j] * dm[2];
+}
+
+}  // namespace ug

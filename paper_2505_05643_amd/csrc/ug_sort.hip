@@ -1,0 +1,158 @@
+// Tile binning: stable LSD radix sort of the (tile id, emission index) key
+// pairs, 8 bits per pass, with the key count read from device memory (so
+// the host never synchronises), and the per-tile [start, end) ranges.
+#include "ug_kernels.h"
+
+namespace ug {
+
+constexpr int kSortThreads = 256;
+
+// Contiguous chunk of the n keys owned by block b of G (multiple of 256).
+__device__ __forceinline__ void sort_chunk(uint32_t n, uint32_t G, uint32_t b, uint32_t& s, uint32_t& e) {
+  uint64_t C = ((uint64_t)n + G - 1) / G;
+  C = (C + 255) & ~(uint64_t)255;
+  const uint64_t s64 = (uint64_t)b * C;
+  s = (uint32_t)(s64 < n ? s64 : n);
+  const uint64_t e64 = s64 + C;
+  e = (uint32_t)(e64 < n ? e64 : n);
+}
+
+// Per-block digit histogram, digit-major: hist[d * G + b].
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Ctrl* __restrict__ ctrl,
+                                                              const uint32_t* __restrict__ keys, uint32_t G,
+                                                              int shift, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[4][256];
+  for (int j = threadIdx.x; j < 1024; j += kSortThreads) (&h[0][0])[j] = 0u;
+  __syncthreads();
+  uint32_t s, e;
+  sort_chunk(ctrl->n_key_eff, G, blockIdx.x, s, e);
+  const int wave = threadIdx.x >> 6;
+  for (uint32_t i = s + threadIdx.x; i < e; i += kSortThreads) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
+  __syncthreads();
+  const int d = threadIdx.x;
+  hist[(size_t)d * G + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+// Single block: exclusive scan over the 256*G histogram entries.
+__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t* __restrict__ hist, uint32_t total) {
+  __shared__ uint32_t sh[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (total + 1023) / 1024;
+  const uint32_t a = min(t * per, total), b = min(a + per, total);
+  uint32_t sum = 0;
+  for (uint32_t i = a; i < b; ++i) sum += hist[i];
+  sh[t] = sum;
+  __syncthreads();
+  for (uint32_t o = 1; o < 1024; o <<= 1) {
+    const uint32_t add = t >= o ? sh[t - o] : 0u;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  uint32_t run = sh[t] - sum;
+  for (uint32_t i = a; i < b; ++i) {
+    const uint32_t v = hist[i];
+    hist[i] = run;
+    run += v;
+  }
+}
+
+// Stable scatter.  The chunk is walked in rounds of 256 consecutive keys;
+// within a wave, lanes holding the same digit are found with eight ballots
+// and ranked by lane order; waves are ordered through LDS.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ hist, uint32_t G,
+    int shift, const uint32_t* __restrict__ rec_of_key, uint32_t* __restrict__ srec) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[4][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t s, e;
+  sort_chunk(ctrl->n_key_eff, G, blockIdx.x, s, e);
+  run[tid] = hist[(size_t)tid * G + blockIdx.x];
+  for (uint32_t base = s; base < e; base += kSortThreads) {
+    for (int j = tid; j < 1024; j += kSortThreads) (&wcnt[0][0])[j] = 0u;
+    __syncthreads();
+    const uint32_t i = base + tid;
+    const bool valid = i < e;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t v = valid ? (vin ? vin[i] : i) : 0u;
+    const uint32_t d = (k >> shift) & 255u;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const unsigned long long bm = __ballot(on);
+      peers &= on ? bm : ~bm;
+    }
+    const uint32_t rank = lanemask_lt_popc(peers);
+    if (valid && (peers >> lane) == 1ull) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pre = 0;
+      for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
+      const uint32_t pos = run[d] + pre + rank;
+      kout[pos] = k;
+      vout[pos] = v;
+      if (srec) srec[pos] = rec_of_key[v];
+    }
+    __syncthreads();
+    run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+    __syncthreads();
+  }
+}
+
+// tile_start[t] = first sorted key index whose tile id is >= t (t in [0, T]).
+__global__ __launch_bounds__(256) void k_tile_ranges(const Ctrl* __restrict__ ctrl,
+                                                     const uint32_t* __restrict__ skeys, uint32_t T,
+                                                     uint32_t* __restrict__ tile_start) {
+  const uint32_t n = ctrl->n_key_eff;
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  if (n == 0) {
+    for (uint32_t t = gid; t <= T; t += stride) tile_start[t] = 0u;
+    return;
+  }
+  for (uint32_t i = gid; i < n; i += stride) {
+    const uint32_t k = min(skeys[i], T - 1);  // keys are < T; the clamp only keeps writes in bounds
+    const uint32_t t0 = i ? min(skeys[i - 1], T - 1) + 1u : 0u;
+    for (uint32_t t = t0; t <= k; ++t) tile_start[t] = i;
+    if (i == n - 1)
+      for (uint32_t t = k + 1; t <= T; ++t) tile_start[t] = n;
+  }
+}
+
+uint32_t sort_blocks_for(uint32_t key_cap) {
+  uint32_t g = (key_cap + 4095u) / 4096u;
+  if (g < 1) g = 1;
+  if (g > 1024) g = 1024;
+  return g;
+}
+
+hipError_t launch_sort(const Ctrl* ctrl, uint32_t* keys0, uint32_t* keys1, uint32_t* vals0, uint32_t* vals1,
+                       const uint32_t* rec_of_key, uint32_t* srec, uint32_t* hist, uint32_t G, int bits,
+                       int* final_buf, hipStream_t s) {
+  const int passes = (bits + 7) / 8 < 1 ? 1 : (bits + 7) / 8;
+  uint32_t* kb[2] = {keys0, keys1};
+  uint32_t* vb[2] = {vals0, vals1};
+  int cur = 0;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = 8 * pass;
+    const bool last = pass == passes - 1;
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, s, ctrl, kb[cur], G, shift, hist);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, hist, 256u * G);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kSortThreads), 0, s, ctrl, kb[cur],
+                       pass == 0 ? (const uint32_t*)nullptr : vb[cur], kb[cur ^ 1], vb[cur ^ 1], hist, G, shift,
+                       last ? rec_of_key : (const uint32_t*)nullptr, last ? srec : (uint32_t*)nullptr);
+    cur ^= 1;
+  }
+  *final_buf = cur;
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, uint32_t* tile_start,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_ranges, dim3(1024), dim3(256), 0, s, ctrl, skeys, num_tiles, tile_start);
+  return hipGetLastError();
+}
+
+}  // namespace ug

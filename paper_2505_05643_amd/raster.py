@@ -1,0 +1,260 @@
+"""Python binding of the probe-plane rasterizer: plans, render, backward.
+
+Thin layer over ``libug.so``: it marshals torch device pointers and the
+current HIP stream into the C ABI and owns nothing but the workspace tensor.
+Every step of the render and its adjoint runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import NamedTuple, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import lib, check
+
+
+@dataclasses.dataclass
+class Params:
+    beta: float = 1e-4
+    chi2: float = 7.815
+    bg_alpha: float = 1e-2
+    bg_color: float = 0.0
+    tile_w: int = 16
+    tile_h: int = 16
+    px_per_lane: int = 0
+    lds_batch: int = 64
+    box_mode: int = _lib.UG_BOX_PAPER
+    flags: int = 0
+
+    def to_c(self) -> _lib.UgParams:
+        p = _lib.UgParams()
+        lib.ug_params_default(ctypes.byref(p))
+        for f in dataclasses.fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        return p
+
+
+class GaussianTensors(NamedTuple):
+    means: torch.Tensor      # [N,3]
+    lraw: torch.Tensor       # [N,6]
+    intensity: torch.Tensor  # [N]
+    opacity: torch.Tensor    # [N] logits
+
+
+class PlaneTensors(NamedTuple):
+    rot: torch.Tensor        # [P,9]
+    origin: torch.Tensor     # [P,3]
+    spacing: torch.Tensor    # [P,2]
+
+
+def _dev_f32(t: torch.Tensor, shape_tail, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 CUDA/HIP tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}")
+    return t
+
+
+def _c_gauss(g: GaussianTensors) -> _lib.UgGaussians:
+    n = g.means.shape[0]
+    _dev_f32(g.means, (3,), "means")
+    _dev_f32(g.lraw, (6,), "lraw")
+    _dev_f32(g.intensity, (), "intensity")
+    _dev_f32(g.opacity, (), "opacity")
+    if not (g.lraw.shape[0] == g.intensity.shape[0] == g.opacity.shape[0] == n):
+        raise ValueError("Gaussian tensors disagree on N")
+    return _lib.UgGaussians(g.means.data_ptr(), g.lraw.data_ptr(), g.intensity.data_ptr(),
+                            g.opacity.data_ptr(), n)
+
+
+def _c_planes(pl: PlaneTensors) -> _lib.UgPlanes:
+    p = pl.rot.shape[0]
+    _dev_f32(pl.rot, (9,), "rot")
+    _dev_f32(pl.origin, (3,), "origin")
+    _dev_f32(pl.spacing, (2,), "spacing")
+    if not (pl.origin.shape[0] == pl.spacing.shape[0] == p):
+        raise ValueError("plane tensors disagree on P")
+    return _lib.UgPlanes(pl.rot.data_ptr(), pl.origin.data_ptr(), pl.spacing.data_ptr(), p)
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """A render plan: N Gaussians onto P planes of fixed pixel sizes.
+
+    Capacities (records, keys) bound one render's work buffers; ``fit``
+    measures them for given inputs.  The workspace tensor carries the
+    forward's state to the backward, so a backward must follow its own
+    forward before the next forward on the same plan.
+    """
+
+    def __init__(self, n: int, wh: Sequence[Sequence[int]], params: Params | None = None,
+                 record_capacity: int = 0, key_capacity: int = 0, device=None):
+        self.params = params or Params()
+        self.wh = np.ascontiguousarray(np.asarray(wh, dtype=np.int32).reshape(-1, 2))
+        self.n = int(n)
+        self.p = int(self.wh.shape[0])
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._c_params = self.params.to_c()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib.ug_plan_create(self.n, self.p, self.wh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     ctypes.byref(self._c_params), int(record_capacity), int(key_capacity),
+                                     ctypes.byref(h)), "ug_plan_create")
+        self._h = h
+        self.num_pixels = int(lib.ug_plan_num_pixels(h))
+        self.num_tiles = int(lib.ug_plan_num_tiles(h))
+        self.record_capacity = int(record_capacity)
+        self.key_capacity = int(key_capacity)
+        self._ws = None
+        self._ws_ptr = 0
+        self.forward_count = 0
+        self._alloc_ws()
+
+    # ---------------------------------------------------------------- workspace
+    def _alloc_ws(self):
+        nbytes = int(lib.ug_plan_workspace_bytes(self._h))
+        if self._ws is not None and self._ws.numel() >= nbytes + 256:
+            return
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib.ug_plan_workspace_bytes(self._h))
+
+    def reserve(self, record_capacity: int, key_capacity: int):
+        check(lib.ug_plan_reserve(self._h, int(record_capacity), int(key_capacity)), "ug_plan_reserve")
+        self.record_capacity, self.key_capacity = int(record_capacity), int(key_capacity)
+        self._alloc_ws()
+
+    def measure(self, g: GaussianTensors, planes: PlaneTensors):
+        """Exact (records, keys) a render of these inputs needs (synchronises)."""
+        cg, cp = _c_gauss(g), _c_planes(planes)
+        out = (ctypes.c_int64 * 2)()
+        code = lib.ug_plan_measure(self._h, ctypes.byref(cg), ctypes.byref(cp), self._ws_ptr, out, _stream())
+        if code not in (_lib.UG_OK, _lib.UG_ERR_NONFINITE):
+            check(code, "ug_plan_measure")
+        return int(out[0]), int(out[1])
+
+    def fit(self, g: GaussianTensors, planes: PlaneTensors, headroom: float = 1.25):
+        """Sizes the capacities for these inputs (plus headroom) if needed."""
+        r, k = self.measure(g, planes)
+        if r > self.record_capacity or k > self.key_capacity:
+            self.reserve(max(int(r * headroom) + 16, r), max(int(k * headroom) + 64, k))
+        return r, k
+
+    # ---------------------------------------------------------------- passes
+    def render(self, g: GaussianTensors, planes: PlaneTensors, image: torch.Tensor | None = None,
+               check_status: bool = True) -> torch.Tensor:
+        cg, cp = _c_gauss(g), _c_planes(planes)
+        if image is None:
+            image = torch.empty(self.num_pixels, dtype=torch.float32, device=self.device)
+        elif image.numel() != self.num_pixels or not image.is_contiguous() or image.dtype != torch.float32:
+            raise ValueError("image must be a contiguous float32 tensor of num_pixels elements")
+        check(lib.ug_render_planes(self._h, ctypes.byref(cg), ctypes.byref(cp), image.data_ptr(), self._ws_ptr,
+                                   _stream()), "ug_render_planes")
+        self.forward_count += 1
+        if check_status:
+            code = self.status()
+            if code == _lib.UG_ERR_CAPACITY:
+                self.fit(g, planes)
+                return self.render(g, planes, image, check_status)
+            if code not in (_lib.UG_OK, _lib.UG_ERR_NONFINITE):
+                check(code, "render status")
+        return image
+
+    def backward(self, g: GaussianTensors, planes: PlaneTensors, image: torch.Tensor, d_image: torch.Tensor,
+                 grads: GaussianTensors | None = None, accumulate: bool = False) -> GaussianTensors:
+        cg, cp = _c_gauss(g), _c_planes(planes)
+        n = g.means.shape[0]
+        if grads is None:
+            dev = self.device
+            grads = GaussianTensors(torch.empty(n, 3, device=dev), torch.empty(n, 6, device=dev),
+                                    torch.empty(n, device=dev), torch.empty(n, device=dev))
+        d_image = d_image.contiguous()
+        if d_image.numel() != self.num_pixels or d_image.dtype != torch.float32:
+            raise ValueError("d_image must be float32 with num_pixels elements")
+        check(lib.ug_render_planes_backward(self._h, ctypes.byref(cg), ctypes.byref(cp), image.data_ptr(),
+                                            d_image.data_ptr(), self._ws_ptr, grads.means.data_ptr(),
+                                            grads.lraw.data_ptr(), grads.intensity.data_ptr(),
+                                            grads.opacity.data_ptr(), 1 if accumulate else 0, _stream()),
+              "ug_render_planes_backward")
+        return grads
+
+    def status(self, counts: bool = False):
+        """Device status of the last render (synchronises); with counts=True
+        (code, records, keys, in-support pairs or 0)."""
+        out = (ctypes.c_int64 * 3)()
+        code = lib.ug_plan_status(self._h, self._ws_ptr, out, _stream())
+        if code == _lib.UG_ERR_HIP:
+            check(code, "ug_plan_status")
+        return (code, int(out[0]), int(out[1]), int(out[2])) if counts else code
+
+    # ---------------------------------------------------------------- measurement
+    def profile_begin(self, stages=None, max_launches: int = 4096):
+        """Start per-stage HIP-event timing on the launch stream."""
+        names = _lib.STAGES if stages is None else stages
+        mask = 0
+        for nm in names:
+            mask |= 1 << _lib.STAGES.index(nm)
+        check(lib.ug_profile_begin(self._h, mask, int(max_launches)), "ug_profile_begin")
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} since profile_begin; stops timing."""
+        ms = (ctypes.c_float * _lib.UG_NUM_STAGES)()
+        cnt = (ctypes.c_int32 * _lib.UG_NUM_STAGES)()
+        check(lib.ug_profile_read(self._h, ms, cnt), "ug_profile_read")
+        return {nm: (float(ms[i]), int(cnt[i])) for i, nm in enumerate(_lib.STAGES) if cnt[i]}
+
+    def split_image(self, image: torch.Tensor):
+        """Views of a packed image, one [H, W] per plane."""
+        out, o = [], 0
+        for W, H in self.wh:
+            out.append(image[o:o + W * H].view(int(H), int(W)))
+            o += int(W) * int(H)
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.ug_plan_destroy(h)
+            self._h = None
+
+
+def mse_grad(image: torch.Tensor, target: torch.Tensor, d_image: torch.Tensor | None = None,
+             loss_buf: torch.Tensor | None = None):
+    """(loss tensor [1], d_image) of the mean squared error, on the device."""
+    m = image.numel()
+    if d_image is None:
+        d_image = torch.empty_like(image)
+    if loss_buf is None:
+        loss_buf = torch.empty(_lib.UG_MSE_SCRATCH_FLOATS, dtype=torch.float32, device=image.device)
+    check(lib.ug_mse_grad(image.data_ptr(), target.data_ptr(), m, d_image.data_ptr(), loss_buf.data_ptr(),
+                          _stream()), "ug_mse_grad")
+    return loss_buf[:1], d_image
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr: float, step: int,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    check(lib.ug_adam_step(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), param.numel(),
+                           float(lr), float(beta1), float(beta2), float(eps), int(step), _stream()),
+          "ug_adam_step")
+
+
+def to_device(obj, device="cuda"):
+    """synth.Gaussians / synth.Planes (numpy) -> tensor tuples on the device."""
+    if hasattr(obj, "lraw"):
+        return GaussianTensors(*(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+                                 for a in (obj.means, obj.lraw, obj.intensity, obj.opacity)))
+    return PlaneTensors(*(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+                          for a in (obj.rot, obj.origin, obj.spacing)))

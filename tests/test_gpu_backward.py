@@ -1,0 +1,133 @@
+"""Adjoint parity: HIP backward vs the oracle's analytic gradient and FP64
+finite differences of the oracle's forward."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_05643_amd import synth
+from tests.parity import check_grads, oracle_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_05643_amd import raster
+    return raster
+
+
+def _fwd_bwd(R, g, pl, dimg, params=None):
+    params = params or R.Params()
+    dev = torch.device("cuda", 0)
+    gd, pd = R.to_device(g, dev), R.to_device(pl, dev)
+    plan = R.Plan(g.n, pl.wh, params, device=dev)
+    plan.fit(gd, pd)
+    img = plan.render(gd, pd)
+    grads = plan.backward(gd, pd, img, torch.from_numpy(np.asarray(dimg, dtype=np.float32)).to(dev))
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy().astype(np.float64) for k, v in zip(("means", "lraw", "intensity", "opacity"), grads)}
+    return img.cpu().numpy(), out, plan
+
+
+def test_config0_gradients_full(R):
+    g, pl, _ = synth.make_config(0)
+    rng = np.random.default_rng(1)
+    dimg = rng.standard_normal(pl.npix)
+    _, gg, plan = _fwd_bwd(R, g, pl, dimg)
+    ref = oracle.grad(g, pl, dimg.astype(np.float32).astype(np.float64), oracle_params(plan.params))
+    print("c0 grads", check_grads(gg, ref))
+
+
+def test_mse_loss_gradients_random_opacity(R):
+    """d_image from an MSE against a second Gaussian set, as in training."""
+    g = synth.make_gaussians(250, 51, (0, 0, 0), (1, 1, 1), (0.03, 0.15), aniso_max=10.0, opacity="random")
+    t = synth.make_gaussians(250, 52, (0, 0, 0), (1, 1, 1), (0.03, 0.15))
+    pl = synth.random_planes(3, 53, (40, 33), 1 / 36, 0.35, 0.65)
+    img_ref, _ = oracle.render(t, pl)
+    op = oracle.Params()
+    cur, _ = oracle.render(g, pl, op)
+    dimg = 2.0 * (cur - img_ref) / cur.size
+    for bm in (0, 2):
+        _, gg, plan = _fwd_bwd(R, g, pl, dimg, R.Params(box_mode=bm, tile_w=16, tile_h=8))
+        ref = oracle.grad(g, pl, dimg.astype(np.float32).astype(np.float64), oracle_params(plan.params))
+        check_grads(gg, ref)
+
+
+def _fd_oracle(g, X, dout, prm, h=1e-6):
+    base = {k: np.array(getattr(g, k), dtype=np.float64) for k in ("means", "lraw", "intensity", "opacity")}
+    out = {}
+    for k in base:
+        num = np.zeros_like(base[k])
+        flat = num.reshape(-1)
+        for j in range(flat.size):
+            ap = {kk: vv.copy() for kk, vv in base.items()}
+            am = {kk: vv.copy() for kk, vv in base.items()}
+            x0 = ap[k].reshape(-1)[j]
+            step = h * max(1.0, abs(x0))
+            ap[k].reshape(-1)[j] += step
+            am[k].reshape(-1)[j] -= step
+            lp = oracle.render_points(synth.Gaussians(**ap), X, prm)[0] @ dout
+            lm = oracle.render_points(synth.Gaussians(**am), X, prm)[0] @ dout
+            flat[j] = (lp - lm) / (2 * step)
+        out[k] = num
+    return out
+
+
+@pytest.mark.parametrize("chi2", [math.inf, 7.815])
+def test_gradients_vs_fp64_finite_differences(R, chi2):
+    rng = np.random.default_rng(7)
+    for seed in range(60, 120):
+        g = synth.make_gaussians(6, seed, (0.35, 0.35, 0.35), (0.65, 0.65, 0.65), (0.05, 0.18), opacity="random")
+        pl = synth.random_planes(2, seed + 200, (20, 18), 0.025, 0.47, 0.53)
+        X = oracle.plane_points(pl)
+        d2 = oracle.d2_points(g, X)
+        if math.isinf(chi2) or (np.min(np.abs(d2 - chi2)) > 2e-3 and np.any(d2 <= chi2)):
+            break
+    dimg = rng.standard_normal(X.shape[0]).astype(np.float32).astype(np.float64)
+    _, gg, plan = _fwd_bwd(R, g, pl, dimg, R.Params(chi2=chi2, tile_w=8, tile_h=8))
+    fd = _fd_oracle(g, X, dimg, oracle_params(plan.params))
+    print("fd", check_grads(gg, fd))
+
+
+@pytest.mark.parametrize("k,count", [(1, 400), (2, 200), (3, 150)])
+def test_configs_sparse_upstream_gradient(R, k, count):
+    """Full-size renders; d_image is non-zero on seeded pixels only, so the
+    oracle's exact gradient needs just those pixels."""
+    g, pl, _ = synth.make_config(k)
+    pix = synth.sample_pixels(pl, count, 600 + k)
+    offs = pl.pixel_offsets()
+    flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
+    rng = np.random.default_rng(k)
+    vals = rng.standard_normal(count).astype(np.float32)
+    dimg = np.zeros(pl.npix, dtype=np.float32)
+    dimg[flat] = vals
+    _, gg, plan = _fwd_bwd(R, g, pl, dimg)
+    ref = oracle.grad_points(g, oracle.plane_points(pl, pix), vals.astype(np.float64), oracle_params(plan.params))
+    print(f"c{k} grads", check_grads(gg, ref))
+
+
+def test_accumulate_flag_and_autograd(R):
+    from paper_2505_05643_amd.autograd import render_planes
+    g = synth.make_gaussians(120, 71, (0, 0, 0), (1, 1, 1), (0.03, 0.15), opacity="random")
+    pl = synth.random_planes(2, 72, (30, 30), 1 / 30, 0.4, 0.6)
+    dev = torch.device("cuda", 0)
+    gd, pd = R.to_device(g, dev), R.to_device(pl, dev)
+    plan = R.Plan(g.n, pl.wh, device=dev)
+    plan.fit(gd, pd)
+    leaves = [t.clone().requires_grad_(True) for t in gd]
+    img = render_planes(R.GaussianTensors(*leaves), pd, plan)
+    w = torch.randn(img.shape, device=dev)
+    (img * w).sum().backward()
+    img2 = plan.render(gd, pd)
+    assert torch.equal(img.detach(), img2)
+    g1 = plan.backward(gd, pd, img2, w)
+    for a, b in zip(leaves, g1):
+        assert torch.equal(a.grad, b)
+    plan.backward(gd, pd, img2, w, grads=g1, accumulate=True)
+    for a, b in zip(leaves, g1):
+        torch.testing.assert_close(b, 2 * a.grad, rtol=1e-6, atol=0)

@@ -1,0 +1,112 @@
+"""Forward parity: HIP render vs the FP64 oracle, element by element."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2505_05643_amd import synth
+from tests.parity import check_image
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_05643_amd import raster
+    return raster
+
+
+def _render(R, g, pl, params=None, fit=True):
+    params = params or R.Params()
+    dev = torch.device("cuda", 0)
+    gd, pd = R.to_device(g, dev), R.to_device(pl, dev)
+    plan = R.Plan(g.n, pl.wh, params, device=dev)
+    if fit:
+        plan.fit(gd, pd)
+    img = plan.render(gd, pd)
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), plan
+
+
+def test_config0_full_image(R):
+    g, pl, _ = synth.make_config(0)
+    img, plan = _render(R, g, pl)
+    st = check_image(img, g, pl, plan.params)
+    print("c0", st)
+
+
+def test_small_ragged_planes_several_tiles(R):
+    g = synth.make_gaussians(300, 41, (0, 0, 0), (1, 1, 1), (0.02, 0.12), opacity="random")
+    pl = synth.random_planes(3, 42, (8, 8), 1 / 40, 0.3, 0.7)
+    pl.wh[:] = [[37, 23], [8, 8], [50, 41]]
+    for bm in (0, 1, 2):
+        img, plan = _render(R, g, pl, R.Params(box_mode=bm))
+        check_image(img, g, pl, plan.params)
+
+
+def test_no_gaussians_is_background(R):
+    g = synth.make_gaussians(0, 1)
+    pl = synth.random_planes(2, 3, (20, 12), 0.05)
+    params = R.Params(bg_color=0.25)
+    img, _ = _render(R, g, pl, params, fit=False)
+    assert np.all(img == np.float32(0.25))
+
+
+def test_chi2_infinite_and_bright_background(R):
+    g = synth.make_gaussians(40, 5, (0.3, 0.3, 0.3), (0.7, 0.7, 0.7), (0.05, 0.2), opacity="random")
+    pl = synth.random_planes(2, 6, (24, 20), 1 / 24, 0.45, 0.55)
+    for params in (R.Params(chi2=math.inf), R.Params(bg_alpha=1.0, bg_color=0.5)):
+        img, plan = _render(R, g, pl, params)
+        check_image(img, g, pl, plan.params)
+
+
+def test_one_pixel_planes_and_far_planes(R):
+    g = synth.make_gaussians(64, 7, (0, 0, 0), (1, 1, 1), (0.05, 0.3))
+    pl = synth.pack_planes([np.eye(3), synth.axis_angle((1, 1, 0), 0.4), np.eye(3)],
+                           [(0.5, 0.5, 0.5), (0.4, 0.6, 0.5), (10.0, 10.0, 10.0)],
+                           [(0.1, 0.1), (0.02, 0.05), (0.1, 0.1)], [(1, 1), (3, 70), (16, 16)])
+    img, plan = _render(R, g, pl)
+    check_image(img, g, pl, plan.params)
+    assert np.all(img[-256:] == 0.0)  # the far plane sees background only
+
+
+def test_tile_shapes_box_modes_batches(R):
+    """Within one tile shape, every pixels-per-lane, LDS batch and binning box
+    gives the same image bit for bit (each pixel sums its in-support Gaussians
+    in record order; a binned pair outside the support adds exactly zero).
+    Across tile shapes only the tile-relative coordinates round differently."""
+    g = synth.make_gaussians(500, 43, (0, 0, 0), (1, 1, 1), (0.02, 0.12), aniso_max=8.0, opacity="random")
+    pl = synth.random_planes(3, 44, (8, 8), 1 / 48, 0.35, 0.65)
+    pl.wh[:] = [[61, 47], [32, 32], [48, 17]]
+    base, plan = _render(R, g, pl)
+    check_image(base, g, pl, plan.params)
+    shapes = {(8, 8): (1,), (16, 8): (1, 2), (16, 16): (1, 2, 4), (32, 8): (1, 2, 4), (32, 16): (2, 4, 8)}
+    for (tw, th), ppls in shapes.items():
+        first = None
+        for ppl in ppls:
+            for bg in (32, 64, 128, 256):
+                for bm in (0, 1, 2):
+                    if bm != 0 and bg != 64:
+                        continue
+                    img, _ = _render(R, g, pl, R.Params(tile_w=tw, tile_h=th, px_per_lane=ppl, lds_batch=bg,
+                                                        box_mode=bm))
+                    if first is None:
+                        first = img
+                        assert np.max(np.abs(img - base)) <= 1e-6 * np.abs(base).max(), (tw, th)
+                    assert np.array_equal(img, first), (tw, th, ppl, bg, bm)
+
+
+@pytest.mark.parametrize("k,count", [(1, 1500), (2, 800), (3, 600), (4, 300)])
+def test_configs_sampled_pixels(R, k, count):
+    """Full-size workloads in the benchmark's launch configuration; the oracle
+    evaluates a seeded sample of pixels against every Gaussian."""
+    g, pl, _ = synth.make_config(k)
+    img, plan = _render(R, g, pl)
+    pix = synth.sample_pixels(pl, count, 500 + k)
+    offs = pl.pixel_offsets()
+    flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
+    st = check_image(img[flat], g, pl, plan.params, pix=pix)
+    print(f"c{k}", st, "records/keys", plan.status(counts=True))
