@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-plane comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-px", type=int, default=640)
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU (plane-sharded) path is a design, "
@@ -142,7 +143,7 @@ def main():
     assert code == 0, f"render status {code}"
 
     # ---- timed region (per-stage events on the launch stream) ----
-    plan.profile_begin(max_launches=args.steps * 16 + 16)
+    plan.profile_begin(max_launches=args.steps * 12 + 16)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -153,7 +154,34 @@ def main():
     torch.cuda.synchronize()
     ms_total = t0.elapsed_time(t1)
     stages = plan.profile_read()
-    ms_step = ms_total / args.steps
+    eager_ms_step = ms_total / args.steps
+    eager_image = image.clone()
+
+    # ---- the same step captured once as a hipGraph and replayed ----
+    graph_ms_step = None
+    if not args.no_graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(image, eager_image), "graph replay must match the eager step"
+        t0.record()
+        for _ in range(args.steps):
+            graph.replay()
+        t1.record()
+        torch.cuda.synchronize()
+        graph_ms_step = t0.elapsed_time(t1) / args.steps
+        assert torch.equal(image, eager_image), "graph replay must match the eager step"
+        del graph
+    ms_step = graph_ms_step if graph_ms_step is not None else eager_ms_step
+    ms_total = ms_step * args.steps
     planes_s = pl.p * args.steps / (ms_total / 1e3)
 
     # in-support pairs of one forward, counted by the kernel itself
@@ -191,15 +219,29 @@ def main():
         for _ in range(max(2, args.warmup // 2)):
             plain_step()
         torch.cuda.synchronize()
+        run = plain_step
+        if graph_ms_step is not None:  # same launch mode as the batched figure
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                plain_step()
+            torch.cuda.current_stream().wait_stream(side)
+            pgraph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(pgraph):
+                plain_step()
+            run = pgraph.replay
+            run()
+            torch.cuda.synchronize()
         psteps = max(3, args.steps // 4)
         t0.record()
         for _ in range(psteps):
-            plain_step()
+            run()
         t1.record()
         torch.cuda.synchronize()
         pms = t0.elapsed_time(t1) / psteps
         plain = {"planes_per_s": pl.p / (pms / 1e3), "ms_per_step": pms,
-                 "batched_speedup": (pl.p / (ms_step / 1e3)) / (pl.p / (pms / 1e3))}
+                 "launch": "hipGraph replay" if graph_ms_step is not None else "eager",
+                 "batched_speedup": pms / ms_step}
         del per
 
     # ---- roofline of the dominant kernel ----
@@ -213,8 +255,8 @@ def main():
                 "work": f"{FLOPS_PER_PAIR[dom_name]} flop x {n_eval} in-support pairs per launch",
                 "avg_launch_ms": avg_ms}
     else:
-        nbytes = {"sort": n_key * 20 * ((plan_bits(plan) + 7) // 8), "cull": g.n * 44,
-                  "write": n_rec * 56 + g.n * 44, "emit": n_key * 8 + n_rec * 24}.get(dom_name, 0)
+        nbytes = {"sort": n_key * 20 * ((plan_bits(plan) + 7) // 8), "cull": g.n * 44 + n_rec * 8,
+                  "record": n_rec * 60 + n_key * 8}.get(dom_name, 0)
         ach = nbytes / (avg_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": dom_name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms}
@@ -243,7 +285,10 @@ def main():
         "config": {"workload": synth.CONFIG_NAMES[k], "gaussians": g.n, "planes": pl.p,
                    "pixels": int(pl.npix), "tile": f"{params.tile_w}x{params.tile_h}",
                    "px_per_lane": plan_ppl(params), "lds_batch": params.lds_batch, "box_mode": params.box_mode,
-                   "step": "render + mse grad + backward"},
+                   "step": "render + mse grad + backward",
+                   "launch": "hipGraph replay" if graph_ms_step is not None else "eager"},
+        "eager_ms_per_step": eager_ms_step,
+        "graph_ms_per_step": graph_ms_step,
         "evals_per_s": evals_s,
         "in_support_pairs": n_eval,
         "records": n_rec,

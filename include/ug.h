@@ -57,19 +57,17 @@ extern "C" {
 #define UG_FLAG_COUNT_EVALS 1 /* forward also counts in-support (Gaussian, pixel) pairs */
 
 /* ---- pipeline stages (measurement hooks) ------------------------------- */
-#define UG_STAGE_SETUP 0     /* plane pose set-up                              */
-#define UG_STAGE_CULL 1      /* Phase-1 cull and per-Gaussian counts (Sec. 4.4) */
-#define UG_STAGE_SCAN 2      /* offsets of records and keys                     */
-#define UG_STAGE_WRITE 3     /* record (in-plane conic) construction            */
-#define UG_STAGE_EMIT 4      /* key emission: one key per (record, tile)        */
-#define UG_STAGE_SORT 5      /* radix sort of the keys by tile (all passes)     */
-#define UG_STAGE_RANGES 6    /* per-tile key ranges                             */
-#define UG_STAGE_ACCUM 7     /* per-tile accumulation, Eq. 5-8 and 12           */
-#define UG_STAGE_BWD_PREP 8  /* per-pixel adjoint inputs                        */
-#define UG_STAGE_ACCUM_BWD 9 /* per-key adjoint of the accumulation             */
-#define UG_STAGE_REDUCE 10   /* per-record sums of the key adjoints             */
-#define UG_STAGE_PREP_BWD 11 /* per-Gaussian adjoint of the record construction */
-#define UG_NUM_STAGES 12
+#define UG_STAGE_SETUP 0      /* plane pose set-up                                 */
+#define UG_STAGE_CULL 1       /* Phase-1 cull and record compaction (Sec. 4.4)     */
+#define UG_STAGE_RECORD 2     /* in-plane conic, key offsets, key emission          */
+#define UG_STAGE_SORT 3       /* radix sort of the keys by tile (all passes)        */
+#define UG_STAGE_RANGES 4     /* per-tile key ranges                                */
+#define UG_STAGE_ACCUM 5      /* per-tile accumulation, Eq. 5-8 and 12              */
+#define UG_STAGE_BWD_PREP 6   /* per-pixel adjoint inputs                           */
+#define UG_STAGE_ACCUM_BWD 7  /* per-key adjoint of the accumulation                */
+#define UG_STAGE_RECORD_ADJ 8 /* per-record adjoint of the conic construction       */
+#define UG_STAGE_GAUSS_GRAD 9 /* per-Gaussian sum of its records' adjoints          */
+#define UG_NUM_STAGES 10
 
 typedef struct ug_plan ug_plan; /* opaque, host-side */
 
@@ -125,7 +123,7 @@ int ug_plan_create(int32_t n, int32_t p, const int32_t *wh_host, const ug_params
 int ug_plan_reserve(ug_plan *plan, int64_t record_capacity, int64_t key_capacity);
 
 /* Bytes of device workspace a render/backward pair needs (256-byte aligned
- * base required).  With zero capacities this is the size ug_plan_measure needs. */
+ * base required). */
 size_t ug_plan_workspace_bytes(const ug_plan *plan);
 
 /* Total pixels of the plan (sum of W*H): the length of image buffers. */
@@ -134,10 +132,12 @@ int64_t ug_plan_num_pixels(const ug_plan *plan);
 /* Number of tiles of the plan's tile grid over all planes. */
 int64_t ug_plan_num_tiles(const ug_plan *plan);
 
-/* Runs the culling pass only and returns, synchronously, out_host[0] = the
- * accepted (Gaussian, plane) records and out_host[1] = the (record, tile)
- * keys that ug_render_planes would produce for these inputs.
- * The workspace must hold ug_plan_workspace_bytes() of a zero-capacity plan. */
+/* Runs the culling and record passes (no key emission) and returns,
+ * synchronously, out_host[0] = the accepted (Gaussian, plane) records and
+ * out_host[1] = the (record, tile) keys that ug_render_planes would produce
+ * for these inputs; out_host[1] is -1 when the records exceed the plan's
+ * record capacity (reserve, then measure again).  The workspace must hold
+ * ug_plan_workspace_bytes(plan) bytes. */
 int ug_plan_measure(const ug_plan *plan, const ug_gaussians *g, const ug_planes *planes,
                     void *workspace, int64_t *out_host, void *stream);
 

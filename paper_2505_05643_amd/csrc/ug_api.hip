@@ -15,12 +15,9 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  // culling pass (ug_plan_measure needs only these)
-  size_t ctrl, pconst, cnt_rec, cnt_key, blk_rec, blk_key, blk_rec_off, blk_key_off;
-  size_t measure_end;
-  // render state
-  size_t off_rec, tile_start, dsave, gq, hist;
-  size_t racc, rgeo, rec_pid, rec_koff, drec;
+  size_t ctrl, pconst, cnt_rec, off_rec, blk_g, blk_r;
+  size_t rec_pair, racc, rgeo, rec_nkey, rec_koff, contrib;
+  size_t tile_start, dsave, gq, hist;
   size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, partial;
   size_t total;
 };
@@ -37,7 +34,6 @@ struct ug_plan {
   int final_buf = 0;
   uint32_t rec_cap = 0, key_cap = 0;
   uint32_t sort_blocks = 1;
-  int nblk = 0;
   int device = 0;
   PlaneInt* d_pint = nullptr;
   uint32_t* d_tile_plane = nullptr;
@@ -63,28 +59,25 @@ void compute_layout(ug_plan* pl) {
     o = align_up(o + (bytes ? bytes : 1));
     return at;
   };
-  const size_t n = (size_t)pl->n, P = (size_t)pl->p, nblk = (size_t)(pl->nblk > 0 ? pl->nblk : 1);
+  const size_t n = (size_t)pl->n, P = (size_t)pl->p;
+  const size_t T = pl->num_tiles, R = pl->rec_cap, K = pl->key_cap;
+  const size_t tpx = (size_t)pl->prm.tile_w * pl->prm.tile_h;
   L.ctrl = take(sizeof(Ctrl));
   L.pconst = take(P * sizeof(PlaneConst));
   L.cnt_rec = take(n * 4);
-  L.cnt_key = take(n * 4);
-  L.blk_rec = take(nblk * 4);
-  L.blk_key = take(nblk * 4);
-  L.blk_rec_off = take(nblk * 8);
-  L.blk_key_off = take(nblk * 8);
-  L.measure_end = o;
-  const size_t T = pl->num_tiles, R = pl->rec_cap, K = pl->key_cap;
-  const size_t tpx = (size_t)pl->prm.tile_w * pl->prm.tile_h;
-  L.off_rec = take(n * 4);
+  L.off_rec = take(n * 8);
+  L.blk_g = take((size_t)cull_blocks(pl->n, pl->p) * 4);
+  L.blk_r = take((size_t)record_blocks(pl->rec_cap) * 4);
+  L.rec_pair = take(R * 8);
+  L.racc = take(R * sizeof(RecAcc));
+  L.rgeo = take(R * sizeof(RecGeo));
+  L.rec_nkey = take(R * 4);
+  L.rec_koff = take((R + 1) * 4);
+  L.contrib = take(R * 48);
   L.tile_start = take((T + 1) * 4);
   L.dsave = take(pl->num_pixels * 4);
   L.gq = take(T * tpx * 8);
-  L.hist = take((size_t)256 * pl->sort_blocks * 4);
-  L.racc = take(R * sizeof(RecAcc));
-  L.rgeo = take(R * sizeof(RecGeo));
-  L.rec_pid = take(R * 4);
-  L.rec_koff = take((R + 1) * 4);
-  L.drec = take(R * 32);
+  L.hist = take((size_t)256 * (pl->sort_blocks + 1) * 4);
   L.key_tile0 = take(K * 4);
   L.key_tile1 = take(K * 4);
   L.key_val0 = take(K * 4);
@@ -170,9 +163,9 @@ int check_inputs(const ug_plan* plan, const ug_gaussians* g, const ug_planes* pl
   return UG_OK;
 }
 
-// Culling pass shared by measure and render: plane set-up, count, top scan.
-hipError_t enqueue_cull(const ug_plan* plan, const ug_gaussians& g, const ug_planes& pl, void* ws,
-                        const RenderParams& rp, uint32_t* rec_koff, hipStream_t s) {
+// Culling and record passes shared by measure and render.
+hipError_t enqueue_preprocess(const ug_plan* plan, const ug_gaussians& g, const ug_planes& pl, void* ws,
+                              const RenderParams& rp, hipStream_t s) {
   const Layout& L = plan->lay;
   Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
   hipError_t e;
@@ -183,14 +176,16 @@ hipError_t enqueue_cull(const ug_plan* plan, const ug_gaussians& g, const ug_pla
   if (e != hipSuccess) return e;
   {
     StageScope sc(plan, UG_STAGE_CULL, s);
-    e = launch_count(g, at<PlaneConst>(ws, L.pconst), plan->d_pint, rp, at<uint32_t>(ws, L.cnt_rec),
-                     at<uint32_t>(ws, L.cnt_key), at<uint32_t>(ws, L.blk_rec), at<uint32_t>(ws, L.blk_key), ctrl, s);
+    e = launch_cull(g, at<PlaneConst>(ws, L.pconst), rp, at<uint32_t>(ws, L.cnt_rec),
+                    at<unsigned long long>(ws, L.off_rec), at<uint2>(ws, L.rec_pair), at<uint32_t>(ws, L.blk_g),
+                    ctrl, s);
   }
   if (e != hipSuccess) return e;
-  StageScope sc(plan, UG_STAGE_SCAN, s);
-  return launch_top_scan(at<uint32_t>(ws, L.blk_rec), at<uint32_t>(ws, L.blk_key),
-                         at<unsigned long long>(ws, L.blk_rec_off), at<unsigned long long>(ws, L.blk_key_off),
-                         plan->nblk, ctrl, rp.rec_cap, rp.key_cap, rec_koff, s);
+  StageScope sc(plan, UG_STAGE_RECORD, s);
+  return launch_record(g, at<PlaneConst>(ws, L.pconst), plan->d_pint, rp, at<uint2>(ws, L.rec_pair),
+                       at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<uint32_t>(ws, L.rec_nkey),
+                       at<uint32_t>(ws, L.rec_koff), at<uint32_t>(ws, L.blk_r), ctrl, at<uint32_t>(ws, L.key_tile0),
+                       at<uint32_t>(ws, L.rec_of_key), s, false);
 }
 
 }  // namespace
@@ -259,7 +254,6 @@ int ug_plan_create(int32_t n, int32_t p, const int32_t* wh_host, const ug_params
   while (bits < 32 && (uint64_t(1) << bits) < tiles) ++bits;
   pl->bits = bits;
   pl->final_buf = ((bits + 7) / 8) % 2;
-  pl->nblk = (n + 255) / 256;
   pl->device = dev;
   pl->rec_cap = (uint32_t)record_capacity;
   pl->key_cap = (uint32_t)key_capacity;
@@ -306,9 +300,8 @@ int ug_plan_measure(const ug_plan* plan, const ug_gaussians* g, const ug_planes*
   if (!out_host) return UG_ERR_INVALID_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   RenderParams rp = make_rp(plan);
-  rp.rec_cap = 0xffffffffu;
-  rp.key_cap = 0xffffffffu;
-  hipError_t e = enqueue_cull(plan, *g, *planes, workspace, rp, nullptr, s);
+  rp.key_cap = 0;  // count keys, emit none
+  hipError_t e = enqueue_preprocess(plan, *g, *planes, workspace, rp, s);
   if (e != hipSuccess) return UG_ERR_HIP;
   Ctrl c;
   if (hipMemcpyAsync(&c, at<Ctrl>(workspace, plan->lay.ctrl), sizeof(Ctrl), hipMemcpyDeviceToHost, s) !=
@@ -316,7 +309,8 @@ int ug_plan_measure(const ug_plan* plan, const ug_gaussians* g, const ug_planes*
       hipStreamSynchronize(s) != hipSuccess)
     return UG_ERR_HIP;
   out_host[0] = (int64_t)c.n_rec;
-  out_host[1] = (int64_t)c.n_key;
+  out_host[1] = (c.flags & kFlagRecCap) ? -1 : (int64_t)c.n_key;
+  if (c.flags & kFlagInternal) return UG_ERR_INTERNAL;
   return (c.flags & kFlagNonfinite) ? UG_ERR_NONFINITE : UG_OK;
 }
 
@@ -330,22 +324,7 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
   void* ws = workspace;
   const RenderParams rp = make_rp(plan);
   Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
-  uint32_t* rec_koff = at<uint32_t>(ws, L.rec_koff);
-  hipError_t e = enqueue_cull(plan, *g, *planes, ws, rp, rec_koff, s);
-  if (e != hipSuccess) return UG_ERR_HIP;
-  {
-    StageScope sc(plan, UG_STAGE_WRITE, s);
-    e = launch_write(*g, at<PlaneConst>(ws, L.pconst), plan->d_pint, rp, at<uint32_t>(ws, L.cnt_rec),
-                     at<uint32_t>(ws, L.cnt_key), at<unsigned long long>(ws, L.blk_rec_off),
-                     at<unsigned long long>(ws, L.blk_key_off), at<uint32_t>(ws, L.off_rec), at<RecAcc>(ws, L.racc),
-                     at<RecGeo>(ws, L.rgeo), at<uint32_t>(ws, L.rec_pid), rec_koff, s);
-  }
-  if (e != hipSuccess) return UG_ERR_HIP;
-  {
-    StageScope sc(plan, UG_STAGE_EMIT, s);
-    e = launch_emit(ctrl, at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<uint32_t>(ws, L.rec_pid), rec_koff,
-                    plan->d_pint, rp, at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.rec_of_key), s);
-  }
+  hipError_t e = enqueue_preprocess(plan, *g, *planes, ws, rp, s);
   if (e != hipSuccess) return UG_ERR_HIP;
   int fb = 0;
   {
@@ -402,15 +381,14 @@ int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const 
   }
   if (e != hipSuccess) return UG_ERR_HIP;
   {
-    StageScope sc(plan, UG_STAGE_REDUCE, s);
-    e = launch_reduce_partials(ctrl, at<uint32_t>(ws, L.rec_koff), at<float>(ws, L.partial),
-                               at<float>(ws, L.drec), plan->rec_cap, s);
+    StageScope sc(plan, UG_STAGE_RECORD_ADJ, s);
+    e = launch_record_adjoint(*g, at<PlaneConst>(ws, L.pconst), rp, ctrl, at<uint2>(ws, L.rec_pair),
+                              at<uint32_t>(ws, L.rec_koff), at<float>(ws, L.partial), at<float>(ws, L.contrib), s);
   }
   if (e != hipSuccess) return UG_ERR_HIP;
-  StageScope sc(plan, UG_STAGE_PREP_BWD, s);
-  e = launch_preprocess_bwd(*g, at<PlaneConst>(ws, L.pconst), rp, ctrl, at<uint32_t>(ws, L.cnt_rec),
-                            at<uint32_t>(ws, L.off_rec), at<uint32_t>(ws, L.rec_pid), at<float>(ws, L.drec), d_means,
-                            d_lraw, d_intensity, d_opacity, accumulate, s);
+  StageScope sc(plan, UG_STAGE_GAUSS_GRAD, s);
+  e = launch_gauss_grad(*g, rp, ctrl, at<uint32_t>(ws, L.cnt_rec), at<unsigned long long>(ws, L.off_rec),
+                        at<float>(ws, L.contrib), d_means, d_lraw, d_intensity, d_opacity, accumulate, s);
   return hip_status(e);
 }
 

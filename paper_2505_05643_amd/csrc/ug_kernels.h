@@ -6,32 +6,31 @@
 namespace ug {
 
 // ---- preprocess (ug_preprocess.hip)
+int pair_width(int p);
+uint32_t cull_blocks(int n, int p);
+uint32_t record_blocks(uint32_t rec_cap);
 hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, Ctrl* ctrl, hipStream_t s);
-hipError_t launch_count(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
-                        uint32_t* cnt_rec, uint32_t* cnt_key, uint32_t* blk_rec, uint32_t* blk_key, Ctrl* ctrl,
-                        hipStream_t s);
-hipError_t launch_top_scan(const uint32_t* blk_rec, const uint32_t* blk_key, unsigned long long* blk_rec_off,
-                           unsigned long long* blk_key_off, int nblk, Ctrl* ctrl, uint32_t rec_cap,
-                           uint32_t key_cap, uint32_t* rec_koff, hipStream_t s);
-hipError_t launch_write(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
-                        const uint32_t* cnt_rec, const uint32_t* cnt_key, const unsigned long long* blk_rec_off,
-                        const unsigned long long* blk_key_off, uint32_t* off_rec, RecAcc* racc, RecGeo* rgeo,
-                        uint32_t* rec_pid, uint32_t* rec_koff, hipStream_t s);
-hipError_t launch_emit(const Ctrl* ctrl, const RecAcc* racc, const RecGeo* rgeo, const uint32_t* rec_pid,
-                       const uint32_t* rec_koff, const PlaneInt* pint, const RenderParams& rp, uint32_t* key_tile,
-                       uint32_t* rec_of_key, hipStream_t s);
-hipError_t launch_reduce_partials(const Ctrl* ctrl, const uint32_t* rec_koff, const float* partial, float* drec,
-                                  uint32_t rec_cap, hipStream_t s);
-hipError_t launch_preprocess_bwd(const ug_gaussians& g, const PlaneConst* pc, const RenderParams& rp,
-                                 const Ctrl* ctrl, const uint32_t* cnt_rec, const uint32_t* off_rec,
-                                 const uint32_t* rec_pid, const float* drec, float* d_means, float* d_lraw,
-                                 float* d_int, float* d_op, int accumulate, hipStream_t s);
+// Phase-1 cull: per-Gaussian record counts and offsets, compact pair list.
+hipError_t launch_cull(const ug_gaussians& g, const PlaneConst* pc, const RenderParams& rp, uint32_t* cnt_rec,
+                       unsigned long long* off_rec, uint2* rec_pair, uint32_t* blk_tot, Ctrl* ctrl, hipStream_t s);
+// Records (conic + footprint), key offsets and key emission.
+hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
+                         const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* rec_koff,
+                         uint32_t* blk_tot, Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, hipStream_t s,
+                         bool emit_stage_split);
+hipError_t launch_record_adjoint(const ug_gaussians& g, const PlaneConst* pc, const RenderParams& rp,
+                                 const Ctrl* ctrl, const uint2* rec_pair, const uint32_t* rec_koff,
+                                 const float* partial, float* contrib, hipStream_t s);
+hipError_t launch_gauss_grad(const ug_gaussians& g, const RenderParams& rp, const Ctrl* ctrl, const uint32_t* cnt_rec,
+                             const unsigned long long* off_rec, const float* contrib, float* d_means, float* d_lraw,
+                             float* d_int, float* d_op, int accumulate, hipStream_t s);
 
 // ---- tile binning sort (ug_sort.hip)
 // Stable LSD radix sort of (tile id, emission index) pairs on `bits` key
 // bits, 8 bits per pass.  keys/vals are ping-pong buffers; on return
 // *final_buf (0 or 1) names the buffer holding the sorted pairs, and srec
-// holds rec_of_key[] gathered in sorted order.
+// holds rec_of_key[] gathered in sorted order.  hist holds 256 * (nblocks + 1)
+// words.
 hipError_t launch_sort(const Ctrl* ctrl, uint32_t* keys0, uint32_t* keys1, uint32_t* vals0, uint32_t* vals1,
                        const uint32_t* rec_of_key, uint32_t* srec, uint32_t* hist, uint32_t nblocks, int bits,
                        int* final_buf, hipStream_t s);

@@ -17,10 +17,10 @@ __device__ __forceinline__ void sort_chunk(uint32_t n, uint32_t G, uint32_t b, u
   e = (uint32_t)(e64 < n ? e64 : n);
 }
 
-// Per-block digit histogram, digit-major: hist[d * G + b].
+// Per-block digit histogram, block-major: cnt[b * 256 + d].
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Ctrl* __restrict__ ctrl,
                                                               const uint32_t* __restrict__ keys, uint32_t G,
-                                                              int shift, uint32_t* __restrict__ hist) {
+                                                              int shift, uint32_t* __restrict__ cnt) {
   __shared__ uint32_t h[4][256];
   for (int j = threadIdx.x; j < 1024; j += kSortThreads) (&h[0][0])[j] = 0u;
   __syncthreads();
@@ -30,46 +30,77 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Ctrl* __restr
   for (uint32_t i = s + threadIdx.x; i < e; i += kSortThreads) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
   __syncthreads();
   const int d = threadIdx.x;
-  hist[(size_t)d * G + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+  cnt[(size_t)blockIdx.x * 256 + d] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
-// Single block: exclusive scan over the 256*G histogram entries.
-__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t* __restrict__ hist, uint32_t total) {
-  __shared__ uint32_t sh[1024];
-  const uint32_t t = threadIdx.x;
-  const uint32_t per = (total + 1023) / 1024;
-  const uint32_t a = min(t * per, total), b = min(a + per, total);
+// One block per digit d: exclusive scan of column d over the G blocks
+// (in place), and the column total coltot[d].  G <= 1024.
+__global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ cnt, uint32_t G,
+                                                       uint32_t* __restrict__ coltot) {
+  __shared__ uint32_t sh[4];
+  const uint32_t d = blockIdx.x, t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  uint32_t v[4];
   uint32_t sum = 0;
-  for (uint32_t i = a; i < b; ++i) sum += hist[i];
-  sh[t] = sum;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t b = 4 * t + j;
+    v[j] = b < G ? cnt[(size_t)b * 256 + d] : 0u;
+    sum += v[j];
+  }
+  uint32_t x = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
   __syncthreads();
-  for (uint32_t o = 1; o < 1024; o <<= 1) {
-    const uint32_t add = t >= o ? sh[t - o] : 0u;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
+  uint32_t before = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) before += sh[w];
+    total += sh[w];
   }
-  uint32_t run = sh[t] - sum;
-  for (uint32_t i = a; i < b; ++i) {
-    const uint32_t v = hist[i];
-    hist[i] = run;
-    run += v;
+  uint32_t run = before + x - sum;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t b = 4 * t + j;
+    if (b < G) cnt[(size_t)b * 256 + d] = run;
+    run += v[j];
   }
+  if (t == 0) coltot[d] = total;
 }
 
 // Stable scatter.  The chunk is walked in rounds of 256 consecutive keys;
 // within a wave, lanes holding the same digit are found with eight ballots
-// and ranked by lane order; waves are ordered through LDS.
+// and ranked by lane order; waves are ordered through LDS.  The digit bases
+// come from an exclusive scan of the column totals.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ hist, uint32_t G,
-    int shift, const uint32_t* __restrict__ rec_of_key, uint32_t* __restrict__ srec) {
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ cnt,
+    const uint32_t* __restrict__ coltot, uint32_t G, int shift, const uint32_t* __restrict__ rec_of_key,
+    uint32_t* __restrict__ srec) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t sh[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t s, e;
   sort_chunk(ctrl->n_key_eff, G, blockIdx.x, s, e);
-  run[tid] = hist[(size_t)tid * G + blockIdx.x];
+  {
+    const uint32_t tot = coltot[tid];
+    uint32_t x = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += sh[w];
+    run[tid] = before + x - tot + cnt[(size_t)blockIdx.x * 256 + tid];
+  }
   for (uint32_t base = s; base < e; base += kSortThreads) {
     for (int j = tid; j < 1024; j += kSortThreads) (&wcnt[0][0])[j] = 0u;
     __syncthreads();
@@ -122,7 +153,7 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const Ctrl* __restrict__ ct
 }
 
 uint32_t sort_blocks_for(uint32_t key_cap) {
-  uint32_t g = (key_cap + 4095u) / 4096u;
+  uint32_t g = (key_cap + 2047u) / 2048u;
   if (g < 1) g = 1;
   if (g > 1024) g = 1024;
   return g;
@@ -138,11 +169,12 @@ hipError_t launch_sort(const Ctrl* ctrl, uint32_t* keys0, uint32_t* keys1, uint3
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = 8 * pass;
     const bool last = pass == passes - 1;
+    uint32_t* coltot = hist + (size_t)256 * G;
     hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, s, ctrl, kb[cur], G, shift, hist);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, hist, 256u * G);
+    hipLaunchKernelGGL(k_radix_colscan, dim3(256), dim3(256), 0, s, hist, G, coltot);
     hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kSortThreads), 0, s, ctrl, kb[cur],
-                       pass == 0 ? (const uint32_t*)nullptr : vb[cur], kb[cur ^ 1], vb[cur ^ 1], hist, G, shift,
-                       last ? rec_of_key : (const uint32_t*)nullptr, last ? srec : (uint32_t*)nullptr);
+                       pass == 0 ? (const uint32_t*)nullptr : vb[cur], kb[cur ^ 1], vb[cur ^ 1], hist, coltot, G,
+                       shift, last ? rec_of_key : (const uint32_t*)nullptr, last ? srec : (uint32_t*)nullptr);
     cur ^= 1;
   }
   *final_buf = cur;

@@ -138,7 +138,8 @@ class Plan:
         self._alloc_ws()
 
     def measure(self, g: GaussianTensors, planes: PlaneTensors):
-        """Exact (records, keys) a render of these inputs needs (synchronises)."""
+        """(records, keys) a render of these inputs needs (synchronises); keys
+        is -1 when the records exceed the current record capacity."""
         cg, cp = _c_gauss(g), _c_planes(planes)
         out = (ctypes.c_int64 * 2)()
         code = lib.ug_plan_measure(self._h, ctypes.byref(cg), ctypes.byref(cp), self._ws_ptr, out, _stream())
@@ -149,8 +150,11 @@ class Plan:
     def fit(self, g: GaussianTensors, planes: PlaneTensors, headroom: float = 1.25):
         """Sizes the capacities for these inputs (plus headroom) if needed."""
         r, k = self.measure(g, planes)
-        if r > self.record_capacity or k > self.key_capacity:
-            self.reserve(max(int(r * headroom) + 16, r), max(int(k * headroom) + 64, k))
+        if k < 0 or r > self.record_capacity:
+            self.reserve(max(int(r * headroom) + 16, r), self.key_capacity)
+            r, k = self.measure(g, planes)
+        if k > self.key_capacity:
+            self.reserve(self.record_capacity, max(int(k * headroom) + 64, k))
         return r, k
 
     # ---------------------------------------------------------------- passes
