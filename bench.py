@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-px", type=int, default=640)
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default launch configuration")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU (plane-sharded) path is a design, "
@@ -103,11 +104,15 @@ def main():
     gd, pd, tgd = R.to_device(g, dev), R.to_device(pl, dev), R.to_device(tg, dev)
 
     params = R.Params()
-    try:
+    tuned = None
+    if not (args.tile or args.lds_batch or args.box is not None or args.no_autotune):
         from paper_2505_05643_amd import autotune
-        params = autotune.cached_params(k) or params
-    except Exception:
-        pass
+        params, results = autotune.tune(gd, pd, pl.wh, steps=3)
+        default = next((r for r in results if (r["tile_w"], r["tile_h"], r["px_per_lane"], r["lds_batch"],
+                                               r["box_mode"]) == (16, 16, 1, 64, 0)), None)
+        best = min(results, key=lambda r: r["ms"])
+        tuned = {"candidates": len(results), "best_ms": best["ms"],
+                 "default_16x16_paper_ms": default["ms"] if default else None}
     if args.tile:
         parts = [int(x) for x in args.tile.lower().split("x")]
         params.tile_w, params.tile_h = parts[0], parts[1]
@@ -287,6 +292,7 @@ def main():
                    "px_per_lane": plan_ppl(params), "lds_batch": params.lds_batch, "box_mode": params.box_mode,
                    "step": "render + mse grad + backward",
                    "launch": "hipGraph replay" if graph_ms_step is not None else "eager"},
+        "autotune": tuned,
         "eager_ms_per_step": eager_ms_step,
         "graph_ms_per_step": graph_ms_step,
         "evals_per_s": evals_s,

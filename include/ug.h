@@ -193,6 +193,41 @@ int ug_mse_grad(const float *image, const float *target, int64_t m, float *d_ima
 int ug_adam_step(float *param, const float *grad, float *mo, float *ve, int64_t count,
                  float lr, float beta1, float beta2, float eps, int32_t step_t, void *stream);
 
+/* Mutable Gaussian tensors (device, float32), same layout as ug_gaussians. */
+typedef struct {
+  float *means;     /* [n][3] */
+  float *lraw;      /* [n][6] */
+  float *intensity; /* [n]    */
+  float *opacity;   /* [n]    */
+  int32_t n;
+} ug_gaussians_mut;
+
+/* Adam hyper-parameters for the Gaussian tensors (Section 4.5: Adam, learning
+ * rate 0.05 for every parameter except the means, which start at 1.6e-4 with
+ * an exponential decay; the final value is not given in the paper). */
+typedef struct {
+  float lr_means;       /* learning rate of the means at step 1             */
+  float lr_means_final; /* reached after decay_steps steps, then held        */
+  int32_t decay_steps;  /* >= 1                                             */
+  float lr;             /* learning rate of lraw, intensity and opacity      */
+  float beta1, beta2, eps;
+} ug_adam_params;
+
+/* One Adam step over all four Gaussian tensors in one launch:
+ *   m1 = b1 m1 + (1-b1) g;  m2 = b2 m2 + (1-b2) g^2;
+ *   p -= lr_t * (m1 / (1 - b1^t)) / (sqrt(m2 / (1 - b2^t)) + eps),
+ * with t = 1 + *step_dev read from DEVICE memory and incremented on the
+ * device after the update, so a captured hipGraph advances the schedule on
+ * every replay.  lr_t for the means decays exponentially from lr_means to
+ * lr_means_final over decay_steps.  If plan and workspace are given and the
+ * render that filled the workspace overflowed its capacity, the update and
+ * the step increment are skipped on the device (the gradients were not
+ * computed).  Moments must start at zero and *step_dev at 0. */
+int ug_adam_gaussians(const ug_plan *plan, const void *workspace, const ug_gaussians_mut *params,
+                      const ug_gaussians_mut *grads, const ug_gaussians_mut *m1,
+                      const ug_gaussians_mut *m2, const ug_adam_params *hp, int32_t *step_dev,
+                      void *stream);
+
 /* Human-readable text for a status code (static storage). */
 const char *ug_status_string(int status);
 

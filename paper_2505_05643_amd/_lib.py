@@ -47,6 +47,15 @@ class UgParams(ctypes.Structure):
                 ("lds_batch", c_i32), ("box_mode", c_i32), ("flags", c_i32)]
 
 
+class UgGaussiansMut(ctypes.Structure):
+    _fields_ = [("means", c_vp), ("lraw", c_vp), ("intensity", c_vp), ("opacity", c_vp), ("n", c_i32)]
+
+
+class UgAdamParams(ctypes.Structure):
+    _fields_ = [("lr_means", c_f32), ("lr_means_final", c_f32), ("decay_steps", c_i32), ("lr", c_f32),
+                ("beta1", c_f32), ("beta2", c_f32), ("eps", c_f32)]
+
+
 # name -> (restype, argtypes); mirrors include/ug.h
 SIGNATURES = {
     "ug_params_default": (None, [ctypes.POINTER(UgParams)]),
@@ -66,6 +75,9 @@ SIGNATURES = {
     "ug_adam_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_f32, c_f32, c_f32, c_f32, c_i32, c_vp]),
     "ug_profile_begin": (c_i32, [c_vp, ctypes.c_uint32, c_i32]),
     "ug_profile_read": (c_i32, [c_vp, ctypes.POINTER(c_f32), ctypes.POINTER(c_i32)]),
+    "ug_adam_gaussians": (c_i32, [c_vp, c_vp, ctypes.POINTER(UgGaussiansMut), ctypes.POINTER(UgGaussiansMut),
+                                  ctypes.POINTER(UgGaussiansMut), ctypes.POINTER(UgGaussiansMut),
+                                  ctypes.POINTER(UgAdamParams), c_vp, c_vp]),
     "ug_status_string": (ctypes.c_char_p, [c_i32]),
     "ug_plan_destroy": (None, [c_vp]),
 }

@@ -1,0 +1,133 @@
+"""Launch-configuration autotuner for the probe-plane rasterizer.
+
+Searches tile shape, pixels per lane, LDS batch and binning box for a given
+workload by timing the library's own forward + backward on the device, and
+checks that every candidate renders the same image: bit for bit within a
+tile shape; across shapes the tile-relative FP32 coordinates round
+differently, so to 2e-5 of the peak (a fifth of the parity tolerance) except
+for rare pixels whose pair sits on the cut-off.  Results can be cached per
+workload signature in a JSON file.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+import json
+import os
+
+import numpy as np
+import torch
+
+from . import raster as R
+
+SHAPES = ((8, 8, 1), (16, 8, 1), (16, 8, 2), (16, 16, 1), (16, 16, 2), (16, 16, 4), (32, 8, 1), (32, 8, 2),
+          (32, 8, 4), (32, 16, 2), (32, 16, 4), (32, 16, 8))
+BATCHES = (32, 64, 128, 256)
+BOXES = (R._lib.UG_BOX_PAPER, R._lib.UG_BOX_CONIC, R._lib.UG_BOX_ROWS)
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
+
+def signature(n: int, wh) -> str:
+    wh = np.asarray(wh, dtype=np.int32)
+    h = hashlib.sha1(wh.tobytes()).hexdigest()[:12]
+    dev = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
+    return f"n={n};p={len(wh)};wh={h};dev={dev}"
+
+
+def _time_candidate(params: R.Params, g, planes, wh, d_image, steps: int):
+    plan = R.Plan(g.means.shape[0], wh, params)
+    plan.fit(g, planes)
+    img = torch.empty(plan.num_pixels, device=plan.device)
+    grads = R.GaussianTensors(torch.empty_like(g.means), torch.empty_like(g.lraw),
+                              torch.empty_like(g.intensity), torch.empty_like(g.opacity))
+    for _ in range(2):
+        plan.render(g, planes, img, check_status=False)
+        plan.backward(g, planes, img, d_image, grads)
+    torch.cuda.synchronize()
+    code = plan.status()
+    if code != 0:
+        raise RuntimeError(f"status {code}")
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        plan.render(g, planes, img, check_status=False)
+        plan.backward(g, planes, img, d_image, grads)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps, img.clone(), plan.status(counts=True)
+
+
+def tune(g: R.GaussianTensors, planes: R.PlaneTensors, wh, base: R.Params | None = None, steps: int = 5,
+         shapes=SHAPES, batches=BATCHES, boxes=BOXES, verbose: bool = False):
+    """Returns (best Params, list of result dicts).  Two stages: tile shape x
+    box at LDS batch 64, then the LDS batch for the three best."""
+    base = base or R.Params()
+    rng = np.random.default_rng(0)
+    npx = int(np.sum(np.asarray(wh, dtype=np.int64)[:, 0] * np.asarray(wh, dtype=np.int64)[:, 1]))
+    d_image = torch.from_numpy(rng.standard_normal(npx).astype(np.float32)).to(g.means.device)
+    results = []
+    ref_img = {}
+    peak = None
+
+    def run(tw, th, ppl, bg, box):
+        nonlocal peak
+        prm = dataclasses.replace(base, tile_w=tw, tile_h=th, px_per_lane=ppl, lds_batch=bg, box_mode=box)
+        ms, img, st = _time_candidate(prm, g, planes, wh, d_image, steps)
+        if peak is None:
+            peak = float(img.abs().max())
+        key = (tw, th)
+        off = 0
+        if key in ref_img:
+            if not torch.equal(img, ref_img[key]):
+                raise RuntimeError(f"candidate {prm} renders a different image than its tile shape's first")
+        else:
+            ref_img[key] = img
+            first = next(iter(ref_img.values()))
+            # Pixels with a pair on the cut-off (d^2 = chi^2 to rounding) may
+            # legitimately flip between shapes; they must stay rare.
+            off = int(((img - first).abs() > 2e-5 * max(peak, 1e-30)).sum())
+            if off > max(1, 1e-4 * img.numel()):
+                raise RuntimeError(f"candidate {prm}: {off} pixels differ from the first tile shape")
+        rec = {"tile_w": tw, "tile_h": th, "px_per_lane": ppl, "lds_batch": bg, "box_mode": box, "ms": ms,
+               "records": st[1], "keys": st[2], "cutoff_flips": off}
+        results.append(rec)
+        if verbose:
+            print(rec, flush=True)
+        return rec
+
+    for tw, th, ppl in shapes:
+        for box in boxes:
+            run(tw, th, ppl, 64, box)
+    best = sorted(results, key=lambda r: r["ms"])[:3]
+    for b in best:
+        for bg in batches:
+            if bg != 64:
+                run(b["tile_w"], b["tile_h"], b["px_per_lane"], bg, b["box_mode"])
+    top = min(results, key=lambda r: r["ms"])
+    params = dataclasses.replace(base, tile_w=top["tile_w"], tile_h=top["tile_h"], px_per_lane=top["px_per_lane"],
+                                 lds_batch=top["lds_batch"], box_mode=top["box_mode"])
+    return params, results
+
+
+def load_cache(path: str = CACHE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def cached_params(sig: str, path: str = CACHE) -> R.Params | None:
+    entry = load_cache(path).get(sig)
+    if entry is None:
+        return None
+    return R.Params(**{k: entry[k] for k in ("tile_w", "tile_h", "px_per_lane", "lds_batch", "box_mode")})
+
+
+def store(sig: str, params: R.Params, ms: float, path: str = CACHE):
+    cache = load_cache(path)
+    cache[sig] = {"tile_w": params.tile_w, "tile_h": params.tile_h, "px_per_lane": params.px_per_lane,
+                  "lds_batch": params.lds_batch, "box_mode": params.box_mode, "ms": ms}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)

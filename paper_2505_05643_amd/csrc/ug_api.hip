@@ -15,7 +15,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t ctrl, pconst, cnt_rec, off_rec, blk_g, blk_r;
+  size_t ctrl, pconst, pcull, cnt_rec, accbits, off_rec, blk_g, blk_r;
   size_t rec_pair, racc, rgeo, rec_nkey, rec_koff, contrib;
   size_t tile_start, dsave, gq, hist;
   size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, partial;
@@ -64,9 +64,11 @@ void compute_layout(ug_plan* pl) {
   const size_t tpx = (size_t)pl->prm.tile_w * pl->prm.tile_h;
   L.ctrl = take(sizeof(Ctrl));
   L.pconst = take(P * sizeof(PlaneConst));
+  L.pcull = take(P * sizeof(PlaneCull));
   L.cnt_rec = take(n * 4);
+  L.accbits = take(accbits_words(pl->n, pl->p) * 8);
   L.off_rec = take(n * 8);
-  L.blk_g = take((size_t)cull_blocks(pl->n, pl->p) * 4);
+  L.blk_g = take((size_t)cull_blocks(pl->n) * 4);
   L.blk_r = take((size_t)record_blocks(pl->rec_cap) * 4);
   L.rec_pair = take(R * 8);
   L.racc = take(R * sizeof(RecAcc));
@@ -171,13 +173,13 @@ hipError_t enqueue_preprocess(const ug_plan* plan, const ug_gaussians& g, const 
   hipError_t e;
   {
     StageScope sc(plan, UG_STAGE_SETUP, s);
-    e = launch_init(pl, plan->d_pint, at<PlaneConst>(ws, L.pconst), ctrl, s);
+    e = launch_init(pl, plan->d_pint, at<PlaneConst>(ws, L.pconst), at<PlaneCull>(ws, L.pcull), ctrl, s);
   }
   if (e != hipSuccess) return e;
   {
     StageScope sc(plan, UG_STAGE_CULL, s);
-    e = launch_cull(g, at<PlaneConst>(ws, L.pconst), rp, at<uint32_t>(ws, L.cnt_rec),
-                    at<unsigned long long>(ws, L.off_rec), at<uint2>(ws, L.rec_pair), at<uint32_t>(ws, L.blk_g),
+    e = launch_cull(g, at<PlaneCull>(ws, L.pcull), rp, at<uint32_t>(ws, L.cnt_rec),
+                    at<unsigned long long>(ws, L.accbits), at<unsigned long long>(ws, L.off_rec), at<uint2>(ws, L.rec_pair), at<uint32_t>(ws, L.blk_g),
                     ctrl, s);
   }
   if (e != hipSuccess) return e;
@@ -424,6 +426,30 @@ int ug_adam_step(float* param, const float* grad, float* mo, float* ve, int64_t 
   if (count == 0) return UG_OK;
   return hip_status(
       launch_adam(param, grad, mo, ve, count, lr, beta1, beta2, eps, step_t, static_cast<hipStream_t>(stream)));
+}
+
+int ug_adam_gaussians(const ug_plan* plan, const void* workspace, const ug_gaussians_mut* params,
+                      const ug_gaussians_mut* grads, const ug_gaussians_mut* m1, const ug_gaussians_mut* m2,
+                      const ug_adam_params* hp, int32_t* step_dev, void* stream) {
+  if (!params || !grads || !m1 || !m2 || !hp || !step_dev) return UG_ERR_INVALID_ARG;
+  const int32_t n = params->n;
+  if (n < 0 || grads->n != n || m1->n != n || m2->n != n) return UG_ERR_INVALID_ARG;
+  if ((plan == nullptr) != (workspace == nullptr)) return UG_ERR_INVALID_ARG;
+  if (plan && plan->n != n) return UG_ERR_INVALID_ARG;
+  const ug_gaussians_mut* all[4] = {params, grads, m1, m2};
+  for (const ug_gaussians_mut* x : all)
+    if (n > 0 && (!x->means || !x->lraw || !x->intensity || !x->opacity)) return UG_ERR_INVALID_ARG;
+  if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) || !(hp->eps > 0.f) ||
+      !(hp->lr_means > 0.f) || !(hp->lr_means_final > 0.f) || !std::isfinite(hp->lr) || hp->decay_steps < 1)
+    return UG_ERR_INVALID_ARG;
+  if (n == 0) return UG_OK;
+  float* const p[4] = {params->means, params->lraw, params->intensity, params->opacity};
+  const float* const g[4] = {grads->means, grads->lraw, grads->intensity, grads->opacity};
+  float* const m[4] = {m1->means, m1->lraw, m1->intensity, m1->opacity};
+  float* const v[4] = {m2->means, m2->lraw, m2->intensity, m2->opacity};
+  const Ctrl* ctrl = plan ? reinterpret_cast<const Ctrl*>(static_cast<const char*>(workspace) + plan->lay.ctrl)
+                          : nullptr;
+  return hip_status(launch_adam_gaussians(p, g, m, v, n, *hp, step_dev, ctrl, static_cast<hipStream_t>(stream)));
 }
 
 const char* ug_status_string(int status) {

@@ -22,39 +22,70 @@
 
 namespace ug {
 
-struct GaussIn {
-  double mu[3];
-  double l[6];   // raw (l11, l21, l31, l22, l32, l33)
-  double a, c;
-  double L11, L21, L31, L22, L32, L33;
-  double alpha, log2a;
+// Gaussian parameters in scalar type T (double for the record construction,
+// float for its adjoint, whose tolerance is far looser).
+template <typename T>
+struct GaussT {
+  T mu[3];
+  T l[6];  // raw (l11, l21, l31, l22, l32, l33)
+  T a, c;
+  T L11, L21, L31, L22, L32, L33;
+  T iL11, iL22, iL33;  // reciprocals of the diagonal
+  T alpha, log2a;
   bool finite;
 };
+using GaussIn = GaussT<double>;
 
-struct Conic {
-  double m1, m2, m3;
-  double g1[3], g2[3], g3[3];
-  double b1[3], b2[3];
-  double S11, S22, S33, S13, S23;
-  double T11, T12, T22, detL, n3;
-  double c1, c2, r2;
+template <typename T>
+struct ConicT {
+  T m1, m2, m3;
+  T g1[3], g2[3], g3[3];
+  T b1[3], b2[3];
+  T S11, S22, S33, S13, S23;
+  T T11, T12, T22, detL, n3;
+  T c1, c2, r2;
+};
+using Conic = ConicT<double>;
+
+// Plane pose in scalar type T.
+template <typename T>
+struct PlaneT {
+  T o[3], rinv[9], e1[3], e2[3], absdet, sx, sy;
 };
 
-__device__ __forceinline__ void load_gauss(const ug_gaussians& g, int i, double beta, GaussIn& G) {
+template <typename T>
+__device__ __forceinline__ PlaneT<T> plane_as(const PlaneConst& P) {
+  PlaneT<T> q;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    q.o[k] = (T)P.o[k];
+    q.e1[k] = (T)P.e1[k];
+    q.e2[k] = (T)P.e2[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) q.rinv[k] = (T)P.rinv[k];
+  q.absdet = (T)P.absdet;
+  q.sx = (T)P.sx;
+  q.sy = (T)P.sy;
+  return q;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_gauss(const ug_gaussians& g, int i, T beta, GaussT<T>& G) {
   bool fin = true;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    G.mu[k] = (double)g.means[3 * i + k];
-    fin = fin && isfinite_d(G.mu[k]);
+    G.mu[k] = (T)g.means[3 * i + k];
+    fin = fin && __builtin_isfinite(G.mu[k]);
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    G.l[k] = (double)g.lraw[6 * i + k];
-    fin = fin && isfinite_d(G.l[k]);
+    G.l[k] = (T)g.lraw[6 * i + k];
+    fin = fin && __builtin_isfinite(G.l[k]);
   }
-  G.a = (double)g.opacity[i];
-  G.c = (double)g.intensity[i];
-  fin = fin && isfinite_d(G.a) && isfinite_d(G.c);
+  G.a = (T)g.opacity[i];
+  G.c = (T)g.intensity[i];
+  fin = fin && __builtin_isfinite(G.a) && __builtin_isfinite(G.c);
   G.finite = fin;
   // Eq. 11: diagonal entries squared plus beta.
   G.L11 = G.l[0] * G.l[0] + beta;
@@ -63,45 +94,54 @@ __device__ __forceinline__ void load_gauss(const ug_gaussians& g, int i, double 
   G.L22 = G.l[3] * G.l[3] + beta;
   G.L32 = G.l[4];
   G.L33 = G.l[5] * G.l[5] + beta;
+  G.iL11 = (T)1 / G.L11;
+  G.iL22 = (T)1 / G.L22;
+  G.iL33 = (T)1 / G.L33;
   // alpha = sigmoid(a); log2(alpha) = -softplus(-a) / ln 2, stable for any a.
-  const double na = -G.a;
-  const double sp = (na > 0 ? na : 0.0) + log1p(exp(-fabs(na)));
-  G.log2a = -sp / kLn2;
-  G.alpha = 1.0 / (1.0 + exp(na));
+  const T na = -G.a;
+  const T sp = (na > (T)0 ? na : (T)0) + log1p(exp(-fabs(na)));
+  G.log2a = -sp / (T)kLn2;
+  G.alpha = (T)1 / ((T)1 + exp(na));
 }
 
 // Forward substitution y = L^-1 q.
-__device__ __forceinline__ void fsub(const GaussIn& G, double q0, double q1, double q2, double* y) {
-  y[0] = q0 / G.L11;
-  y[1] = (q1 - G.L21 * y[0]) / G.L22;
-  y[2] = (q2 - G.L31 * y[0] - G.L32 * y[1]) / G.L33;
+template <typename T>
+__device__ __forceinline__ void fsub(const GaussT<T>& G, T q0, T q1, T q2, T* y) {
+  y[0] = q0 * G.iL11;
+  y[1] = (q1 - G.L21 * y[0]) * G.iL22;
+  y[2] = (q2 - G.L31 * y[0] - G.L32 * y[1]) * G.iL33;
 }
 
 // Back substitution h = L^-T d.
-__device__ __forceinline__ void bsub(const GaussIn& G, const double* d, double* h) {
-  h[2] = d[2] / G.L33;
-  h[1] = (d[1] - G.L32 * h[2]) / G.L22;
-  h[0] = (d[0] - G.L21 * h[1] - G.L31 * h[2]) / G.L11;
+template <typename T>
+__device__ __forceinline__ void bsub(const GaussT<T>& G, const T* d, T* h) {
+  h[2] = d[2] * G.iL33;
+  h[1] = (d[1] - G.L32 * h[2]) * G.iL22;
+  h[0] = (d[0] - G.L21 * h[1] - G.L31 * h[2]) * G.iL11;
 }
 
 // Phase 1 of Section 4.4: probe coordinates of the mean and the distance of
 // the plane from the ellipsoid.  Returns false if the plane misses the
 // chi^2 ellipsoid (|m3| > sqrt(chi^2 Sigma'_33), i.e. r^2 > chi^2).
-__device__ __forceinline__ bool conic_cull(const GaussIn& G, const PlaneConst& P, double chi2, Conic& k) {
-  const double d0 = G.mu[0] - P.o[0], d1 = G.mu[1] - P.o[1], d2 = G.mu[2] - P.o[2];
-  k.m1 = P.rinv[0] * d0 + P.rinv[1] * d1 + P.rinv[2] * d2;
-  k.m2 = P.rinv[3] * d0 + P.rinv[4] * d1 + P.rinv[5] * d2;
+template <typename T>
+__device__ __forceinline__ bool conic_cull(const GaussT<T>& G, const PlaneT<T>& P, T chi2, ConicT<T>& k) {
+  const T d0 = G.mu[0] - P.o[0], d1 = G.mu[1] - P.o[1], d2 = G.mu[2] - P.o[2];
   k.m3 = P.rinv[6] * d0 + P.rinv[7] * d1 + P.rinv[8] * d2;
   fsub(G, P.rinv[6], P.rinv[7], P.rinv[8], k.g3);
   k.S33 = k.g3[0] * k.g3[0] + k.g3[1] * k.g3[1] + k.g3[2] * k.g3[2];
-  k.r2 = k.m3 * k.m3 / k.S33;
-  return k.r2 <= chi2;  // false for NaN as well
+  return k.m3 * k.m3 <= chi2 * k.S33;  // false for NaN as well
 }
 
 // The rest of the conic, after conic_cull accepted the pair.
-__device__ __forceinline__ void conic_full(const GaussIn& G, const PlaneConst& P, Conic& k) {
+template <typename T>
+__device__ __forceinline__ void conic_full(const GaussT<T>& G, const PlaneT<T>& P, ConicT<T>& k) {
+  const T d0 = G.mu[0] - P.o[0], d1 = G.mu[1] - P.o[1], d2 = G.mu[2] - P.o[2];
+  k.m1 = P.rinv[0] * d0 + P.rinv[1] * d1 + P.rinv[2] * d2;
+  k.m2 = P.rinv[3] * d0 + P.rinv[4] * d1 + P.rinv[5] * d2;
   fsub(G, P.rinv[0], P.rinv[1], P.rinv[2], k.g1);
   fsub(G, P.rinv[3], P.rinv[4], P.rinv[5], k.g2);
+  const T iS = (T)1 / k.S33;
+  k.r2 = k.m3 * k.m3 * iS;
   k.S11 = k.g1[0] * k.g1[0] + k.g1[1] * k.g1[1] + k.g1[2] * k.g1[2];
   k.S22 = k.g2[0] * k.g2[0] + k.g2[1] * k.g2[1] + k.g2[2] * k.g2[2];
   k.S13 = k.g1[0] * k.g3[0] + k.g1[1] * k.g3[1] + k.g1[2] * k.g3[2];
@@ -114,12 +154,13 @@ __device__ __forceinline__ void conic_full(const GaussIn& G, const PlaneConst& P
   k.b2[1] = G.L22 * P.e2[1] + G.L32 * P.e2[2];
   k.b2[2] = G.L33 * P.e2[2];
   k.T11 = sqrt(k.b1[0] * k.b1[0] + k.b1[1] * k.b1[1] + k.b1[2] * k.b1[2]);
-  k.T12 = (k.b1[0] * k.b2[0] + k.b1[1] * k.b2[1] + k.b1[2] * k.b2[2]) / k.T11;
+  const T iT11 = (T)1 / k.T11;
+  k.T12 = (k.b1[0] * k.b2[0] + k.b1[1] * k.b2[1] + k.b1[2] * k.b2[2]) * iT11;
   k.detL = G.L11 * G.L22 * G.L33;
   k.n3 = sqrt(k.S33);
-  k.T22 = k.detL * P.absdet * k.n3 / k.T11;
-  k.c1 = k.m1 - k.m3 * k.S13 / k.S33;
-  k.c2 = k.m2 - k.m3 * k.S23 / k.S33;
+  k.T22 = k.detL * P.absdet * k.n3 * iT11;
+  k.c1 = k.m1 - k.m3 * k.S13 * iS;
+  k.c2 = k.m2 - k.m3 * k.S23 * iS;
 }
 
 __device__ __forceinline__ double cross_norm2(const double* a, const double* b) {
@@ -257,49 +298,51 @@ __device__ __forceinline__ bool make_footprint(const GaussIn& G, const PlaneCons
 // raw parameters, holding the cut-off set fixed.  dr = (dt11, dt12, dt22,
 // dfu, dfv, de0, dc).  Accumulates into dmu[3], dL[6] (L11, L21, L31, L22,
 // L32, L33), da, dc.
-__device__ __forceinline__ void footprint_adjoint(const GaussIn& G, const PlaneConst& P, const Conic& k,
-                                                  const float* dr, double* dmu, double* dL, double& da,
-                                                  double& dc) {
-  const double ks = sqrt(kHalfLog2e);
-  const double dT11 = ks * P.sx * (double)dr[0];
-  const double dT12 = ks * P.sy * (double)dr[1];
-  const double dT22 = ks * P.sy * (double)dr[2];
-  const double dc1 = (double)dr[3] / P.sx;
-  const double dc2 = (double)dr[4] / P.sy;
-  const double de0 = (double)dr[5];
-  dc += (double)dr[6];
+template <typename T>
+__device__ __forceinline__ void footprint_adjoint(const GaussT<T>& G, const PlaneT<T>& P, const ConicT<T>& k,
+                                                  const float* dr, T* dmu, T* dL, T& da, T& dc) {
+  const T ks = (T)0.84932180028801904272;  // sqrt(log2(e) / 2)
+  const T dT11 = ks * P.sx * (T)dr[0];
+  const T dT12 = ks * P.sy * (T)dr[1];
+  const T dT22 = ks * P.sy * (T)dr[2];
+  const T dc1 = (T)dr[3] / P.sx;
+  const T dc2 = (T)dr[4] / P.sy;
+  const T de0 = (T)dr[5];
+  dc += (T)dr[6];
   // e0 = log2(sigmoid(a)) - kHalfLog2e r^2
-  da += de0 * (1.0 - G.alpha) / kLn2;
-  const double dr2 = -kHalfLog2e * de0;
+  da += de0 * ((T)1 - G.alpha) / (T)kLn2;
+  const T dr2 = -(T)kHalfLog2e * de0;
   // T22 = detM n3 / T11, T12 = b1.b2 / T11, T11 = |b1|
-  const double detM = k.detL * P.absdet;
-  const double dT11t = dT11 - dT12 * k.T12 / k.T11 - dT22 * k.T22 / k.T11;
-  const double ddetL = dT22 * P.absdet * k.n3 / k.T11;
-  const double dn3 = dT22 * detM / k.T11;
-  double db1[3], db2[3];
+  const T iT11 = (T)1 / k.T11;
+  const T detM = k.detL * P.absdet;
+  const T dT11t = dT11 - (dT12 * k.T12 + dT22 * k.T22) * iT11;
+  const T ddetL = dT22 * P.absdet * k.n3 * iT11;
+  const T dn3 = dT22 * detM * iT11;
+  T db1[3], db2[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    db1[j] = dT11t * k.b1[j] / k.T11 + dT12 * k.b2[j] / k.T11;
-    db2[j] = dT12 * k.b1[j] / k.T11;
+    db1[j] = (dT11t * k.b1[j] + dT12 * k.b2[j]) * iT11;
+    db2[j] = dT12 * k.b1[j] * iT11;
   }
   // c1 = m1 - m3 S13/S33, c2 = m2 - m3 S23/S33, r2 = m3^2 / S33
-  const double iS = 1.0 / k.S33;
-  double dm[3];
+  const T iS = (T)1 / k.S33;
+  T dm[3];
   dm[0] = dc1;
   dm[1] = dc2;
-  dm[2] = -dc1 * k.S13 * iS - dc2 * k.S23 * iS + dr2 * 2.0 * k.m3 * iS;
-  const double dS13 = -dc1 * k.m3 * iS;
-  const double dS23 = -dc2 * k.m3 * iS;
-  const double dS33 = (dc1 * k.m3 * k.S13 + dc2 * k.m3 * k.S23 - dr2 * k.m3 * k.m3) * iS * iS;
-  double dg1[3], dg2[3], dg3[3];
+  dm[2] = (-dc1 * k.S13 - dc2 * k.S23 + dr2 * (T)2 * k.m3) * iS;
+  const T dS13 = -dc1 * k.m3 * iS;
+  const T dS23 = -dc2 * k.m3 * iS;
+  const T dS33 = (dc1 * k.m3 * k.S13 + dc2 * k.m3 * k.S23 - dr2 * k.m3 * k.m3) * iS * iS;
+  const T in3 = (T)1 / k.n3;
+  T dg1[3], dg2[3], dg3[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     dg1[j] = dS13 * k.g3[j];
     dg2[j] = dS23 * k.g3[j];
-    dg3[j] = dS13 * k.g1[j] + dS23 * k.g2[j] + 2.0 * dS33 * k.g3[j] + dn3 * k.g3[j] / k.n3;
+    dg3[j] = dS13 * k.g1[j] + dS23 * k.g2[j] + (T)2 * dS33 * k.g3[j] + dn3 * k.g3[j] * in3;
   }
   // g = L^-1 q  ->  dL_ij -= h_i g_j with h = L^-T dg (lower triangle)
-  double h[3];
+  T h[3];
   bsub(G, dg1, h);
   dL[0] -= h[0] * k.g1[0]; dL[1] -= h[1] * k.g1[0]; dL[2] -= h[2] * k.g1[0];
   dL[3] -= h[1] * k.g1[1]; dL[4] -= h[2] * k.g1[1]; dL[5] -= h[2] * k.g1[2];

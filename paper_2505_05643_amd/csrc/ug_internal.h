@@ -59,6 +59,16 @@ struct PlaneConst {
   int32_t pad;
 };
 
+// Float copy of what the Phase-1 pre-test needs: origin and the third row
+// of R^-1 (probe-frame normal coordinate m3 = r3 . (mu - o)).
+struct PlaneCull {
+  float o[3];
+  float r3[3];
+  int32_t valid;
+  int32_t pad;
+};
+static_assert(sizeof(PlaneCull) == 32, "PlaneCull layout");
+
 // ---------------------------------------------------------------- records
 // One accepted (Gaussian, plane) pair as the accumulate kernels use it.
 // In pixel-index units, with du = u - (ub + fu), dv = v - (vb + fv):

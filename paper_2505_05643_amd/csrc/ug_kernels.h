@@ -6,13 +6,15 @@
 namespace ug {
 
 // ---- preprocess (ug_preprocess.hip)
-int pair_width(int p);
-uint32_t cull_blocks(int n, int p);
+uint32_t cull_blocks(int n);
 uint32_t record_blocks(uint32_t rec_cap);
-hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, PlaneCull* pcf, Ctrl* ctrl,
+                       hipStream_t s);
 // Phase-1 cull: per-Gaussian record counts and offsets, compact pair list.
-hipError_t launch_cull(const ug_gaussians& g, const PlaneConst* pc, const RenderParams& rp, uint32_t* cnt_rec,
-                       unsigned long long* off_rec, uint2* rec_pair, uint32_t* blk_tot, Ctrl* ctrl, hipStream_t s);
+size_t accbits_words(int n, int p);
+hipError_t launch_cull(const ug_gaussians& g, const PlaneCull* pcf, const RenderParams& rp, uint32_t* cnt_rec,
+                       unsigned long long* accbits, unsigned long long* off_rec, uint2* rec_pair, uint32_t* blk_tot,
+                       Ctrl* ctrl, hipStream_t s);
 // Records (conic + footprint), key offsets and key emission.
 hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
                          const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* rec_koff,
@@ -58,5 +60,8 @@ hipError_t launch_mse(const float* image, const float* target, int64_t m, float*
                       hipStream_t s);
 hipError_t launch_adam(float* param, const float* grad, float* mo, float* ve, int64_t count, float lr, float b1,
                        float b2, float eps, int32_t t, hipStream_t s);
+hipError_t launch_adam_gaussians(float* const p[4], const float* const g[4], float* const m[4], float* const v[4],
+                                 int64_t n, const ug_adam_params& hp, int32_t* step_dev, const Ctrl* ctrl,
+                                 hipStream_t s);
 
 }  // namespace ug

@@ -17,7 +17,8 @@ namespace ug {
 // One thread per plane: FP64 constants of the pose (an invalid pose is marked
 // and skipped; the cull raises the flag).  Thread 0 clears the control block.
 __global__ __launch_bounds__(256) void k_init(ug_planes pl, const PlaneInt* __restrict__ pint,
-                                              PlaneConst* __restrict__ pc, Ctrl* __restrict__ ctrl) {
+                                              PlaneConst* __restrict__ pc, PlaneCull* __restrict__ pcf,
+                                              Ctrl* __restrict__ ctrl) {
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid == 0) {
     ctrl->n_rec = 0;
@@ -68,6 +69,29 @@ __global__ __launch_bounds__(256) void k_init(ug_planes pl, const PlaneInt* __re
   c.valid = fin ? 1 : 0;
   c.pad = 0;
   pc[p] = c;
+  PlaneCull q;
+  for (int k = 0; k < 3; ++k) {
+    q.o[k] = pl.origin[3 * p + k];
+    q.r3[k] = (float)c.rinv[6 + k];
+  }
+  q.valid = c.valid;
+  q.pad = 0;
+  pcf[p] = q;
+}
+
+// Conservative float pre-test of Phase 1: false only if the exact (double)
+// test surely rejects the pair.  The float m3 is off by at most a few ulps of
+// sum |r3_i (mu_i - o_i)|, the float Sigma'_33 by a few ulps relative; the
+// margins below are ten times larger.
+__device__ __forceinline__ bool cull_maybe(const GaussT<float>& G, const PlaneCull& P, float chi2) {
+  const float d0 = G.mu[0] - P.o[0], d1 = G.mu[1] - P.o[1], d2 = G.mu[2] - P.o[2];
+  const float m3 = P.r3[0] * d0 + P.r3[1] * d1 + P.r3[2] * d2;
+  const float slack = 2e-6f * (fabsf(P.r3[0] * d0) + fabsf(P.r3[1] * d1) + fabsf(P.r3[2] * d2));
+  float g3[3];
+  fsub(G, P.r3[0], P.r3[1], P.r3[2], g3);
+  const float S33 = g3[0] * g3[0] + g3[1] * g3[1] + g3[2] * g3[2];
+  const float a = fmaxf(fabsf(m3) - slack, 0.f);
+  return a * a <= chi2 * S33 * 1.0002f;  // false for NaN as well
 }
 
 // ---------------------------------------------------------------- block scan
@@ -106,61 +130,50 @@ __device__ __forceinline__ unsigned long long block_prefix(const uint32_t* __res
 }
 
 // ---------------------------------------------------------------- cull pass
-// Lanes = (Gaussian, plane) pairs.  A wave holds 64 / pw Gaussians, each
-// owning a segment of pw lanes (pw = plane count rounded up to a power of
-// two, at most 64) that walks the Gaussian's planes in chunks of pw; a block
-// covers gpb consecutive Gaussians in rounds of 4 * 64 / pw.  A pair is a
-// record iff the plane meets the Eq. 12 ellipsoid (the Phase-1 test of
-// Eq. 13's box along the normal).
-struct CullLane {
-  int per_wave, seg, pl, gl;
-  unsigned long long segmask;
-};
-
-__device__ __forceinline__ CullLane cull_lane(int pw) {
-  CullLane c;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  c.per_wave = 64 / pw;
-  c.seg = lane / pw;
-  c.pl = lane - c.seg * pw;
-  c.gl = wave * c.per_wave + c.seg;
-  c.segmask = (pw == 64 ? ~0ull : ((1ull << pw) - 1ull)) << (c.seg * pw);
-  return c;
-}
-
-// Counts: per-Gaussian records and the block's total.
-__global__ __launch_bounds__(256) void k_cull_count(ug_gaussians g, const PlaneConst* __restrict__ pc,
-                                                    RenderParams rp, int pw, int gpb, uint32_t* __restrict__ cnt_rec,
+// Lanes = Gaussians; a block covers gpb Gaussians in rounds of 256 and every
+// lane walks all planes in the same order, so the plane data is uniform
+// (scalar loads).  A pair becomes a record iff the conservative float test
+// of Phase 1 (Eq. 13's box along the normal meets the plane, i.e. the plane
+// meets the Eq. 12 ellipsoid) passes; the test only errs towards accepting a
+// pair whose plane narrowly misses the ellipsoid, and such a record has an
+// empty support, so it adds exactly zero everywhere.  Acceptance is kept as
+// one bit per (Gaussian, plane), 64 planes per word.
+__global__ __launch_bounds__(256) void k_cull_count(ug_gaussians g, const PlaneCull* __restrict__ pcf,
+                                                    RenderParams rp, int gpb, uint32_t* __restrict__ cnt_rec,
+                                                    unsigned long long* __restrict__ accbits,
                                                     uint32_t* __restrict__ blk_tot, Ctrl* __restrict__ ctrl) {
   __shared__ uint32_t s_tot;
-  const CullLane L = cull_lane(pw);
   if (threadIdx.x == 0) s_tot = 0;
-  __syncthreads();
-  const double chi2 = (double)rp.chi2;
-  const int round = 4 * L.per_wave;
-  uint32_t mine = 0;
-  for (int r0 = 0; r0 < gpb; r0 += round) {
-    const int gi = blockIdx.x * gpb + r0 + L.gl;
-    const bool has = gi < rp.n;
-    GaussIn G;
-    G.finite = false;
-    if (has) load_gauss(g, gi, (double)rp.beta, G);
-    if (has && !G.finite && L.pl == 0) atomicOr(&ctrl->flags, kFlagNonfinite);
-    uint32_t count = 0;
-    for (int p0 = 0; p0 < rp.p; p0 += pw) {
-      const int p = p0 + L.pl;
-      bool acc = false;
-      if (has && G.finite && p < rp.p) {
-        if (pc[p].valid) {
-          Conic k;
-          acc = conic_cull(G, pc[p], chi2, k);
-        } else if (gi == 0) {
-          atomicOr(&ctrl->flags, kFlagNonfinite);
-        }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int p = 0; p < rp.p; ++p)
+      if (!pcf[p].valid) {
+        atomicOr(&ctrl->flags, kFlagNonfinite);
+        break;
       }
-      count += (uint32_t)__popcll(__ballot(acc) & L.segmask);
+  }
+  __syncthreads();
+  const int nch = (rp.p + 63) / 64;
+  uint32_t mine = 0;
+  for (int r0 = 0; r0 < gpb; r0 += 256) {
+    const int gi = blockIdx.x * gpb + r0 + threadIdx.x;
+    const bool has = gi < rp.n;
+    GaussT<float> G;
+    G.finite = false;
+    if (has) load_gauss<float>(g, gi, rp.beta, G);
+    if (has && !G.finite) atomicOr(&ctrl->flags, kFlagNonfinite);
+    const bool live = has && G.finite;
+    uint32_t count = 0;
+    for (int c = 0; c < nch; ++c) {
+      const int pend = min(64, rp.p - c * 64);
+      unsigned long long bits = 0;
+      for (int j = 0; j < pend; ++j) {
+        const PlaneCull pf = pcf[c * 64 + j];
+        if (live && pf.valid && cull_maybe(G, pf, rp.chi2)) bits |= 1ull << j;
+      }
+      if (has) accbits[(size_t)gi * nch + c] = bits;
+      count += (uint32_t)__popcll(bits);
     }
-    if (has && L.pl == 0) {
+    if (has) {
       cnt_rec[gi] = count;
       mine += count;
     }
@@ -172,55 +185,34 @@ __global__ __launch_bounds__(256) void k_cull_count(ug_gaussians g, const PlaneC
 
 // Offsets and the compact (Gaussian, plane) list, Gaussian-major with planes
 // ascending.  The last block publishes the total and the capacity check.
-__global__ __launch_bounds__(256) void k_cull_write(ug_gaussians g, const PlaneConst* __restrict__ pc,
-                                                    RenderParams rp, int pw, int gpb, uint32_t nblk,
+__global__ __launch_bounds__(256) void k_cull_write(RenderParams rp, int gpb, uint32_t nblk,
                                                     const uint32_t* __restrict__ cnt_rec,
+                                                    const unsigned long long* __restrict__ accbits,
                                                     const uint32_t* __restrict__ blk_tot,
                                                     unsigned long long* __restrict__ off_rec,
                                                     uint2* __restrict__ rec_pair, Ctrl* __restrict__ ctrl) {
   __shared__ unsigned long long s_sh[4];
-  __shared__ uint32_t s_sh32[4];
-  __shared__ uint32_t s_cnt[256];
-  const CullLane L = cull_lane(pw);
   unsigned long long carry = block_prefix(blk_tot, blockIdx.x, s_sh);
-  const double chi2 = (double)rp.chi2;
-  const int round = 4 * L.per_wave;
-  for (int r0 = 0; r0 < gpb; r0 += round) {
-    const int gi = blockIdx.x * gpb + r0 + L.gl;
+  const int nch = (rp.p + 63) / 64;
+  for (int r0 = 0; r0 < gpb; r0 += 256) {
+    const int gi = blockIdx.x * gpb + r0 + threadIdx.x;
     const bool has = gi < rp.n;
-    s_cnt[threadIdx.x] = 0;
-    __syncthreads();
-    if (has && L.pl == 0) s_cnt[L.gl] = cnt_rec[gi];
-    __syncthreads();
-    uint32_t rtot;
-    const uint32_t ex = block_exscan_256<uint32_t>(s_cnt[threadIdx.x], s_sh32, rtot);
-    __syncthreads();
-    s_cnt[threadIdx.x] = ex;
-    __syncthreads();
-    const unsigned long long base = carry + s_cnt[L.gl];
-    carry += rtot;
-    GaussIn G;
-    G.finite = false;
-    if (has) {
-      load_gauss(g, gi, (double)rp.beta, G);
-      if (L.pl == 0) off_rec[gi] = base;
-    }
+    const unsigned long long cnt = has ? cnt_rec[gi] : 0ull;
+    unsigned long long tot;
+    const unsigned long long base = carry + block_exscan_256<unsigned long long>(cnt, s_sh, tot);
+    carry += tot;
+    if (!has) continue;
+    off_rec[gi] = base;
     unsigned long long r = base;
-    for (int p0 = 0; p0 < rp.p; p0 += pw) {
-      const int p = p0 + L.pl;
-      bool acc = false;
-      if (has && G.finite && p < rp.p && pc[p].valid) {
-        Conic k;
-        acc = conic_cull(G, pc[p], chi2, k);
+    for (int c = 0; c < nch; ++c) {
+      unsigned long long bits = accbits[(size_t)gi * nch + c];
+      while (bits) {
+        const int j = __builtin_ctzll(bits);
+        bits &= bits - 1ull;
+        if (r < rp.rec_cap) rec_pair[r] = make_uint2((uint32_t)gi, (uint32_t)(c * 64 + j));
+        ++r;
       }
-      const unsigned long long m = __ballot(acc) & L.segmask;
-      if (acc) {
-        const unsigned long long ri = r + lanemask_lt_popc(m);
-        if (ri < rp.rec_cap) rec_pair[ri] = make_uint2((uint32_t)gi, (uint32_t)p);
-      }
-      r += (unsigned long long)__popcll(m);
     }
-    __syncthreads();
   }
   if (blockIdx.x == nblk - 1 && threadIdx.x == 0) {
     ctrl->n_rec = carry;
@@ -286,9 +278,10 @@ __global__ __launch_bounds__(256) void k_record(ug_gaussians g, const PlaneConst
     GaussIn G;
     load_gauss(g, (int)gp.x, (double)rp.beta, G);
     const PlaneConst& P = pc[gp.y];
+    const PlaneT<double> Pd = plane_as<double>(P);
     Conic k;
-    conic_cull(G, P, chi2, k);
-    conic_full(G, P, k);
+    conic_cull(G, Pd, chi2, k);
+    conic_full(G, Pd, k);
     Footprint f;
     if (!make_footprint(G, P, pint[gp.y], k, chi2, rp.box_mode, rp.tile_w, rp.tile_h, f)) {
       // the plane cuts the ellipsoid outside the image: a record with no keys
@@ -346,8 +339,9 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
 
 // ---------------------------------------------------------------- adjoint
 // One thread per record: sum of its keys' partial derivatives (its keys are
-// contiguous in emission order), then the FP64 chain rule through the record
-// construction; the Gaussian's share is written to contrib[r] (12 floats).
+// contiguous in emission order), then the chain rule through the record
+// construction (in FP32: the adjoint's tolerance is 1e-3, and FP32 keeps the
+// register footprint small); the Gaussian's share goes to contrib[r].
 __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const PlaneConst* __restrict__ pc,
                                                         RenderParams rp, const Ctrl* __restrict__ ctrl,
                                                         const uint2* __restrict__ rec_pair,
@@ -356,7 +350,7 @@ __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const Pl
                                                         float* __restrict__ contrib) {
   const bool ok = (ctrl->flags & (kFlagRecCap | kFlagKeyCap)) == 0;
   const uint32_t nrec = ok ? ctrl->n_rec_eff : 0u;
-  const double chi2 = (double)rp.chi2;
+  const float chi2 = rp.chi2;
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nrec; r += gridDim.x * blockDim.x) {
     const uint32_t k0 = rec_koff[r], k1 = rec_koff[r + 1];
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f), c = a;
@@ -365,14 +359,14 @@ __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const Pl
       a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
       c.x += y.x; c.y += y.y; c.z += y.z; c.w += y.w;
     }
-    double dmu[3] = {0, 0, 0}, dL[6] = {0, 0, 0, 0, 0, 0}, da = 0.0, dc = 0.0;
+    float dmu[3] = {0, 0, 0}, dL[6] = {0, 0, 0, 0, 0, 0}, da = 0.f, dc = 0.f;
     if (k1 > k0) {
       const float dr[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
       const uint2 gp = rec_pair[r];
-      GaussIn G;
-      load_gauss(g, (int)gp.x, (double)rp.beta, G);
-      const PlaneConst& P = pc[gp.y];
-      Conic k;
+      GaussT<float> G;
+      load_gauss<float>(g, (int)gp.x, rp.beta, G);
+      const PlaneT<float> P = plane_as<float>(pc[gp.y]);
+      ConicT<float> k;
       conic_cull(G, P, chi2, k);
       conic_full(G, P, k);
       footprint_adjoint(G, P, k, dr, dmu, dL, da, dc);
@@ -425,22 +419,15 @@ __global__ __launch_bounds__(256) void k_gauss_grad(ug_gaussians g, RenderParams
 // ---------------------------------------------------------------- launchers
 constexpr uint32_t kMaxScanBlocks = 2048;
 
-int pair_width(int p) {
-  int pw = 1;
-  while (pw < p && pw < 64) pw <<= 1;
-  return pw;
-}
-
-// Gaussians per cull block: whole rounds of 4 * 64 / pw, at most 2048 blocks.
-int cull_gpb(int n, int p) {
-  const int round = 4 * (64 / pair_width(p));
-  const long rounds = ((long)n + round - 1) / round;
+// Gaussians per cull block: whole rounds of 256, at most 2048 blocks.
+int cull_gpb(int n) {
+  const long rounds = ((long)n + 255) / 256;
   const long per = (rounds + kMaxScanBlocks - 1) / kMaxScanBlocks;
-  return (int)((per < 1 ? 1 : per) * round);
+  return (int)((per < 1 ? 1 : per) * 256);
 }
 
-uint32_t cull_blocks(int n, int p) {
-  const int gpb = cull_gpb(n, p);
+uint32_t cull_blocks(int n) {
+  const int gpb = cull_gpb(n);
   return (uint32_t)((n + gpb - 1) / gpb);
 }
 
@@ -457,21 +444,23 @@ uint32_t record_blocks(uint32_t rec_cap) {
   return nb < 1 ? 1 : nb;
 }
 
-hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, Ctrl* ctrl, hipStream_t s) {
+hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, PlaneCull* pcf, Ctrl* ctrl,
+                       hipStream_t s) {
   const uint32_t blocks = ((uint32_t)pl.p + 255) / 256;
-  hipLaunchKernelGGL(k_init, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, pl, pint, pc, ctrl);
+  hipLaunchKernelGGL(k_init, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, pl, pint, pc, pcf, ctrl);
   return hipGetLastError();
 }
 
-hipError_t launch_cull(const ug_gaussians& g, const PlaneConst* pc, const RenderParams& rp, uint32_t* cnt_rec,
-                       unsigned long long* off_rec, uint2* rec_pair, uint32_t* blk_tot, Ctrl* ctrl, hipStream_t s) {
-  const uint32_t nb = cull_blocks(rp.n, rp.p);
-  const int pw = pair_width(rp.p), gpb = cull_gpb(rp.n, rp.p);
-  if (nb == 0) {  // no Gaussians: still publish the (zero) record total
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_cull_count, dim3(nb), dim3(256), 0, s, g, pc, rp, pw, gpb, cnt_rec, blk_tot, ctrl);
-  hipLaunchKernelGGL(k_cull_write, dim3(nb), dim3(256), 0, s, g, pc, rp, pw, gpb, nb, cnt_rec, blk_tot, off_rec,
+size_t accbits_words(int n, int p) { return (size_t)n * (size_t)((p + 63) / 64); }
+
+hipError_t launch_cull(const ug_gaussians& g, const PlaneCull* pcf, const RenderParams& rp, uint32_t* cnt_rec,
+                       unsigned long long* accbits, unsigned long long* off_rec, uint2* rec_pair, uint32_t* blk_tot,
+                       Ctrl* ctrl, hipStream_t s) {
+  const uint32_t nb = cull_blocks(rp.n);
+  const int gpb = cull_gpb(rp.n);
+  if (nb == 0) return hipGetLastError();  // no Gaussians: the zeroed totals stand
+  hipLaunchKernelGGL(k_cull_count, dim3(nb), dim3(256), 0, s, g, pcf, rp, gpb, cnt_rec, accbits, blk_tot, ctrl);
+  hipLaunchKernelGGL(k_cull_write, dim3(nb), dim3(256), 0, s, rp, gpb, nb, cnt_rec, accbits, blk_tot, off_rec,
                      rec_pair, ctrl);
   return hipGetLastError();
 }

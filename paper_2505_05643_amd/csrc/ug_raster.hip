@@ -18,6 +18,21 @@ namespace ug {
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
 // ---------------------------------------------------------------- forward
+// Lane layout: each wave owns a sub-tile LW*K pixels wide and 64/LW rows tall
+// (LW = lanes per pixel row, at most 8); a lane owns K pixels of one row,
+// LW apart.  Per staged record a wave first tests the record's bounding box
+// (from its own conic factor) against its sub-tile and then its row bound,
+// and skips the record when either shows no pixel of the wave in support.
+template <int TW, int TH, int K>
+struct FwdLayout {
+  static constexpr int NT = TW * TH / K;
+  static constexpr int LW = (TW / K) < 8 ? (TW / K) : 8;
+  static constexpr int SW = LW * K;  // sub-tile width
+  static constexpr int SH = 64 / LW; // sub-tile height
+  static constexpr int NWX = TW / SW;
+  static_assert(NT % 64 == 0 && TW % SW == 0 && TH % SH == 0 && (TW / SW) * (TH / SH) == NT / 64, "layout");
+};
+
 // CNT: also count the in-support pairs of pixels inside the plane (a
 // measurement variant; the counter costs one VALU op per pair).
 template <int TW, int TH, int K, int BG, bool CNT>
@@ -29,11 +44,11 @@ __global__ __launch_bounds__(TW* TH / K) void k_accum_fwd(const PlaneInt* __rest
                                                           const RecGeo* __restrict__ rgeo, float* __restrict__ image,
                                                           float* __restrict__ dsave, float bg_alpha, float bg_color,
                                                           unsigned long long* __restrict__ n_eval) {
-  constexpr int NT = TW * TH / K;  // threads
-  constexpr int LPR = TW / K;      // lanes per pixel row
-  static_assert(NT % 64 == 0 && LPR * K == TW, "tile shape");
+  using Lay = FwdLayout<TW, TH, K>;
+  constexpr int NT = Lay::NT, LW = Lay::LW, SW = Lay::SW, SH = Lay::SH, NWX = Lay::NWX;
   __shared__ float4 sA[BG];
   __shared__ float4 sB[BG];
+  __shared__ float4 sC[BG];
 
   const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t p = tile_plane[t];
@@ -42,37 +57,75 @@ __global__ __launch_bounds__(TW* TH / K) void k_accum_fwd(const PlaneInt* __rest
   const int tx = (int)(lt % (uint32_t)PI.ntx), ty = (int)(lt / (uint32_t)PI.ntx);
   const int x0 = tx * TW, y0 = ty * TH;
   const int tid = threadIdx.x;
-  const int row = tid / LPR, col0 = tid % LPR;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int sx0 = (wave % NWX) * SW, sy0 = (wave / NWX) * SH;
+  const int row = sy0 + lane / LW, col0 = sx0 + lane % LW;
   const float vrow = (float)row;
+  const float wx_lo = (float)sx0, wx_hi = (float)(sx0 + SW - 1);
+  const float wy_lo = (float)sy0, wy_hi = (float)(sy0 + SH - 1);
   float ucol[K], Nacc[K], Dacc[K];
   uint32_t cnt[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    ucol[k] = (float)(col0 + k * LPR);
+    ucol[k] = (float)(col0 + k * LW);
     Nacc[k] = 0.f;
     Dacc[k] = 0.f;
     cnt[k] = 0u;
   }
   const uint32_t s = tile_start[t], e = tile_start[t + 1];
+  // Records are staged through LDS in batches of BG; the next batch is
+  // fetched into registers while the current one is evaluated.
+  constexpr int PER = (BG + NT - 1) / NT;  // records each thread stages per batch
+  RecAcc pa[PER];
+  RecGeo pg[PER];
+  auto fetch = [&](uint32_t base) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t j = tid + q * NT;
+      if (j < (uint32_t)BG && base + j < e) {
+        const uint32_t r = srec[base + j];
+        pa[q] = racc[r];
+        pg[q] = rgeo[r];
+      }
+    }
+  };
+  if (s < e) fetch(s);
   for (uint32_t base = s; base < e; base += BG) {
     const uint32_t nb = min((uint32_t)BG, e - base);
-    for (uint32_t j = tid; j < nb; j += NT) {
-      const uint32_t r = srec[base + j];
-      const RecAcc A = racc[r];
-      const RecGeo G = rgeo[r];
-      const float du0 = (float)(G.ub - x0) + A.fu;
-      const float dv0 = (float)(G.vb - y0) + A.fv;
-      sA[j] = make_float4(A.t11, A.t12, A.t22, -A.t11 * du0);
-      sB[j] = make_float4(dv0, A.e0, A.emin, A.c);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t j = tid + q * NT;
+      if (j < nb) {
+        const RecAcc& A = pa[q];
+        const float du0 = (float)(pg[q].ub - x0) + A.fu;
+        const float dv0 = (float)(pg[q].vb - y0) + A.fv;
+        sA[j] = make_float4(A.t11, A.t12, A.t22, -A.t11 * du0);
+        sB[j] = make_float4(dv0, A.e0, A.emin, A.c);
+        // bounding box of (t11 du + t12 dv)^2 + (t22 dv)^2 <= e0 - emin,
+        // padded well beyond float rounding (an empty support gives an
+        // inverted box, which every wave skips)
+        const float thr = A.e0 - A.emin;
+        const float sq = sqrtf(fmaxf(thr, 0.f));
+        const float hv = sq / A.t22 * 1.001f + 0.01f;
+        const float hu = sq * sqrtf(A.t12 * A.t12 + A.t22 * A.t22) / (A.t11 * A.t22) * 1.001f + 0.01f;
+        sC[j] = thr >= 0.f ? make_float4(du0 - hu, du0 + hu, dv0 - hv, dv0 + hv)
+                           : make_float4(1.f, -1.f, 1.f, -1.f);
+      }
     }
     __syncthreads();
+    if (base + BG < e) fetch(base + BG);
     for (uint32_t j = 0; j < nb; ++j) {
+      const float4 bb = sC[j];
+      if (bb.x > wx_hi || bb.y < wx_lo || bb.z > wy_hi || bb.w < wy_lo) continue;  // uniform
       const float4 a = sA[j];
       const float4 b = sB[j];
       const float dv = vrow - b.x;
-      const float B = fmaf(a.y, dv, a.w);
       const float t2 = a.z * dv;
       const float erow = fmaf(-t2, t2, b.y);
+      // e <= erow on the whole pixel row: skip when no lane's row reaches
+      // the support (wave-uniform branch).
+      if (!__any(erow >= b.z)) continue;
+      const float B = fmaf(a.y, dv, a.w);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const float t1 = fmaf(a.x, ucol[k], B);
@@ -91,7 +144,7 @@ __global__ __launch_bounds__(TW* TH / K) void k_accum_fwd(const PlaneInt* __rest
     uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int u = x0 + col0 + k * LPR;
+      const int u = x0 + col0 + k * LW;
       if (u < PI.W) {
         const float Dt = Dacc[k] + bg_alpha;
         image[rowbase + u] = (Nacc[k] + bg_alpha * bg_color) / Dt;

@@ -34,17 +34,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Ctrl* __restr
 }
 
 // One block per digit d: exclusive scan of column d over the G blocks
-// (in place), and the column total coltot[d].  G <= 1024.
+// (in place), and the column total coltot[d].  G <= 4096.
+constexpr int kColPer = 16;
 __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ cnt, uint32_t G,
                                                        uint32_t* __restrict__ coltot) {
   __shared__ uint32_t sh[4];
   const uint32_t d = blockIdx.x, t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  uint32_t v[4];
+  uint32_t v[kColPer];
   uint32_t sum = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t b = 4 * t + j;
+  for (int j = 0; j < kColPer; ++j) {
+    const uint32_t b = kColPer * t + j;
     v[j] = b < G ? cnt[(size_t)b * 256 + d] : 0u;
     sum += v[j];
   }
@@ -64,25 +65,33 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ cn
   }
   uint32_t run = before + x - sum;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t b = 4 * t + j;
+  for (int j = 0; j < kColPer; ++j) {
+    const uint32_t b = kColPer * t + j;
     if (b < G) cnt[(size_t)b * 256 + d] = run;
     run += v[j];
   }
   if (t == 0) coltot[d] = total;
 }
 
-// Stable scatter.  The chunk is walked in rounds of 256 consecutive keys;
-// within a wave, lanes holding the same digit are found with eight ballots
-// and ranked by lane order; waves are ordered through LDS.  The digit bases
-// come from an exclusive scan of the column totals.
+// Stable scatter.  The block's chunk is walked in rounds of 2048 keys (8
+// sub-rounds of 256).  Ranks: inside a wave, lanes holding the same digit
+// are found with eight ballots; waves and sub-rounds are ordered through
+// LDS counters.  The round is then reordered by digit in LDS and written out
+// as contiguous runs per digit, so the global writes coalesce.
+constexpr int kItems = 8;
+constexpr int kRound = kSortThreads * kItems;
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ cnt,
     const uint32_t* __restrict__ coltot, uint32_t G, int shift, const uint32_t* __restrict__ rec_of_key,
     uint32_t* __restrict__ srec) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t s_key[kRound];
+  __shared__ uint32_t s_val[kRound];
+  __shared__ uint32_t run[256];      // global output position of the next key of each digit
+  __shared__ uint32_t cum[256];      // keys of each digit seen so far in this round
+  __shared__ uint32_t loc[256];      // first LDS slot of each digit in this round
+  __shared__ uint32_t wcnt[4][256];  // per-wave digit counts of one sub-round
   __shared__ uint32_t sh[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t s, e;
@@ -100,35 +109,75 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     uint32_t before = 0;
     for (int w = 0; w < wave; ++w) before += sh[w];
     run[tid] = before + x - tot + cnt[(size_t)blockIdx.x * 256 + tid];
+    cum[tid] = 0;
   }
-  for (uint32_t base = s; base < e; base += kSortThreads) {
-    for (int j = tid; j < 1024; j += kSortThreads) (&wcnt[0][0])[j] = 0u;
-    __syncthreads();
-    const uint32_t i = base + tid;
-    const bool valid = i < e;
-    const uint32_t k = valid ? kin[i] : 0u;
-    const uint32_t v = valid ? (vin ? vin[i] : i) : 0u;
-    const uint32_t d = (k >> shift) & 255u;
-    unsigned long long peers = __ballot(valid);
+  for (uint32_t base = s; base < e; base += kRound) {
+    uint32_t kk[kItems], vv[kItems], rr[kItems];
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      const bool on = (d >> bit) & 1u;
-      const unsigned long long bm = __ballot(on);
-      peers &= on ? bm : ~bm;
-    }
-    const uint32_t rank = lanemask_lt_popc(peers);
-    if (valid && (peers >> lane) == 1ull) wcnt[wave][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
+    for (int it = 0; it < kItems; ++it) {
+      for (int j = tid; j < 1024; j += kSortThreads) (&wcnt[0][0])[j] = 0u;
+      __syncthreads();
+      const uint32_t i = base + it * kSortThreads + tid;
+      const bool valid = i < e;
+      const uint32_t k = valid ? kin[i] : 0u;
+      const uint32_t v = valid ? (vin ? vin[i] : i) : 0u;
+      const uint32_t d = (k >> shift) & 255u;
+      unsigned long long peers = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const unsigned long long bm = __ballot(on);
+        peers &= on ? bm : ~bm;
+      }
+      const uint32_t rank = lanemask_lt_popc(peers);
+      if (valid && (peers >> lane) == 1ull) wcnt[wave][d] = (uint32_t)__popcll(peers);
+      __syncthreads();
       uint32_t pre = 0;
       for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
-      const uint32_t pos = run[d] + pre + rank;
+      kk[it] = k;
+      vv[it] = v;
+      rr[it] = valid ? cum[d] + pre + rank : 0xffffffffu;
+      __syncthreads();
+      cum[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+      __syncthreads();  // wcnt is cleared again at the top of the next sub-round
+    }
+    // digit offsets inside the round
+    {
+      const uint32_t c = cum[tid];
+      uint32_t x = c;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (lane == 63) sh[wave] = x;
+      __syncthreads();
+      uint32_t before = 0;
+      for (int w = 0; w < wave; ++w) before += sh[w];
+      loc[tid] = before + x - c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      if (rr[it] != 0xffffffffu) {
+        const uint32_t slot = loc[(kk[it] >> shift) & 255u] + rr[it];
+        s_key[slot] = kk[it];
+        s_val[slot] = vv[it];
+      }
+    }
+    __syncthreads();
+    const uint32_t n_round = min((uint32_t)kRound, e - base);
+    for (uint32_t i = tid; i < n_round; i += kSortThreads) {
+      const uint32_t k = s_key[i], v = s_val[i];
+      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t pos = run[d] + (i - loc[d]);
       kout[pos] = k;
       vout[pos] = v;
       if (srec) srec[pos] = rec_of_key[v];
     }
     __syncthreads();
-    run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+    run[tid] += cum[tid];
+    cum[tid] = 0;
     __syncthreads();
   }
 }
@@ -155,7 +204,7 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const Ctrl* __restrict__ ct
 uint32_t sort_blocks_for(uint32_t key_cap) {
   uint32_t g = (key_cap + 2047u) / 2048u;
   if (g < 1) g = 1;
-  if (g > 1024) g = 1024;
+  if (g > 4096) g = 4096;
   return g;
 }
 

@@ -55,6 +55,73 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
   }
 }
 
+// Adam over the concatenation [means | lraw | intensity | opacity] (11 n
+// floats); the step number comes from device memory.
+struct AdamPtrs {
+  float* p[4];
+  const float* g[4];
+  float* m[4];
+  float* v[4];
+};
+
+__global__ __launch_bounds__(256) void k_adam_gaussians(AdamPtrs A, int64_t n, ug_adam_params hp,
+                                                        const int32_t* __restrict__ step_dev,
+                                                        const Ctrl* __restrict__ ctrl) {
+  if (ctrl && (ctrl->flags & (kFlagRecCap | kFlagKeyCap))) return;
+  const int t = *step_dev + 1;
+  const float c1 = 1.f / (1.f - powf(hp.beta1, (float)t));
+  const float c2 = 1.f / (1.f - powf(hp.beta2, (float)t));
+  const float frac = fminf((float)(t - 1) / (float)hp.decay_steps, 1.f);
+  const float lr_mu = hp.lr_means * powf(hp.lr_means_final / hp.lr_means, frac);
+  const int64_t total = 11 * n;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    int seg;
+    int64_t j;
+    if (i < 3 * n) {
+      seg = 0;
+      j = i;
+    } else if (i < 9 * n) {
+      seg = 1;
+      j = i - 3 * n;
+    } else if (i < 10 * n) {
+      seg = 2;
+      j = i - 9 * n;
+    } else {
+      seg = 3;
+      j = i - 10 * n;
+    }
+    const float lr = seg == 0 ? lr_mu : hp.lr;
+    const float gi = A.g[seg][j];
+    const float m = fmaf(hp.beta1, A.m[seg][j], (1.f - hp.beta1) * gi);
+    const float v = fmaf(hp.beta2, A.v[seg][j], (1.f - hp.beta2) * gi * gi);
+    A.m[seg][j] = m;
+    A.v[seg][j] = v;
+    A.p[seg][j] -= lr * (m * c1) / (sqrtf(v * c2) + hp.eps);
+  }
+}
+
+__global__ void k_step_increment(int32_t* __restrict__ step_dev, const Ctrl* __restrict__ ctrl) {
+  if (ctrl && (ctrl->flags & (kFlagRecCap | kFlagKeyCap))) return;
+  *step_dev += 1;
+}
+
+hipError_t launch_adam_gaussians(float* const p[4], const float* const g[4], float* const m[4], float* const v[4],
+                                 int64_t n, const ug_adam_params& hp, int32_t* step_dev, const Ctrl* ctrl,
+                                 hipStream_t s) {
+  AdamPtrs A;
+  for (int k = 0; k < 4; ++k) {
+    A.p[k] = p[k];
+    A.g[k] = g[k];
+    A.m[k] = m[k];
+    A.v[k] = v[k];
+  }
+  const int64_t want = (11 * n + 255) / 256;
+  const int blocks = (int)(want < 1 ? 1 : (want > 8192 ? 8192 : want));
+  hipLaunchKernelGGL(k_adam_gaussians, dim3(blocks), dim3(256), 0, s, A, n, hp, step_dev, ctrl);
+  hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(1), 0, s, step_dev, ctrl);
+  return hipGetLastError();
+}
+
 hipError_t launch_mse(const float* image, const float* target, int64_t m, float* d_image, float* loss,
                       hipStream_t s) {
   int64_t want = (m + 4095) / 4096;

@@ -1,0 +1,131 @@
+"""One training step of the Gaussians (render, MSE, adjoint, Adam) as a hipGraph.
+
+The whole step is enqueued on one stream with no host synchronisation and
+no allocation, so it is captured once with ``torch.cuda.CUDAGraph`` and
+replayed.  The Adam step counter lives in device memory and the Adam kernel
+skips itself when the render overflowed its capacity; ``run`` checks the
+status every ``check_every`` steps and, on an overflow, re-sizes the plan,
+captures again and redoes the step.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib
+from ._lib import lib, check
+from . import raster as R
+
+
+@dataclasses.dataclass
+class AdamConfig:
+    """Section 4.5: Adam, lr 0.05 for all parameters but the means, which
+    start at 1.6e-4 and decay exponentially (final value: 1% of the start,
+    an assumption; the paper does not give it)."""
+    lr_means: float = 1.6e-4
+    lr_means_final: float = 1.6e-6
+    decay_steps: int = 2000
+    lr: float = 0.05
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    def to_c(self) -> _lib.UgAdamParams:
+        return _lib.UgAdamParams(self.lr_means, self.lr_means_final, self.decay_steps, self.lr, self.beta1,
+                                 self.beta2, self.eps)
+
+
+def _mut(g: R.GaussianTensors) -> _lib.UgGaussiansMut:
+    return _lib.UgGaussiansMut(g.means.data_ptr(), g.lraw.data_ptr(), g.intensity.data_ptr(),
+                               g.opacity.data_ptr(), g.means.shape[0])
+
+
+def adam_gaussians(params: R.GaussianTensors, grads: R.GaussianTensors, m1: R.GaussianTensors,
+                   m2: R.GaussianTensors, cfg: AdamConfig, step_dev: torch.Tensor, plan: R.Plan | None = None):
+    """One Adam step over the four tensors (step number read on the device)."""
+    hp = cfg.to_c()
+    a, b, c, d = _mut(params), _mut(grads), _mut(m1), _mut(m2)
+    check(lib.ug_adam_gaussians(plan._h if plan is not None else None,
+                                plan._ws_ptr if plan is not None else None,
+                                ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                                ctypes.byref(hp), step_dev.data_ptr(), R._stream()), "ug_adam_gaussians")
+
+
+class TrainStep:
+    """Fits the Gaussians ``params`` (updated in place) to ``target`` images on
+    the planes ``planes`` (both device tensors whose storage stays fixed; new
+    poses or targets can be copied into them between steps)."""
+
+    def __init__(self, params: R.GaussianTensors, planes: R.PlaneTensors, wh, target: torch.Tensor,
+                 render_params: R.Params | None = None, adam: AdamConfig | None = None, headroom: float = 1.5):
+        self.params = params
+        self.planes = planes
+        self.target = target
+        self.adam = adam or AdamConfig()
+        self.headroom = headroom
+        dev = params.means.device
+        self.plan = R.Plan(params.means.shape[0], wh, render_params, device=dev)
+        self.plan.fit(params, planes, headroom)
+        z = lambda t: torch.zeros_like(t)  # noqa: E731
+        self.grads = R.GaussianTensors(*(z(t) for t in params))
+        self.m1 = R.GaussianTensors(*(z(t) for t in params))
+        self.m2 = R.GaussianTensors(*(z(t) for t in params))
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.image = torch.empty(self.plan.num_pixels, device=dev)
+        self.d_image = torch.empty_like(self.image)
+        self.loss_buf = torch.zeros(_lib.UG_MSE_SCRATCH_FLOATS, device=dev)
+        self.graph = None
+
+    # ---------------------------------------------------------------- eager
+    def enqueue(self):
+        """Enqueue one step on the current stream (no synchronisation)."""
+        self.plan.render(self.params, self.planes, self.image, check_status=False)
+        R.mse_grad(self.image, self.target, self.d_image, self.loss_buf)
+        self.plan.backward(self.params, self.planes, self.image, self.d_image, self.grads)
+        adam_gaussians(self.params, self.grads, self.m1, self.m2, self.adam, self.step_dev, self.plan)
+
+    # ---------------------------------------------------------------- graph
+    def capture(self):
+        """Capture one step as a hipGraph (the capture itself runs no step)."""
+        self.graph = None
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.enqueue()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+
+    # ---------------------------------------------------------------- driver
+    def run(self, steps: int, use_graph: bool = True, check_every: int = 1):
+        """Runs ``steps`` steps; returns the list of losses read at each check."""
+        losses = []
+        start = self.step_count
+        done = 0
+        while done < steps:
+            (self.replay if use_graph else self.enqueue)()
+            done += 1
+            if done % check_every == 0 or done == steps:
+                code = self.plan.status()
+                if code == _lib.UG_ERR_CAPACITY:
+                    # every Adam launch since the overflow skipped itself and
+                    # left the device step counter alone: re-size, re-capture
+                    # and redo the steps that did not happen
+                    self.plan.fit(self.params, self.planes, self.headroom)
+                    self.graph = None
+                    done = self.step_count - start
+                    continue
+                if code not in (_lib.UG_OK, _lib.UG_ERR_NONFINITE):
+                    check(code, "train step")
+                losses.append(float(self.loss_buf[0]))
+        return losses
+
+    @property
+    def step_count(self) -> int:
+        return int(self.step_dev.item())

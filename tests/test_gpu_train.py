@@ -1,0 +1,116 @@
+"""Training step: the device-step Adam against a float64 reference of the
+update rule, hipGraph replay against eager steps, the overflow guard, and a
+short fit."""
+import numpy as np
+import pytest
+
+from paper_2505_05643_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_05643_amd import raster, step
+    return raster, step
+
+
+def _adam_ref(p, g_seq, cfg, seg_lr):
+    """Adam in float64 for a list of gradients; seg_lr(t) -> learning rate."""
+    p = p.astype(np.float64).copy()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t, g in enumerate(g_seq, start=1):
+        g = g.astype(np.float64)
+        m = cfg.beta1 * m + (1 - cfg.beta1) * g
+        v = cfg.beta2 * v + (1 - cfg.beta2) * g * g
+        mh = m / (1 - cfg.beta1 ** t)
+        vh = v / (1 - cfg.beta2 ** t)
+        p -= seg_lr(t) * mh / (np.sqrt(vh) + cfg.eps)
+    return p
+
+
+def test_adam_gaussians_matches_reference(M):
+    R, S = M
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(0)
+    n = 777
+    cfg = S.AdamConfig(lr_means=1e-2, lr_means_final=1e-4, decay_steps=4, lr=0.05)
+    p0 = [rng.standard_normal((n, 3)), rng.standard_normal((n, 6)), rng.random(n), rng.standard_normal(n)]
+    params = R.GaussianTensors(*(torch.tensor(x, dtype=torch.float32, device=dev) for x in p0))
+    z = lambda t: torch.zeros_like(t)  # noqa: E731
+    m1 = R.GaussianTensors(*(z(t) for t in params))
+    m2 = R.GaussianTensors(*(z(t) for t in params))
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    gseq = []
+    for _ in range(6):
+        gs = [rng.standard_normal(x.shape).astype(np.float32) for x in p0]
+        gseq.append(gs)
+        grads = R.GaussianTensors(*(torch.tensor(x, device=dev) for x in gs))
+        S.adam_gaussians(params, grads, m1, m2, cfg, step)
+    torch.cuda.synchronize()
+    assert int(step.item()) == 6
+    lr_mu = lambda t: cfg.lr_means * (cfg.lr_means_final / cfg.lr_means) ** min((t - 1) / cfg.decay_steps, 1.0)  # noqa: E731
+    for k in range(4):
+        ref = _adam_ref(p0[k].astype(np.float32), [gs[k] for gs in gseq], cfg,
+                        lr_mu if k == 0 else (lambda t: cfg.lr))
+        got = params[k].cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-6)
+
+
+def _problem(R, n=300, seed=81):
+    g = synth.make_gaussians(n, seed, (0, 0, 0), (1, 1, 1), (0.03, 0.12), opacity="random")
+    t = synth.make_gaussians(n, seed + 1, (0, 0, 0), (1, 1, 1), (0.03, 0.12))
+    pl = synth.random_planes(4, seed + 2, (48, 40), 1 / 40, 0.35, 0.65)
+    dev = torch.device("cuda", 0)
+    gt, pt, tt = R.to_device(g, dev), R.to_device(pl, dev), R.to_device(t, dev)
+    tplan = R.Plan(t.n, pl.wh, device=dev)
+    tplan.fit(tt, pt)
+    target = tplan.render(tt, pt).clone()
+    return gt, pt, pl.wh, target
+
+
+def test_graph_replay_equals_eager_steps(M):
+    R, S = M
+    gt, pt, wh, target = _problem(R)
+    a = R.GaussianTensors(*(x.clone() for x in gt))
+    b = R.GaussianTensors(*(x.clone() for x in gt))
+    ea = S.TrainStep(a, pt, wh, target)
+    eb = S.TrainStep(b, pt, wh, target)
+    la = ea.run(8, use_graph=False)
+    lb = eb.run(8, use_graph=True)
+    torch.cuda.synchronize()
+    assert ea.step_count == eb.step_count == 8
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert la == lb
+
+
+def test_training_reduces_loss(M):
+    R, S = M
+    gt, pt, wh, target = _problem(R, seed=91)
+    st = S.TrainStep(gt, pt, wh, target, adam=S.AdamConfig(lr_means=2e-3, lr_means_final=2e-4, decay_steps=60,
+                                                            lr=0.02))
+    losses = st.run(60, use_graph=True, check_every=10)
+    assert losses[-1] < 0.7 * losses[0], losses
+
+
+def test_overflow_skips_update_and_run_recovers(M):
+    R, S = M
+    gt, pt, wh, target = _problem(R, seed=95)
+    st = S.TrainStep(gt, pt, wh, target)
+    st.run(2, use_graph=True)
+    before = [x.clone() for x in st.params]
+    st.plan.reserve(4, 8)          # far too small for this scene
+    st.graph = None
+    st.replay()
+    torch.cuda.synchronize()
+    assert st.plan.status() == R._lib.UG_ERR_CAPACITY
+    assert st.step_count == 2      # the Adam launch skipped itself
+    for x, y in zip(before, st.params):
+        assert torch.equal(x, y)
+    st.run(3, use_graph=True)      # re-sizes, re-captures, redoes the step
+    assert st.step_count == 5
