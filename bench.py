@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--cpu-px", type=int, default=640)
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch configuration")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="finish with 5 device-to-device copies of MIB MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU (plane-sharded) path is a design, "
@@ -109,7 +111,7 @@ def main():
         from paper_2505_05643_amd import autotune
         params, results = autotune.tune(gd, pd, pl.wh, steps=3)
         default = next((r for r in results if (r["tile_w"], r["tile_h"], r["px_per_lane"], r["lds_batch"],
-                                               r["box_mode"]) == (16, 16, 1, 64, 0)), None)
+                                               r["box_mode"]) == (16, 16, 2, 64, 0)), None)
         best = min(results, key=lambda r: r["ms"])
         tuned = {"candidates": len(results), "best_ms": best["ms"],
                  "default_16x16_paper_ms": default["ms"] if default else None}
@@ -148,7 +150,7 @@ def main():
     assert code == 0, f"render status {code}"
 
     # ---- timed region (per-stage events on the launch stream) ----
-    plan.profile_begin(max_launches=args.steps * 12 + 16)
+    plan.profile_begin(max_launches=args.steps * 32 + 16)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -194,7 +196,7 @@ def main():
     cplan = R.Plan(g.n, pl.wh, cparams, device=dev)
     cplan.fit(gd, pd)
     cimg = cplan.render(gd, pd)
-    _, _, _, n_eval = cplan.status(counts=True)
+    _, _, _, n_eval, n_exec = cplan.status(counts=True)
     assert torch.equal(cimg, image), "counting variant must render the same image"
     del cplan
     tpx = params.tile_w * params.tile_h
@@ -249,30 +251,31 @@ def main():
                  "batched_speedup": pms / ms_step}
         del per
 
-    # ---- roofline of the dominant kernel ----
-    dom = max(stages.items(), key=lambda kv: kv[1][0])
-    dom_name, (dom_ms, dom_n) = dom
-    avg_ms = dom_ms / max(dom_n, 1)
-    if dom_name in FLOPS_PER_PAIR:
-        ach = n_eval * FLOPS_PER_PAIR[dom_name] / (avg_ms / 1e3) / 1e12
-        roof = {"bound": "alu", "kernel": dom_name, "achieved": ach, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / ALU_PEAK_TFLOPS, "traffic": None,
-                "work": f"{FLOPS_PER_PAIR[dom_name]} flop x {n_eval} in-support pairs per launch",
-                "avg_launch_ms": avg_ms}
-    else:
-        nbytes = {"sort": n_key * 20 * ((plan_bits(plan) + 7) // 8), "cull": g.n * 44 + n_rec * 8,
-                  "record": n_rec * 60 + n_key * 8}.get(dom_name, 0)
-        ach = nbytes / (avg_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom_name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg_ms}
-    # the accumulate kernels are reported either way
-    acc = {}
-    for nm in ("accum", "accum_bwd"):
-        if nm in stages:
-            ms, n = stages[nm]
-            a = n_eval * FLOPS_PER_PAIR[nm] / (ms / n / 1e3) / 1e12
-            acc[nm] = {"avg_launch_ms": ms / n, "tflops": a, "frac": a / ALU_PEAK_TFLOPS,
-                       "executed_pairs_per_launch": n_key * tpx}
+    # ---- roofline of every kernel; the dominant one is the headline ----
+    sizes = dict(n=g.n, p=pl.p, r=n_rec, k=n_key, t=plan.num_tiles, m=int(pl.npix),
+                 passes=(plan_bits(plan) + 7) // 8, w=(pl.p + 63) // 64, rows=params.box_mode == 2,
+                 g_sort=min(4096, max(1, (plan.key_capacity + 2047) // 2048)))
+    kernels = {}
+    for nm, (ms, n) in stages.items():
+        avg = ms / max(n, 1)
+        row = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps, "avg_launch_ms": avg}
+        if nm in FLOPS_PER_PAIR:
+            ach = n_eval * FLOPS_PER_PAIR[nm] / (avg / 1e3) / 1e12
+            row.update(bound="alu", achieved=ach, peak=ALU_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / ALU_PEAK_TFLOPS,
+                       work=f"{FLOPS_PER_PAIR[nm]} flop x {n_eval} in-support pairs per launch",
+                       evaluated_pairs=n_exec)
+        else:
+            nbytes = kernel_bytes(nm, **sizes)
+            ach = nbytes / (avg / 1e3) / 1e9
+            row.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                       work=f"{nbytes} algorithmic bytes per launch")
+        kernels[nm] = row
+    dom_name = max(kernels, key=lambda nm: kernels[nm]["ms_per_step"])
+    d = kernels[dom_name]
+    roof = {"bound": d["bound"], "kernel": dom_name, "achieved": d["achieved"], "peak": d["peak"],
+            "unit": d["unit"], "frac": d["frac"], "traffic": stored_traffic(dom_name, k, params, plan),
+            "work": d["work"], "avg_launch_ms": d["avg_launch_ms"]}
+    acc = {nm: kernels[nm] for nm in ("accum", "accum_bwd") if nm in kernels}
 
     out = {
         "metric": METRIC,
@@ -299,10 +302,12 @@ def main():
         "in_support_pairs": n_eval,
         "records": n_rec,
         "keys": n_key,
+        "evaluated_pairs": n_exec,
         "tile_efficiency": n_eval / max(n_key * tpx, 1),
+        "subblock_efficiency": n_eval / max(n_exec, 1),
         "plain_per_plane": plain,
-        "stage_ms_per_step": {nm: v[0] / args.steps for nm, v in stages.items()},
         "accumulate_kernels": acc,
+        "kernels": kernels,
         "roofline": roof,
     }
 
@@ -321,17 +326,85 @@ def main():
         out["parity_sample_max_rel"] = float(np.abs(gpu_vals - ref).max() / max(np.abs(ref).max(), 1e-30))
     print(json.dumps(out), flush=True)
 
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe << 18, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
 
 def plan_bits(plan) -> int:
     t = max(plan.num_tiles, 2)
     return int(np.ceil(np.log2(t)))
 
 
+def kernel_bytes(name, n, p, r, k, t, m, passes, w, rows, g_sort) -> int:
+    """Algorithmic HBM bytes of one launch of an HBM-bound kernel: what the
+    kernel must read and write once (N Gaussians, R records, K keys, T tiles,
+    M pixels; W = 64-plane words per Gaussian; a sort pass moves the keys
+    and their indices once; the last pass also gathers the record ids)."""
+    if name == "setup":
+        return p * (56 + 160)
+    if name == "cull_count":
+        return 36 * n + 8 * n * w + 4 * n
+    if name == "cull_write":
+        return 4 * n + 8 * n * w + 8 * n + 8 * r
+    if name == "record":
+        return 8 * r + 44 * n + 52 * r
+    if name == "emit":
+        return 4 * r + 16 * r + (32 * r if rows else 0) + 4 * r + 8 * k
+    if name == "sort_hist":
+        return 4 * k
+    if name == "sort_scan":
+        return 8 * 256 * g_sort
+    if name == "sort_scatter":
+        total = 4 * k + 8 * k + (passes - 1) * 16 * k + 8 * k
+        return total // max(passes, 1)
+    if name == "ranges":
+        return 4 * k + 4 * t
+    if name == "bwd_prep":
+        return 20 * m
+    if name == "record_adj":
+        return 12 * r + 32 * k + 44 * n + 48 * r
+    if name == "gauss_grad":
+        return 12 * n + 48 * r + 44 * n
+    return 0
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def stored_traffic(kernel, k, params, plan):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), if they were
+    taken on this workload and launch configuration with the current kernel
+    sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    key = f"c{k}:{kernel}:{params.tile_w}x{params.tile_h}x{plan_ppl(params)}:{params.lds_batch}:{params.box_mode}"
+    ent = rec.get(key)
+    if not ent or ent.get("sources") != sources_digest():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2505_05643_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, fn), "rb") as f:
+                h.update(fn.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def plan_ppl(params) -> int:
-    if params.px_per_lane:
-        return params.px_per_lane
-    px = params.tile_w * params.tile_h
-    return px // 256 if px >= 512 else 1
+    return params.px_per_lane or params.tile_w // 8
 
 
 if __name__ == "__main__":

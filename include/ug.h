@@ -57,17 +57,21 @@ extern "C" {
 #define UG_FLAG_COUNT_EVALS 1 /* forward also counts in-support (Gaussian, pixel) pairs */
 
 /* ---- pipeline stages (measurement hooks) ------------------------------- */
-#define UG_STAGE_SETUP 0      /* plane pose set-up                                 */
-#define UG_STAGE_CULL 1       /* Phase-1 cull and record compaction (Sec. 4.4)     */
-#define UG_STAGE_RECORD 2     /* in-plane conic, key offsets, key emission          */
-#define UG_STAGE_SORT 3       /* radix sort of the keys by tile (all passes)        */
-#define UG_STAGE_RANGES 4     /* per-tile key ranges                                */
-#define UG_STAGE_ACCUM 5      /* per-tile accumulation, Eq. 5-8 and 12              */
-#define UG_STAGE_BWD_PREP 6   /* per-pixel adjoint inputs                           */
-#define UG_STAGE_ACCUM_BWD 7  /* per-key adjoint of the accumulation                */
-#define UG_STAGE_RECORD_ADJ 8 /* per-record adjoint of the conic construction       */
-#define UG_STAGE_GAUSS_GRAD 9 /* per-Gaussian sum of its records' adjoints          */
-#define UG_NUM_STAGES 10
+#define UG_STAGE_SETUP 0         /* plane pose set-up                                  */
+#define UG_STAGE_CULL_COUNT 1    /* Phase-1 cull (Sec. 4.4): acceptance bits, counts    */
+#define UG_STAGE_CULL_WRITE 2    /* record offsets and the compact pair list            */
+#define UG_STAGE_RECORD 3        /* in-plane conic, footprint, per-record key counts    */
+#define UG_STAGE_EMIT 4          /* key offsets and key emission                        */
+#define UG_STAGE_SORT_HIST 5     /* radix sort: digit histograms (once per pass)        */
+#define UG_STAGE_SORT_SCAN 6     /* radix sort: histogram column scan (once per pass)   */
+#define UG_STAGE_SORT_SCATTER 7  /* radix sort: stable scatter (once per pass)          */
+#define UG_STAGE_RANGES 8        /* per-tile key ranges                                 */
+#define UG_STAGE_ACCUM 9         /* per-tile accumulation, Eq. 5-8 and 12               */
+#define UG_STAGE_BWD_PREP 10     /* per-pixel adjoint inputs                            */
+#define UG_STAGE_ACCUM_BWD 11    /* per-key adjoint of the accumulation                 */
+#define UG_STAGE_RECORD_ADJ 12   /* per-record adjoint of the conic construction        */
+#define UG_STAGE_GAUSS_GRAD 13   /* per-Gaussian sum of its records' adjoints           */
+#define UG_NUM_STAGES 14
 
 typedef struct ug_plan ug_plan; /* opaque, host-side */
 
@@ -97,11 +101,12 @@ typedef struct {
   float chi2;      /* Eq. 12 bound on d^2, > 0, may be +inf (default 7.815)      */
   float bg_alpha;  /* Eq. 5 background coefficient, > 0 (default 1e-2)           */
   float bg_color;  /* Eq. 6 background colour (default 0)                         */
-  int32_t tile_w;  /* tile width in pixels: 8, 16 or 32 (default 16)              */
-  int32_t tile_h;  /* tile height in pixels: 8 or 16 (default 16)                 */
-  int32_t px_per_lane; /* forward pixels per lane along a row: 1, 2, 4 or 8, with
-                          tile_w*tile_h/px_per_lane a multiple of 64 (0 = auto)    */
-  int32_t lds_batch; /* records staged in LDS per batch: 32, 64, 128 or 256 (default 64) */
+  int32_t tile_w;  /* tile width in pixels (default 16); (tile_w, tile_h) is one
+                      of 8x8, 16x8, 8x16, 16x16, 32x8, 32x16, 16x32, 32x32      */
+  int32_t tile_h;  /* tile height in pixels (default 16)                          */
+  int32_t px_per_lane; /* forward pixels per lane: tile_w / 8 (or 0 = that)        */
+  int32_t lds_batch; /* records each forward wave stages in LDS per round: 32, 64,
+                        128 or 256 (default 64)                                   */
   int32_t box_mode;  /* UG_BOX_* (default UG_BOX_PAPER)                           */
   int32_t flags;     /* UG_FLAG_* bits (default 0)                                */
 } ug_params;
@@ -162,8 +167,8 @@ int ug_render_planes_backward(const ug_plan *plan, const ug_gaussians *g,
 /* Reads the device-side status the last render left in the workspace
  * (synchronises the stream): UG_OK, UG_ERR_CAPACITY, UG_ERR_NONFINITE or
  * UG_ERR_INTERNAL.  counts_host (may be NULL) receives [records, keys,
- * in-support pairs] of that render; the third is 0 unless the plan was
- * created with UG_FLAG_COUNT_EVALS. */
+ * in-support pairs, evaluated pairs] of that render; the last two are 0
+ * unless the plan was created with UG_FLAG_COUNT_EVALS. */
 int ug_plan_status(const ug_plan *plan, const void *workspace, int64_t *counts_host,
                    void *stream);
 

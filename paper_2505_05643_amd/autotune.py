@@ -20,8 +20,7 @@ import torch
 
 from . import raster as R
 
-SHAPES = ((8, 8, 1), (16, 8, 1), (16, 8, 2), (16, 16, 1), (16, 16, 2), (16, 16, 4), (32, 8, 1), (32, 8, 2),
-          (32, 8, 4), (32, 16, 2), (32, 16, 4), (32, 16, 8))
+SHAPES = ((8, 8, 1), (16, 8, 2), (8, 16, 1), (16, 16, 2), (32, 8, 4), (32, 16, 4), (16, 32, 2), (32, 32, 4))
 BATCHES = (32, 64, 128, 256)
 BOXES = (R._lib.UG_BOX_PAPER, R._lib.UG_BOX_CONIC, R._lib.UG_BOX_ROWS)
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")

@@ -18,7 +18,7 @@ struct Layout {
   size_t ctrl, pconst, pcull, cnt_rec, accbits, off_rec, blk_g, blk_r;
   size_t rec_pair, racc, rgeo, rec_nkey, rec_koff, contrib;
   size_t tile_start, dsave, gq, hist;
-  size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, partial;
+  size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, kmask, smask, partial;
   size_t total;
 };
 
@@ -86,6 +86,8 @@ void compute_layout(ug_plan* pl) {
   L.key_val1 = take(K * 4);
   L.rec_of_key = take(K * 4);
   L.srec = take(K * 4);
+  L.kmask = take(K * 4);
+  L.smask = take(K * 4);
   L.partial = take(K * 32);
   L.total = o;
 }
@@ -177,17 +179,59 @@ hipError_t enqueue_preprocess(const ug_plan* plan, const ug_gaussians& g, const 
   }
   if (e != hipSuccess) return e;
   {
-    StageScope sc(plan, UG_STAGE_CULL, s);
-    e = launch_cull(g, at<PlaneCull>(ws, L.pcull), rp, at<uint32_t>(ws, L.cnt_rec),
-                    at<unsigned long long>(ws, L.accbits), at<unsigned long long>(ws, L.off_rec), at<uint2>(ws, L.rec_pair), at<uint32_t>(ws, L.blk_g),
-                    ctrl, s);
+    StageScope sc(plan, UG_STAGE_CULL_COUNT, s);
+    e = launch_cull_count(g, at<PlaneCull>(ws, L.pcull), rp, at<uint32_t>(ws, L.cnt_rec),
+                          at<unsigned long long>(ws, L.accbits), at<uint32_t>(ws, L.blk_g), ctrl, s);
   }
   if (e != hipSuccess) return e;
-  StageScope sc(plan, UG_STAGE_RECORD, s);
-  return launch_record(g, at<PlaneConst>(ws, L.pconst), plan->d_pint, rp, at<uint2>(ws, L.rec_pair),
-                       at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<uint32_t>(ws, L.rec_nkey),
-                       at<uint32_t>(ws, L.rec_koff), at<uint32_t>(ws, L.blk_r), ctrl, at<uint32_t>(ws, L.key_tile0),
-                       at<uint32_t>(ws, L.rec_of_key), s, false);
+  {
+    StageScope sc(plan, UG_STAGE_CULL_WRITE, s);
+    e = launch_cull_write(rp, at<uint32_t>(ws, L.cnt_rec), at<unsigned long long>(ws, L.accbits),
+                          at<uint32_t>(ws, L.blk_g), at<unsigned long long>(ws, L.off_rec), at<uint2>(ws, L.rec_pair),
+                          ctrl, s);
+  }
+  if (e != hipSuccess) return e;
+  {
+    StageScope sc(plan, UG_STAGE_RECORD, s);
+    e = launch_record(g, at<PlaneConst>(ws, L.pconst), plan->d_pint, rp, at<uint2>(ws, L.rec_pair),
+                      at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<uint32_t>(ws, L.rec_nkey),
+                      at<uint32_t>(ws, L.blk_r), ctrl, s);
+  }
+  if (e != hipSuccess) return e;
+  StageScope sc(plan, UG_STAGE_EMIT, s);
+  return launch_emit(plan->d_pint, rp, at<uint2>(ws, L.rec_pair), at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo),
+                     at<uint32_t>(ws, L.rec_nkey), at<uint32_t>(ws, L.blk_r), at<uint32_t>(ws, L.rec_koff), ctrl,
+                     at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.rec_of_key), at<uint32_t>(ws, L.kmask), s);
+}
+
+// The radix sort of the emitted keys, one launch per kernel and pass.
+hipError_t enqueue_sort(const ug_plan* plan, void* ws, hipStream_t s) {
+  const Layout& L = plan->lay;
+  const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+  uint32_t* kb[2] = {at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.key_tile1)};
+  uint32_t* vb[2] = {at<uint32_t>(ws, L.key_val0), at<uint32_t>(ws, L.key_val1)};
+  uint32_t* hist = at<uint32_t>(ws, L.hist);
+  const uint32_t G = plan->sort_blocks;
+  const int passes = sort_passes(plan->bits);
+  hipError_t e = hipSuccess;
+  for (int pass = 0, cur = 0; pass < passes && e == hipSuccess; ++pass, cur ^= 1) {
+    const bool last = pass == passes - 1;
+    {
+      StageScope sc(plan, UG_STAGE_SORT_HIST, s);
+      e = launch_radix_hist(ctrl, kb[cur], hist, G, pass, s);
+    }
+    if (e != hipSuccess) break;
+    {
+      StageScope sc(plan, UG_STAGE_SORT_SCAN, s);
+      e = launch_radix_colscan(hist, G, s);
+    }
+    if (e != hipSuccess) break;
+    StageScope sc(plan, UG_STAGE_SORT_SCATTER, s);
+    e = launch_radix_scatter(ctrl, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], hist, G, pass,
+                             last ? at<uint32_t>(ws, L.rec_of_key) : nullptr, last ? at<uint32_t>(ws, L.srec) : nullptr,
+                             last ? at<uint32_t>(ws, L.kmask) : nullptr, last ? at<uint32_t>(ws, L.smask) : nullptr, s);
+  }
+  return e;
 }
 
 }  // namespace
@@ -255,7 +299,7 @@ int ug_plan_create(int32_t n, int32_t p, const int32_t* wh_host, const ug_params
   int bits = 1;
   while (bits < 32 && (uint64_t(1) << bits) < tiles) ++bits;
   pl->bits = bits;
-  pl->final_buf = ((bits + 7) / 8) % 2;
+  pl->final_buf = sort_passes(bits) % 2;
   pl->device = dev;
   pl->rec_cap = (uint32_t)record_capacity;
   pl->key_cap = (uint32_t)key_capacity;
@@ -328,14 +372,9 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
   Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
   hipError_t e = enqueue_preprocess(plan, *g, *planes, ws, rp, s);
   if (e != hipSuccess) return UG_ERR_HIP;
-  int fb = 0;
-  {
-    StageScope sc(plan, UG_STAGE_SORT, s);
-    e = launch_sort(ctrl, at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.key_tile1),
-                    at<uint32_t>(ws, L.key_val0), at<uint32_t>(ws, L.key_val1), at<uint32_t>(ws, L.rec_of_key),
-                    at<uint32_t>(ws, L.srec), at<uint32_t>(ws, L.hist), plan->sort_blocks, plan->bits, &fb, s);
-  }
+  e = enqueue_sort(plan, ws, s);
   if (e != hipSuccess) return UG_ERR_HIP;
+  const int fb = plan->final_buf;
   const uint32_t* skeys = at<uint32_t>(ws, fb ? L.key_tile1 : L.key_tile0);
   {
     StageScope sc(plan, UG_STAGE_RANGES, s);
@@ -344,8 +383,8 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
   if (e != hipSuccess) return UG_ERR_HIP;
   unsigned long long* n_eval = (plan->prm.flags & UG_FLAG_COUNT_EVALS) ? &ctrl->n_eval : nullptr;
   StageScope sc(plan, UG_STAGE_ACCUM, s);
-  e = launch_accum_fwd(plan->prm.tile_w, plan->prm.tile_h, plan->ppl, plan->prm.lds_batch, plan->d_pint,
-                       plan->d_tile_plane, at<uint32_t>(ws, L.tile_start), at<uint32_t>(ws, L.srec),
+  e = launch_accum_fwd(plan->prm.tile_w, plan->prm.tile_h, plan->prm.lds_batch, plan->d_pint, plan->d_tile_plane,
+                       at<uint32_t>(ws, L.tile_start), at<uint32_t>(ws, L.srec), at<uint32_t>(ws, L.smask),
                        at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), image, at<float>(ws, L.dsave),
                        plan->prm.bg_alpha, plan->prm.bg_color, plan->num_tiles, n_eval, s);
   return hip_status(e);
@@ -378,7 +417,7 @@ int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const 
     e = launch_accum_bwd(plan->prm.tile_w, plan->prm.tile_h, ctrl, plan->d_pint, plan->d_tile_plane,
                          at<uint32_t>(ws, fb ? L.key_tile1 : L.key_tile0),
                          at<uint32_t>(ws, fb ? L.key_val1 : L.key_val0), at<uint32_t>(ws, L.srec),
-                         at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<float>(ws, L.gq),
+                         at<uint32_t>(ws, L.smask), at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<float>(ws, L.gq),
                          at<float>(ws, L.partial), plan->key_cap, s);
   }
   if (e != hipSuccess) return UG_ERR_HIP;
@@ -406,6 +445,7 @@ int ug_plan_status(const ug_plan* plan, const void* workspace, int64_t* counts_h
     counts_host[0] = (int64_t)c.n_rec;
     counts_host[1] = (int64_t)c.n_key;
     counts_host[2] = (int64_t)c.n_eval;
+    counts_host[3] = (int64_t)c.n_exec;
   }
   if (c.flags & kFlagInternal) return UG_ERR_INTERNAL;
   if (c.flags & (kFlagRecCap | kFlagKeyCap)) return UG_ERR_CAPACITY;

@@ -196,7 +196,7 @@ struct Footprint {
 // bit.  The ellipse is (t11 du + t12 dv)^2 + (t22 dv)^2 <= e0 - emin; its
 // right edge is concave in dv and its left edge convex, so the extreme
 // columns over a row band sit at the clamped stationary points.
-__device__ __forceinline__ bool rows_band(const RecAcc& ra, int ub, int vb, int ya, int yb, int umin,
+__host__ __device__ __forceinline__ bool rows_band(const RecAcc& ra, int ub, int vb, int ya, int yb, int umin,
                                           int umax, int& ua, int& uz) {
 #pragma clang fp contract(off)
   const double thr = (double)ra.e0 - (double)ra.emin;
@@ -233,6 +233,102 @@ __device__ __forceinline__ bool rows_band(const RecAcc& ra, int ub, int vb, int 
   ua = (int)ceil(a);
   uz = (int)floor(b);
   return ua <= uz;
+}
+
+// Sub-block coverage masks.  A tile is split into 8x8-pixel sub-blocks,
+// numbered row-major (bit band * (TW / 8) + column block).  A band is the
+// 8 pixel rows of one sub-block row; the column range of the ellipse over a
+// band (its projection, exact for a convex set) decides which sub-blocks of
+// the band it touches.  The per-record part is hoisted out of the band loop.
+struct BandPrep {
+  double thr, t11, t12, t22, u0, v0, vext, dvr, dvl;
+  bool inf;
+};
+
+__host__ __device__ __forceinline__ bool band_prep(const RecAcc& ra, int ub, int vb, BandPrep& b) {
+  b.thr = (double)ra.e0 - (double)ra.emin;
+  if (!(b.thr >= 0.0)) return false;
+  b.inf = __builtin_isinf(b.thr);
+  if (b.inf) return true;
+  b.t11 = ra.t11;
+  b.t12 = ra.t12;
+  b.t22 = ra.t22;
+  b.u0 = (double)ub + (double)ra.fu;
+  b.v0 = (double)vb + (double)ra.fv;
+  const double sq = sqrt(b.thr);
+  b.vext = sq / b.t22 * (1.0 + 1e-6) + 1e-3;
+  const double S = sqrt(b.t12 * b.t12 + b.t22 * b.t22);
+  b.dvr = -b.t12 * sq / (b.t22 * S);
+  b.dvl = -b.dvr;
+  return true;
+}
+
+// Column range [ua, uz] of the ellipse over pixel rows [ya, yb], clipped to
+// [umin, umax] and padded like rows_band; false if empty.
+__host__ __device__ __forceinline__ bool band_cols(const BandPrep& b, int ya, int yb, int umin, int umax, int& ua, int& uz) {
+  if (b.inf) {
+    ua = umin;
+    uz = umax;
+    return umin <= umax;
+  }
+  double lo = (double)ya - b.v0, hi = (double)yb - b.v0;
+  lo = lo > -b.vext ? lo : -b.vext;
+  hi = hi < b.vext ? hi : b.vext;
+  if (!(lo <= hi)) return false;
+  const double dvr = b.dvr < lo ? lo : (b.dvr > hi ? hi : b.dvr);
+  const double dvl = b.dvl < lo ? lo : (b.dvl > hi ? hi : b.dvl);
+  double qr = b.thr - b.t22 * b.t22 * dvr * dvr;
+  double ql = b.thr - b.t22 * b.t22 * dvl * dvl;
+  qr = qr > 0.0 ? qr : 0.0;
+  ql = ql > 0.0 ? ql : 0.0;
+  const double ur = b.u0 + (-b.t12 * dvr + sqrt(qr)) / b.t11;
+  const double ul = b.u0 + (-b.t12 * dvl - sqrt(ql)) / b.t11;
+  const double pad = 1e-3 + 1e-5 * (ur - ul);
+  double a = ul - pad, c = ur + pad;
+  a = a > (double)umin ? a : (double)umin;
+  c = c < (double)umax ? c : (double)umax;
+  if (!(a <= c)) return false;
+  ua = (int)ceil(a);
+  uz = (int)floor(c);
+  return ua <= uz;
+}
+
+// Column ranges of the bands of tile row ty (TH / 8 <= kMaxBands bands) over
+// the record's column span [umin, umax].  Empty bands get ua > uz.
+constexpr int kMaxBands = 4;
+__host__ __device__ __forceinline__ void band_ranges(const BandPrep& bp, bool ok, int ty, int TH, int H, int umin, int umax,
+                                            int (&ua)[kMaxBands], int (&uz)[kMaxBands]) {
+#pragma unroll
+  for (int b = 0; b < kMaxBands; ++b) {
+    const int ya = ty * TH + b * kSubBlock;
+    const int yb = min(ya + kSubBlock - 1, H - 1);
+    ua[b] = 1;
+    uz[b] = 0;
+    if (ok && b * kSubBlock < TH && ya <= yb) {
+      int a, z;
+      if (band_cols(bp, ya, yb, umin, umax, a, z)) {
+        ua[b] = a;
+        uz[b] = z;
+      }
+    }
+  }
+}
+
+// Mask of the sub-blocks of tile column tx touched by the band ranges
+// (TW / 8 column blocks per band).
+__host__ __device__ __forceinline__ uint32_t tile_mask(const int (&ua)[kMaxBands], const int (&uz)[kMaxBands], int tx, int TW) {
+  const int K = TW / kSubBlock;
+  const int x0 = tx * TW;
+  uint32_t m = 0;
+#pragma unroll
+  for (int b = 0; b < kMaxBands; ++b) {
+    const int lo = max(ua[b], x0) - x0, hi = min(uz[b], x0 + TW - 1) - x0;
+    if (lo <= hi) {
+      const uint32_t bits = ((2u << (hi / kSubBlock)) - 1u) & ~((1u << (lo / kSubBlock)) - 1u);
+      m |= bits << (b * K);
+    }
+  }
+  return m;
 }
 
 // Key count of a ROWS-mode record over its tile rectangle.

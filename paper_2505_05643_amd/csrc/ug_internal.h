@@ -21,10 +21,11 @@ struct Ctrl {
   unsigned long long n_rec;   // accepted (Gaussian, plane) records
   unsigned long long n_key;   // (record, tile) keys
   unsigned long long n_eval;  // in-support pairs (counted only on request)
+  unsigned long long n_exec;  // evaluated pairs, n_eval's companion
   unsigned int flags;         // kFlag* bits
   unsigned int n_rec_eff;     // records the later kernels process (0 on overflow)
   unsigned int n_key_eff;     // keys the later kernels process (0 on overflow)
-  unsigned int pad[7];
+  unsigned int pad[5];
 };
 static_assert(sizeof(Ctrl) == 64, "Ctrl layout");
 
@@ -78,6 +79,10 @@ static_assert(sizeof(PlaneCull) == 32, "PlaneCull layout");
 // scaled by sqrt(log2(e)/2); e0 = log2(alpha) - log2(e)/2 * r^2 with r^2 the
 // squared distance of the plane from the Gaussian; emin = log2(alpha) -
 // log2(e)/2 * chi^2, so e >= emin is exactly d^2 <= chi^2 (Eq. 12).
+// Side of the square pixel sub-blocks that tiles are split into (tile widths
+// and heights are multiples of it).
+constexpr int kSubBlock = 8;
+
 struct RecAcc {
   float t11, t12, t22, fu;
   float fv, e0, emin, c;

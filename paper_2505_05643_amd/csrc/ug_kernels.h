@@ -10,16 +10,22 @@ uint32_t cull_blocks(int n);
 uint32_t record_blocks(uint32_t rec_cap);
 hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, PlaneCull* pcf, Ctrl* ctrl,
                        hipStream_t s);
-// Phase-1 cull: per-Gaussian record counts and offsets, compact pair list.
+// Phase-1 cull: per-(Gaussian, plane) acceptance bits and per-Gaussian record
+// counts, then record offsets and the compact (Gaussian, plane) pair list.
 size_t accbits_words(int n, int p);
-hipError_t launch_cull(const ug_gaussians& g, const PlaneCull* pcf, const RenderParams& rp, uint32_t* cnt_rec,
-                       unsigned long long* accbits, unsigned long long* off_rec, uint2* rec_pair, uint32_t* blk_tot,
-                       Ctrl* ctrl, hipStream_t s);
-// Records (conic + footprint), key offsets and key emission.
+hipError_t launch_cull_count(const ug_gaussians& g, const PlaneCull* pcf, const RenderParams& rp, uint32_t* cnt_rec,
+                             unsigned long long* accbits, uint32_t* blk_tot, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_cull_write(const RenderParams& rp, const uint32_t* cnt_rec, const unsigned long long* accbits,
+                             const uint32_t* blk_tot, unsigned long long* off_rec, uint2* rec_pair, Ctrl* ctrl,
+                             hipStream_t s);
+// Records (conic + footprint and per-record key counts), then key offsets and
+// key emission: per key its tile id, record id and sub-block mask.
 hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
-                         const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* rec_koff,
-                         uint32_t* blk_tot, Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, hipStream_t s,
-                         bool emit_stage_split);
+                         const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* blk_tot,
+                         Ctrl* ctrl, hipStream_t s);
+hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const RecAcc* racc,
+                       const RecGeo* rgeo, const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
+                       Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, uint32_t* kmask, hipStream_t s);
 hipError_t launch_record_adjoint(const ug_gaussians& g, const PlaneConst* pc, const RenderParams& rp,
                                  const Ctrl* ctrl, const uint2* rec_pair, const uint32_t* rec_koff,
                                  const float* partial, float* contrib, hipStream_t s);
@@ -28,14 +34,20 @@ hipError_t launch_gauss_grad(const ug_gaussians& g, const RenderParams& rp, cons
                              float* d_int, float* d_op, int accumulate, hipStream_t s);
 
 // ---- tile binning sort (ug_sort.hip)
-// Stable LSD radix sort of (tile id, emission index) pairs on `bits` key
-// bits, 8 bits per pass.  keys/vals are ping-pong buffers; on return
-// *final_buf (0 or 1) names the buffer holding the sorted pairs, and srec
-// holds rec_of_key[] gathered in sorted order.  hist holds 256 * (nblocks + 1)
-// words.
-hipError_t launch_sort(const Ctrl* ctrl, uint32_t* keys0, uint32_t* keys1, uint32_t* vals0, uint32_t* vals1,
-                       const uint32_t* rec_of_key, uint32_t* srec, uint32_t* hist, uint32_t nblocks, int bits,
-                       int* final_buf, hipStream_t s);
+// Stable LSD radix sort of (tile id, emission index) pairs, 8 key bits per
+// pass (sort_passes(bits) passes over ping-pong buffers; pass k reads buffer
+// k%2 and writes buffer (k+1)%2).  Per pass: block-major digit histograms
+// (hist holds 256 * (nblocks + 1) words), their column scan, then the stable
+// scatter; the last pass also gathers rec_of_key[] and kmask[] into srec and
+// smask in sorted order.
+int sort_passes(int bits);
+hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t nblocks, int pass,
+                             hipStream_t s);
+hipError_t launch_radix_colscan(uint32_t* hist, uint32_t nblocks, hipStream_t s);
+hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
+                                uint32_t* vals_out, const uint32_t* hist, uint32_t nblocks, int pass,
+                                const uint32_t* rec_of_key, uint32_t* srec, const uint32_t* kmask, uint32_t* smask,
+                                hipStream_t s);
 hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, uint32_t* tile_start,
                               hipStream_t s);
 uint32_t sort_blocks_for(uint32_t key_cap);
@@ -43,17 +55,17 @@ uint32_t sort_blocks_for(uint32_t key_cap);
 // ---- accumulate (ug_raster.hip)
 int accum_default_ppl(int tile_w, int tile_h);
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);
-hipError_t launch_accum_fwd(int tile_w, int tile_h, int ppl, int lds_batch, const PlaneInt* pint, const uint32_t* tile_plane,
-                            const uint32_t* tile_start, const uint32_t* srec, const RecAcc* racc,
-                            const RecGeo* rgeo, float* image, float* dsave, float bg_alpha, float bg_color,
-                            uint32_t num_tiles, unsigned long long* n_eval, hipStream_t s);
+hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneInt* pint, const uint32_t* tile_plane,
+                            const uint32_t* tile_start, const uint32_t* srec, const uint32_t* smask,
+                            const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave, float bg_alpha,
+                            float bg_color, uint32_t num_tiles, unsigned long long* n_eval, hipStream_t s);
 hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const uint32_t* tile_plane,
                            const float* image, const float* d_image, const float* dsave, float* gq,
                            uint32_t num_tiles, hipStream_t s);
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const PlaneInt* pint,
                             const uint32_t* tile_plane, const uint32_t* skey, const uint32_t* sval,
-                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo, const float* gq,
-                            float* partial, uint32_t key_cap, hipStream_t s);
+                            const uint32_t* srec, const uint32_t* smask, const RecAcc* racc, const RecGeo* rgeo,
+                            const float* gq, float* partial, uint32_t key_cap, hipStream_t s);
 
 // ---- training helpers (ug_train.hip)
 hipError_t launch_mse(const float* image, const float* target, int64_t m, float* d_image, float* loss,

@@ -24,6 +24,7 @@ __global__ __launch_bounds__(256) void k_init(ug_planes pl, const PlaneInt* __re
     ctrl->n_rec = 0;
     ctrl->n_key = 0;
     ctrl->n_eval = 0;
+    ctrl->n_exec = 0;
     ctrl->flags = 0;
     ctrl->n_rec_eff = 0;
     ctrl->n_key_eff = 0;
@@ -226,33 +227,31 @@ __global__ __launch_bounds__(256) void k_cull_write(RenderParams rp, int gpb, ui
 // covers rpb consecutive records in rounds of 256.
 __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, const PlaneInt& PI, int box_mode,
                                           int TW, int TH, uint32_t r, uint32_t e, uint32_t e_end,
-                                          uint32_t* __restrict__ key_tile, uint32_t* __restrict__ rec_of_key) {
-  if (box_mode != UG_BOX_ROWS) {
-    for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
-      const uint32_t rowbase = PI.tile_off + (uint32_t)ty * (uint32_t)PI.ntx;
-      for (int tx = geo.tx0; tx <= geo.tx1; ++tx) {
-        if (e < e_end) {
-          key_tile[e] = rowbase + (uint32_t)tx;
-          rec_of_key[e] = r;
-        }
-        ++e;
-      }
-    }
-  } else {
-    const int umin = geo.tx0 * TW;
-    const int umax = min(geo.tx1 * TW + TW - 1, PI.W - 1);
-    for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
+                                          uint32_t* __restrict__ key_tile, uint32_t* __restrict__ rec_of_key,
+                                          uint32_t* __restrict__ kmask) {
+  const int umin = geo.tx0 * TW;
+  const int umax = min(geo.tx1 * TW + TW - 1, PI.W - 1);
+  BandPrep bp;
+  const bool ok = band_prep(ra, geo.ub, geo.vb, bp);
+  for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
+    int tx0 = geo.tx0, tx1 = geo.tx1;
+    if (box_mode == UG_BOX_ROWS) {
       const int ya = ty * TH, yb = min(ya + TH - 1, PI.H - 1);
       int ua, uz;
       if (!rows_band(ra, geo.ub, geo.vb, ya, yb, umin, umax, ua, uz)) continue;
-      const uint32_t rowbase = PI.tile_off + (uint32_t)ty * (uint32_t)PI.ntx;
-      for (int tx = ua / TW; tx <= uz / TW; ++tx) {
-        if (e < e_end) {
-          key_tile[e] = rowbase + (uint32_t)tx;
-          rec_of_key[e] = r;
-        }
-        ++e;
+      tx0 = ua / TW;
+      tx1 = uz / TW;
+    }
+    int bua[kMaxBands], buz[kMaxBands];
+    band_ranges(bp, ok, ty, TH, PI.H, umin, umax, bua, buz);
+    const uint32_t rowbase = PI.tile_off + (uint32_t)ty * (uint32_t)PI.ntx;
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      if (e < e_end) {
+        key_tile[e] = rowbase + (uint32_t)tx;
+        rec_of_key[e] = r;
+        kmask[e] = tile_mask(bua, buz, tx, TW);
       }
+      ++e;
     }
   }
 }
@@ -306,7 +305,7 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
                                               const RecGeo* __restrict__ rgeo, const uint32_t* __restrict__ rec_nkey,
                                               const uint32_t* __restrict__ blk_tot, uint32_t* __restrict__ rec_koff,
                                               Ctrl* __restrict__ ctrl, uint32_t* __restrict__ key_tile,
-                                              uint32_t* __restrict__ rec_of_key) {
+                                              uint32_t* __restrict__ rec_of_key, uint32_t* __restrict__ kmask) {
   __shared__ unsigned long long s_sh[4];
   const uint32_t nrec = ctrl->n_rec_eff;
   const uint32_t r_begin = blockIdx.x * (uint32_t)rpb;
@@ -325,7 +324,7 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
       rec_koff[r] = (uint32_t)(koff < rp.key_cap ? koff : rp.key_cap);
       if (nk > 0 && koff + nk <= rp.key_cap)
         emit_keys(racc[r], rgeo[r], pint[rec_pair[r].y], rp.box_mode, rp.tile_w, rp.tile_h, r, (uint32_t)koff,
-                  (uint32_t)(koff + nk), key_tile, rec_of_key);
+                  (uint32_t)(koff + nk), key_tile, rec_of_key, kmask);
     }
   }
   if (blockIdx.x == nact - 1 && threadIdx.x == 0) {
@@ -453,29 +452,38 @@ hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc
 
 size_t accbits_words(int n, int p) { return (size_t)n * (size_t)((p + 63) / 64); }
 
-hipError_t launch_cull(const ug_gaussians& g, const PlaneCull* pcf, const RenderParams& rp, uint32_t* cnt_rec,
-                       unsigned long long* accbits, unsigned long long* off_rec, uint2* rec_pair, uint32_t* blk_tot,
-                       Ctrl* ctrl, hipStream_t s) {
+hipError_t launch_cull_count(const ug_gaussians& g, const PlaneCull* pcf, const RenderParams& rp, uint32_t* cnt_rec,
+                             unsigned long long* accbits, uint32_t* blk_tot, Ctrl* ctrl, hipStream_t s) {
   const uint32_t nb = cull_blocks(rp.n);
-  const int gpb = cull_gpb(rp.n);
   if (nb == 0) return hipGetLastError();  // no Gaussians: the zeroed totals stand
-  hipLaunchKernelGGL(k_cull_count, dim3(nb), dim3(256), 0, s, g, pcf, rp, gpb, cnt_rec, accbits, blk_tot, ctrl);
-  hipLaunchKernelGGL(k_cull_write, dim3(nb), dim3(256), 0, s, rp, gpb, nb, cnt_rec, accbits, blk_tot, off_rec,
-                     rec_pair, ctrl);
+  hipLaunchKernelGGL(k_cull_count, dim3(nb), dim3(256), 0, s, g, pcf, rp, cull_gpb(rp.n), cnt_rec, accbits, blk_tot,
+                     ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_cull_write(const RenderParams& rp, const uint32_t* cnt_rec, const unsigned long long* accbits,
+                             const uint32_t* blk_tot, unsigned long long* off_rec, uint2* rec_pair, Ctrl* ctrl,
+                             hipStream_t s) {
+  const uint32_t nb = cull_blocks(rp.n);
+  if (nb == 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_cull_write, dim3(nb), dim3(256), 0, s, rp, cull_gpb(rp.n), nb, cnt_rec, accbits, blk_tot,
+                     off_rec, rec_pair, ctrl);
   return hipGetLastError();
 }
 
 hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
-                         const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* rec_koff,
-                         uint32_t* blk_tot, Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, hipStream_t s,
-                         bool emit_stage_split) {
-  (void)emit_stage_split;
-  const uint32_t nb = record_blocks(rp.rec_cap);
-  const int rpb = record_rpb(rp.rec_cap);
-  hipLaunchKernelGGL(k_record, dim3(nb), dim3(256), 0, s, g, pc, pint, rp, rpb, rec_pair, racc, rgeo, rec_nkey,
-                     blk_tot, ctrl);
-  hipLaunchKernelGGL(k_emit, dim3(nb), dim3(256), 0, s, pint, rp, rpb, rec_pair, racc, rgeo, rec_nkey, blk_tot,
-                     rec_koff, ctrl, key_tile, rec_of_key);
+                         const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* blk_tot,
+                         Ctrl* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_record, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, g, pc, pint, rp,
+                     record_rpb(rp.rec_cap), rec_pair, racc, rgeo, rec_nkey, blk_tot, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const RecAcc* racc,
+                       const RecGeo* rgeo, const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
+                       Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, uint32_t* kmask, hipStream_t s) {
+  hipLaunchKernelGGL(k_emit, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, pint, rp, record_rpb(rp.rec_cap),
+                     rec_pair, racc, rgeo, rec_nkey, blk_tot, rec_koff, ctrl, key_tile, rec_of_key, kmask);
   return hipGetLastError();
 }
 

@@ -1,142 +1,142 @@
 // Per-tile accumulation of the ultrasound image formation (Eq. 5-8, 12) and
 // its adjoint.
 //
-// Forward: one workgroup per tile, lanes = pixels.  The tile's records
-// (sorted by record id, so every pixel sums its Gaussians in the same order
-// whatever the tile shape) are staged through LDS in batches and every lane
-// walks the batch: per pixel-record pair two FMAs give the exponent, one
-// compare applies the Eq. 12 cut-off, one v_exp_f32 gives the weight.
+// Tiles are split into 8x8-pixel sub-blocks; every key carries the mask of
+// the sub-blocks its record's ellipse touches (Eq. 12 support, computed at
+// key emission), so both passes evaluate (record, pixel) pairs only inside
+// touched sub-blocks.
 //
-// Adjoint: lanes = keys (one record in one tile).  Each lane walks its
-// tile's pixels and accumulates the record's seven partial derivatives in
-// registers, so no cross-lane reduction or atomic is needed; rows that no
-// lane's ellipse reaches are skipped with a wave vote.
+// Forward: one workgroup per tile, one wave per band of 8 pixel rows, lanes
+// = pixels (a lane owns one pixel in each of the band's TW/8 sub-blocks).
+// Each wave streams the tile's records (sorted by record id, so every pixel
+// sums its Gaussians in the same order whatever the launch shape), keeps
+// those whose mask touches its band in a wave-private LDS list and walks the
+// list: per pixel-record pair two FMAs give the exponent, one compare
+// applies the cut-off and one v_exp_f32 gives the weight.
+//
+// Adjoint: a wave takes a chunk of keys and expands them into (key,
+// sub-block) items through an LDS queue; lanes = items, each walking its 64
+// pixels and accumulating the record's seven partial derivatives in
+// registers.  The items of a key are summed in sub-block order into the
+// key's partial, so no atomic is needed and the result is deterministic.
 #include "ug_kernels.h"
 
 namespace ug {
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// ---------------------------------------------------------------- forward
-// Lane layout: each wave owns a sub-tile LW*K pixels wide and 64/LW rows tall
-// (LW = lanes per pixel row, at most 8); a lane owns K pixels of one row,
-// LW apart.  Per staged record a wave first tests the record's bounding box
-// (from its own conic factor) against its sub-tile and then its row bound,
-// and skips the record when either shows no pixel of the wave in support.
-template <int TW, int TH, int K>
-struct FwdLayout {
-  static constexpr int NT = TW * TH / K;
-  static constexpr int LW = (TW / K) < 8 ? (TW / K) : 8;
-  static constexpr int SW = LW * K;  // sub-tile width
-  static constexpr int SH = 64 / LW; // sub-tile height
-  static constexpr int NWX = TW / SW;
-  static_assert(NT % 64 == 0 && TW % SW == 0 && TH % SH == 0 && (TW / SW) * (TH / SH) == NT / 64, "layout");
-};
+// Orders LDS writes and reads between the lanes of one wave (LDS operations
+// of a wave execute in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-// CNT: also count the in-support pairs of pixels inside the plane (a
-// measurement variant; the counter costs one VALU op per pair).
-template <int TW, int TH, int K, int BG, bool CNT>
-__global__ __launch_bounds__(TW* TH / K) void k_accum_fwd(const PlaneInt* __restrict__ pint,
-                                                          const uint32_t* __restrict__ tile_plane,
-                                                          const uint32_t* __restrict__ tile_start,
-                                                          const uint32_t* __restrict__ srec,
-                                                          const RecAcc* __restrict__ racc,
-                                                          const RecGeo* __restrict__ rgeo, float* __restrict__ image,
-                                                          float* __restrict__ dsave, float bg_alpha, float bg_color,
-                                                          unsigned long long* __restrict__ n_eval) {
-  using Lay = FwdLayout<TW, TH, K>;
-  constexpr int NT = Lay::NT, LW = Lay::LW, SW = Lay::SW, SH = Lay::SH, NWX = Lay::NWX;
-  __shared__ float4 sA[BG];
-  __shared__ float4 sB[BG];
-  __shared__ float4 sC[BG];
+// ---------------------------------------------------------------- forward
+// CNT: also count the in-support pairs of pixels inside the plane and the
+// evaluated pairs (64 per evaluated wave sub-block) into counters[0] and
+// counters[1] (a measurement variant; one more VALU op per pair).  BG records
+// are staged per wave and round (PER per lane; lanes beyond BG idle when
+// BG < 64).
+template <int TW, int TH, int BG, bool CNT>
+__global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
+    const PlaneInt* __restrict__ pint, const uint32_t* __restrict__ tile_plane,
+    const uint32_t* __restrict__ tile_start, const uint32_t* __restrict__ srec, const uint32_t* __restrict__ smask,
+    const RecAcc* __restrict__ racc, const RecGeo* __restrict__ rgeo, float* __restrict__ image,
+    float* __restrict__ dsave, float bg_alpha, float bg_color, unsigned long long* __restrict__ counters) {
+  constexpr int K = TW / kSubBlock;   // pixels per lane = sub-blocks per band
+  constexpr int NB = TH / kSubBlock;  // bands = waves
+  constexpr int PER = BG >= 64 ? BG / 64 : 1;
+  constexpr int CAP = PER * 64;
+  static_assert(TW % kSubBlock == 0 && TH % kSubBlock == 0 && K * NB <= 32, "tile shape");
+  __shared__ float4 cA[NB][CAP];
+  __shared__ float4 cB[NB][CAP];
+  __shared__ uint32_t cM[NB][CAP];
 
   const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t p = tile_plane[t];
   const PlaneInt PI = pint[p];
   const uint32_t lt = t - PI.tile_off;
-  const int tx = (int)(lt % (uint32_t)PI.ntx), ty = (int)(lt / (uint32_t)PI.ntx);
-  const int x0 = tx * TW, y0 = ty * TH;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int sx0 = (wave % NWX) * SW, sy0 = (wave / NWX) * SH;
-  const int row = sy0 + lane / LW, col0 = sx0 + lane % LW;
+  const int x0 = (int)(lt % (uint32_t)PI.ntx) * TW, y0 = (int)(lt / (uint32_t)PI.ntx) * TH;
+  const int lane = threadIdx.x & 63, band = threadIdx.x >> 6;
+  const int row = band * kSubBlock + lane / kSubBlock, col0 = lane % kSubBlock;
   const float vrow = (float)row;
-  const float wx_lo = (float)sx0, wx_hi = (float)(sx0 + SW - 1);
-  const float wy_lo = (float)sy0, wy_hi = (float)(sy0 + SH - 1);
+  const uint32_t bshift = (uint32_t)(band * K), bmask = (1u << K) - 1u;
   float ucol[K], Nacc[K], Dacc[K];
   uint32_t cnt[K];
+  uint32_t nexec = 0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    ucol[k] = (float)(col0 + k * LW);
+    ucol[k] = (float)(col0 + k * kSubBlock);
     Nacc[k] = 0.f;
     Dacc[k] = 0.f;
     cnt[k] = 0u;
   }
   const uint32_t s = tile_start[t], e = tile_start[t + 1];
-  // Records are staged through LDS in batches of BG; the next batch is
-  // fetched into registers while the current one is evaluated.
-  constexpr int PER = (BG + NT - 1) / NT;  // records each thread stages per batch
   RecAcc pa[PER];
   RecGeo pg[PER];
+  uint32_t pm[PER];
   auto fetch = [&](uint32_t base) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const uint32_t j = tid + q * NT;
-      if (j < (uint32_t)BG && base + j < e) {
-        const uint32_t r = srec[base + j];
-        pa[q] = racc[r];
-        pg[q] = rgeo[r];
+      const uint32_t j = base + (uint32_t)(q * 64 + lane);
+      pm[q] = 0u;
+      if (q * 64 + lane < BG && j < e) {
+        const uint32_t m = (smask[j] >> bshift) & bmask;
+        pm[q] = m;
+        if (m) {
+          const uint32_t r = srec[j];
+          pa[q] = racc[r];
+          pg[q] = rgeo[r];
+        }
       }
     }
   };
   if (s < e) fetch(s);
   for (uint32_t base = s; base < e; base += BG) {
-    const uint32_t nb = min((uint32_t)BG, e - base);
+    // keep this round's records that touch the band, in order
+    uint32_t n = 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const uint32_t j = tid + q * NT;
-      if (j < nb) {
+      const uint32_t m = pm[q];
+      const unsigned long long bal = __ballot(m != 0u);
+      if (m) {
+        const uint32_t slot = n + lanemask_lt_popc(bal);
         const RecAcc& A = pa[q];
         const float du0 = (float)(pg[q].ub - x0) + A.fu;
         const float dv0 = (float)(pg[q].vb - y0) + A.fv;
-        sA[j] = make_float4(A.t11, A.t12, A.t22, -A.t11 * du0);
-        sB[j] = make_float4(dv0, A.e0, A.emin, A.c);
-        // bounding box of (t11 du + t12 dv)^2 + (t22 dv)^2 <= e0 - emin,
-        // padded well beyond float rounding (an empty support gives an
-        // inverted box, which every wave skips)
-        const float thr = A.e0 - A.emin;
-        const float sq = sqrtf(fmaxf(thr, 0.f));
-        const float hv = sq / A.t22 * 1.001f + 0.01f;
-        const float hu = sq * sqrtf(A.t12 * A.t12 + A.t22 * A.t22) / (A.t11 * A.t22) * 1.001f + 0.01f;
-        sC[j] = thr >= 0.f ? make_float4(du0 - hu, du0 + hu, dv0 - hv, dv0 + hv)
-                           : make_float4(1.f, -1.f, 1.f, -1.f);
+        cA[band][slot] = make_float4(A.t11, A.t12, A.t22, -A.t11 * du0);
+        cB[band][slot] = make_float4(dv0, A.e0, A.emin, A.c);
+        cM[band][slot] = m;
       }
+      n += (uint32_t)__popcll(bal);
     }
-    __syncthreads();
     if (base + BG < e) fetch(base + BG);
-    for (uint32_t j = 0; j < nb; ++j) {
-      const float4 bb = sC[j];
-      if (bb.x > wx_hi || bb.y < wx_lo || bb.z > wy_hi || bb.w < wy_lo) continue;  // uniform
-      const float4 a = sA[j];
-      const float4 b = sB[j];
+    wave_lds_sync();
+    for (uint32_t j = 0; j < n; ++j) {
+      const float4 a = cA[band][j];
+      const float4 b = cB[band][j];
+      const uint32_t m = __builtin_amdgcn_readfirstlane(cM[band][j]);
       const float dv = vrow - b.x;
       const float t2 = a.z * dv;
       const float erow = fmaf(-t2, t2, b.y);
-      // e <= erow on the whole pixel row: skip when no lane's row reaches
-      // the support (wave-uniform branch).
-      if (!__any(erow >= b.z)) continue;
       const float B = fmaf(a.y, dv, a.w);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
+        if (K > 1 && !((m >> k) & 1u)) continue;  // uniform
         const float t1 = fmaf(a.x, ucol[k], B);
         const float ee = fmaf(-t1, t1, erow);
         const float w = ee >= b.z ? fast_exp2(ee) : 0.f;
         Dacc[k] += w;
         Nacc[k] = fmaf(w, b.w, Nacc[k]);
-        if constexpr (CNT) cnt[k] += ee >= b.z ? 1u : 0u;
+        if constexpr (CNT) {
+          cnt[k] += ee >= b.z ? 1u : 0u;
+          ++nexec;
+        }
       }
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   const int v = y0 + row;
   if (v < PI.H) {
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(TW* TH / K) void k_accum_fwd(const PlaneInt* __rest
     uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int u = x0 + col0 + k * LW;
+      const int u = x0 + col0 + k * kSubBlock;
       if (u < PI.W) {
         const float Dt = Dacc[k] + bg_alpha;
         image[rowbase + u] = (Nacc[k] + bg_alpha * bg_color) / Dt;
@@ -153,8 +153,11 @@ __global__ __launch_bounds__(TW* TH / K) void k_accum_fwd(const PlaneInt* __rest
       }
     }
     if constexpr (CNT) {
-      if (c) atomicAdd(n_eval, (unsigned long long)c);
+      if (c) atomicAdd(&counters[0], (unsigned long long)c);
     }
+  }
+  if constexpr (CNT) {
+    if (lane == 0 && nexec) atomicAdd(&counters[1], 64ull * nexec);
   }
 }
 
@@ -185,27 +188,46 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const PlaneInt* __restrict__ p
 }
 
 // ---------------------------------------------------------------- backward
+// Keys per wave chunk: the chunk's (key, sub-block) slots fit 256 entries.
+template <int TW, int TH>
+struct BwdShape {
+  static constexpr int K = TW / kSubBlock, NB = TH / kSubBlock, Q = K * NB;
+  static constexpr int KC = Q <= 4 ? 64 : 256 / Q;
+  static constexpr int SLOTS = KC * Q;
+};
+
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl, const PlaneInt* __restrict__ pint,
                                                    const uint32_t* __restrict__ tile_plane,
                                                    const uint32_t* __restrict__ skey,
                                                    const uint32_t* __restrict__ sval,
                                                    const uint32_t* __restrict__ srec,
+                                                   const uint32_t* __restrict__ smask,
                                                    const RecAcc* __restrict__ racc, const RecGeo* __restrict__ rgeo,
                                                    const float2* __restrict__ gq, float4* __restrict__ partial) {
+  using S = BwdShape<TW, TH>;
+  constexpr int K = S::K, Q = S::Q, KC = S::KC, SLOTS = S::SLOTS;
+  // per wave: key parameters, the item queue and one 7-sum slot per item
+  __shared__ float4 kpA[4][KC];      // t11, t12, t22, -t11 du0
+  __shared__ float4 kpB[4][KC];      // du0, dv0, e0, emin
+  __shared__ float kpC[4][KC];       // c
+  __shared__ uint32_t kpT[4][KC];    // tile
+  __shared__ uint16_t queue[4][SLOTS];
+  __shared__ float slot[4][SLOTS][7];
   const uint32_t n = ctrl->n_key_eff;
   const float ln2 = (float)kLn2;
-  const uint32_t nchunks = (n + 255u) / 256u;
-  const uint32_t G = gridDim.x;
-  for (uint32_t it = 0; it * G < nchunks; ++it) {
-    const uint32_t chunk = it * G + xcd_remap(blockIdx.x, G);
-    if (chunk >= nchunks) break;  // uniform over the block
-    const uint32_t i = chunk * 256u + threadIdx.x;
-    const bool act = i < n;
-    float t11 = 0.f, t12 = 0.f, t22 = 0.f, P = 0.f, du0 = 0.f, dv0 = 0.f, e0 = 0.f, emin = INFINITY, c = 0.f;
-    uint32_t t = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t nchunks = (n + KC - 1u) / KC;
+  const uint32_t W = gridDim.x * 4u;
+  const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x) * 4u + (uint32_t)wave;
+  for (uint32_t chunk = wid; chunk < nchunks; chunk += W) {
+    // ---- load the chunk's keys and queue their touched sub-blocks
+    const uint32_t i = chunk * KC + (uint32_t)lane;
+    const bool act = lane < KC && i < n;
+    uint32_t m = 0u;
     if (act) {
-      t = skey[i];
+      m = smask[i];
+      const uint32_t t = skey[i];
       const uint32_t r = srec[i];
       const RecAcc A = racc[r];
       const RecGeo Gg = rgeo[r];
@@ -213,71 +235,134 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
       const uint32_t lt = t - PI.tile_off;
       const int x0 = (int)(lt % (uint32_t)PI.ntx) * TW;
       const int y0 = (int)(lt / (uint32_t)PI.ntx) * TH;
-      du0 = (float)(Gg.ub - x0) + A.fu;
-      dv0 = (float)(Gg.vb - y0) + A.fv;
-      t11 = A.t11;
-      t12 = A.t12;
-      t22 = A.t22;
-      P = -A.t11 * du0;
-      e0 = A.e0;
-      emin = A.emin;
-      c = A.c;
+      const float du0 = (float)(Gg.ub - x0) + A.fu;
+      const float dv0 = (float)(Gg.vb - y0) + A.fv;
+      kpA[wave][lane] = make_float4(A.t11, A.t12, A.t22, -A.t11 * du0);
+      kpB[wave][lane] = make_float4(du0, dv0, A.e0, A.emin);
+      kpC[wave][lane] = A.c;
+      kpT[wave][lane] = t;
     }
-    const float2* __restrict__ px = gq + (size_t)t * (TW * TH);
-    float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
-    for (int y = 0; y < TH; ++y) {
-      const float dv = (float)y - dv0;
-      const float B = fmaf(t12, dv, P);
-      const float t2 = t22 * dv;
-      const float erow = fmaf(-t2, t2, e0);
-      if (!__any(erow >= emin)) continue;  // no lane's ellipse reaches this row
-      float rge = 0.f, ra = 0.f;
-#pragma unroll 4
-      for (int x = 0; x < TW; ++x) {
-        const float xf = (float)x;
-        const float t1 = fmaf(t11, xf, B);
-        const float ee = fmaf(-t1, t1, erow);
-        const float w = ee >= emin ? fast_exp2(ee) : 0.f;
-        const float2 gg = px[y * TW + x];
-        const float gw = fmaf(gg.x, c, -gg.y);  // dL/dw = gamma (c - c_hat)
-        const float ge = w * gw;
-        rge += ge;
-        Sdc = fmaf(gg.x, w, Sdc);
-        const float a = ge * t1;
-        ra += a;
-        Sau = fmaf(a, xf, Sau);
+    uint32_t L = 0;
+#pragma unroll
+    for (int sb = 0; sb < Q; ++sb) {
+      const bool on = (m >> sb) & 1u;
+      const unsigned long long bal = __ballot(on);
+      if (on) queue[wave][L + lanemask_lt_popc(bal)] = (uint16_t)(lane | (sb << 8));
+      L += (uint32_t)__popcll(bal);
+    }
+    wave_lds_sync();
+    // ---- lanes = items: 8x8 pixels of one key each
+    for (uint32_t q0 = 0; q0 < L; q0 += 64) {
+      const uint32_t q = q0 + (uint32_t)lane;
+      const bool has = q < L;
+      const uint32_t ent = has ? (uint32_t)queue[wave][q] : 0u;
+      const int kl = (int)(ent & 255u), sb = (int)(ent >> 8);
+      const float4 a = kpA[wave][kl];
+      const float4 b = kpB[wave][kl];
+      const float c = kpC[wave][kl];
+      const uint32_t t = kpT[wave][kl];
+      const float t11 = a.x, t12 = a.y, t22 = a.z, P = a.w;
+      const float e0 = b.z, emin = has ? b.w : INFINITY;
+      const int bx = (sb % K) * kSubBlock, by = (sb / K) * kSubBlock;
+      const float2* __restrict__ px = gq + (size_t)t * (TW * TH) + by * TW + bx;
+      float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
+      for (int y = 0; y < kSubBlock; ++y) {
+        const float dv = (float)(by + y) - b.y;
+        const float B = fmaf(t12, dv, P);
+        const float t2 = t22 * dv;
+        const float erow = fmaf(-t2, t2, e0);
+        if (!__any(erow >= emin)) continue;  // no item's ellipse reaches this row
+        const float4* __restrict__ prow = reinterpret_cast<const float4*>(px + y * TW);
+        float rge = 0.f, ra = 0.f;
+#pragma unroll
+        for (int x2 = 0; x2 < kSubBlock / 2; ++x2) {
+          const float4 gg2 = prow[x2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const float gx = h ? gg2.z : gg2.x, gy = h ? gg2.w : gg2.y;
+            const float xf = (float)(bx + 2 * x2 + h);
+            const float t1 = fmaf(t11, xf, B);
+            const float ee = fmaf(-t1, t1, erow);
+            const float w = ee >= emin ? fast_exp2(ee) : 0.f;
+            const float gw = fmaf(gx, c, -gy);  // dL/dw = gamma (c - c_hat)
+            const float ge = w * gw;
+            rge += ge;
+            Sdc = fmaf(gx, w, Sdc);
+            const float av = ge * t1;
+            ra += av;
+            Sau = fmaf(av, xf, Sau);
+          }
+        }
+        Sge += rge;
+        Sa += ra;
+        S12 = fmaf(dv, ra, S12);
+        Sb = fmaf(t2, rge, Sb);
+        S22 = fmaf(t2 * dv, rge, S22);
       }
-      Sge += rge;
-      Sa += ra;
-      S12 = fmaf(dv, ra, S12);
-      Sb = fmaf(t2, rge, Sb);
-      S22 = fmaf(t2 * dv, rge, S22);
+      if (has) {
+        float* o = slot[wave][kl * Q + sb];
+        o[0] = Sge;
+        o[1] = Sa;
+        o[2] = Sau;
+        o[3] = S12;
+        o[4] = S22;
+        o[5] = Sb;
+        o[6] = Sdc;
+      }
     }
+    wave_lds_sync();
+    // ---- per key: its items in sub-block order, then the partials
     if (act) {
+      float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
+      for (int sb = 0; sb < Q; ++sb) {
+        if (!((m >> sb) & 1u)) continue;
+        const float* o = slot[wave][lane * Q + sb];
+        Sge += o[0];
+        Sa += o[1];
+        Sau += o[2];
+        S12 += o[3];
+        S22 += o[4];
+        Sb += o[5];
+        Sdc += o[6];
+      }
+      const float4 a = kpA[wave][lane];
+      const float du0 = kpB[wave][lane].x;
       // w = 2^(e0 - t1^2 - t2^2):  dL/ds = -ln2 w dL/dw, s = t1^2 + t2^2.
       const float k2 = 2.f * ln2;
       const uint32_t eidx = sval[i];
-      partial[2 * (size_t)eidx] = make_float4(-k2 * (Sau - du0 * Sa), -k2 * S12, -k2 * S22, k2 * t11 * Sa);
-      partial[2 * (size_t)eidx + 1] = make_float4(k2 * (t12 * Sa + t22 * Sb), ln2 * Sge, Sdc, 0.f);
+      partial[2 * (size_t)eidx] = make_float4(-k2 * (Sau - du0 * Sa), -k2 * S12, -k2 * S22, k2 * a.x * Sa);
+      partial[2 * (size_t)eidx + 1] = make_float4(k2 * (a.y * Sa + a.z * Sb), ln2 * Sge, Sdc, 0.f);
     }
+    wave_lds_sync();  // the next chunk rewrites this wave's LDS
   }
 }
 
 // ---------------------------------------------------------------- dispatch
-template <int TW, int TH, int K>
+// Tile shapes compiled in (multiples of the 8x8 sub-block).
+#define UG_TILE_SHAPES(X) \
+  X(8, 8)                 \
+  X(16, 8)                \
+  X(8, 16)                \
+  X(16, 16)               \
+  X(32, 8)                \
+  X(32, 16)               \
+  X(16, 32)               \
+  X(32, 32)
+
+template <int TW, int TH>
 static hipError_t fwd_bg(int bg, dim3 grid, hipStream_t s, const PlaneInt* pint, const uint32_t* tp,
-                         const uint32_t* ts, const uint32_t* srec, const RecAcc* ra, const RecGeo* rg, float* img,
-                         float* ds, float ba, float bc, unsigned long long* n_eval) {
-  constexpr int NT = TW * TH / K;
+                         const uint32_t* ts, const uint32_t* srec, const uint32_t* smask, const RecAcc* ra,
+                         const RecGeo* rg, float* img, float* ds, float ba, float bc, unsigned long long* n_eval) {
+  constexpr int NT = 64 * (TH / kSubBlock);
   switch (bg) {
-#define UG_BG(B)                                                                                                  \
-  case B:                                                                                                         \
-    if (n_eval)                                                                                                   \
-      hipLaunchKernelGGL((k_accum_fwd<TW, TH, K, B, true>), grid, dim3(NT), 0, s, pint, tp, ts, srec, ra, rg, img, \
-                         ds, ba, bc, n_eval);                                                                     \
-    else                                                                                                          \
-      hipLaunchKernelGGL((k_accum_fwd<TW, TH, K, B, false>), grid, dim3(NT), 0, s, pint, tp, ts, srec, ra, rg,     \
-                         img, ds, ba, bc, n_eval);                                                                \
+#define UG_BG(B)                                                                                                   \
+  case B:                                                                                                          \
+    if (n_eval)                                                                                                    \
+      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, true>), grid, dim3(NT), 0, s, pint, tp, ts, srec, smask, ra, rg, \
+                         img, ds, ba, bc, n_eval);                                                                 \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, false>), grid, dim3(NT), 0, s, pint, tp, ts, srec, smask, ra, rg, \
+                         img, ds, ba, bc, n_eval);                                                                 \
     return hipGetLastError();
     UG_BG(32)
     UG_BG(64)
@@ -289,45 +374,31 @@ static hipError_t fwd_bg(int bg, dim3 grid, hipStream_t s, const PlaneInt* pint,
   }
 }
 
-// (tile_w, tile_h, pixels per lane) combinations compiled in.
-#define UG_FWD_SHAPES(X) \
-  X(8, 8, 1)             \
-  X(16, 8, 1)            \
-  X(16, 8, 2)            \
-  X(16, 16, 1)           \
-  X(16, 16, 2)           \
-  X(16, 16, 4)           \
-  X(32, 8, 1)            \
-  X(32, 8, 2)            \
-  X(32, 8, 4)            \
-  X(32, 16, 2)           \
-  X(32, 16, 4)           \
-  X(32, 16, 8)
-
 int accum_default_ppl(int tile_w, int tile_h) {
-  const int px = tile_w * tile_h;
-  return px >= 512 ? px / 256 : 1;
+  (void)tile_h;
+  return tile_w / kSubBlock;
 }
 
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch) {
   if (!(lds_batch == 32 || lds_batch == 64 || lds_batch == 128 || lds_batch == 256)) return false;
-#define UG_OK_SHAPE(W, H, K) \
-  if (tile_w == W && tile_h == H && ppl == K) return true;
-  UG_FWD_SHAPES(UG_OK_SHAPE)
+  if (ppl != tile_w / kSubBlock) return false;
+#define UG_OK_SHAPE(W, H) \
+  if (tile_w == W && tile_h == H) return true;
+  UG_TILE_SHAPES(UG_OK_SHAPE)
 #undef UG_OK_SHAPE
   return false;
 }
 
-hipError_t launch_accum_fwd(int tile_w, int tile_h, int ppl, int lds_batch, const PlaneInt* pint,
-                            const uint32_t* tile_plane, const uint32_t* tile_start, const uint32_t* srec,
+hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneInt* pint, const uint32_t* tile_plane,
+                            const uint32_t* tile_start, const uint32_t* srec, const uint32_t* smask,
                             const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave, float bg_alpha,
                             float bg_color, uint32_t num_tiles, unsigned long long* n_eval, hipStream_t s) {
   const dim3 grid(num_tiles);
-#define UG_LAUNCH_SHAPE(W, H, K)                                                                            \
-  if (tile_w == W && tile_h == H && ppl == K)                                                               \
-    return fwd_bg<W, H, K>(lds_batch, grid, s, pint, tile_plane, tile_start, srec, racc, rgeo, image, dsave, \
-                           bg_alpha, bg_color, n_eval);
-  UG_FWD_SHAPES(UG_LAUNCH_SHAPE)
+#define UG_LAUNCH_SHAPE(W, H)                                                                                   \
+  if (tile_w == W && tile_h == H)                                                                               \
+    return fwd_bg<W, H>(lds_batch, grid, s, pint, tile_plane, tile_start, srec, smask, racc, rgeo, image, dsave, \
+                        bg_alpha, bg_color, n_eval);
+  UG_TILE_SHAPES(UG_LAUNCH_SHAPE)
 #undef UG_LAUNCH_SHAPE
   return hipErrorInvalidValue;
 }
@@ -344,35 +415,27 @@ hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const u
                        num_tiles);                                                                                 \
     return hipGetLastError();                                                                                      \
   }
-  UG_PREP(8, 8)
-  UG_PREP(16, 8)
-  UG_PREP(16, 16)
-  UG_PREP(32, 8)
-  UG_PREP(32, 16)
+  UG_TILE_SHAPES(UG_PREP)
 #undef UG_PREP
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const PlaneInt* pint,
                             const uint32_t* tile_plane, const uint32_t* skey, const uint32_t* sval,
-                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo, const float* gq,
-                            float* partial, uint32_t key_cap, hipStream_t s) {
-  uint32_t want = (key_cap + 255u) / 256u;
-  if (want < 1) want = 1;
-  const uint32_t blocks = want < 16384u ? want : 16384u;
+                            const uint32_t* srec, const uint32_t* smask, const RecAcc* racc, const RecGeo* rgeo,
+                            const float* gq, float* partial, uint32_t key_cap, hipStream_t s) {
   const float2* g2 = reinterpret_cast<const float2*>(gq);
   float4* p4 = reinterpret_cast<float4*>(partial);
-#define UG_BWD(W, H)                                                                                         \
-  if (tile_w == W && tile_h == H) {                                                                          \
+#define UG_BWD(W, H)                                                                                          \
+  if (tile_w == W && tile_h == H) {                                                                           \
+    const uint32_t kc = (uint32_t)BwdShape<W, H>::KC;                                                         \
+    uint32_t want = (key_cap / kc + 4u) / 4u;                                                                 \
+    const uint32_t blocks = want < 1u ? 1u : (want > 16384u ? 16384u : want);                                 \
     hipLaunchKernelGGL((k_accum_bwd<W, H>), dim3(blocks), dim3(256), 0, s, ctrl, pint, tile_plane, skey, sval, \
-                       srec, racc, rgeo, g2, p4);                                                            \
-    return hipGetLastError();                                                                                \
+                       srec, smask, racc, rgeo, g2, p4);                                                      \
+    return hipGetLastError();                                                                                 \
   }
-  UG_BWD(8, 8)
-  UG_BWD(16, 8)
-  UG_BWD(16, 16)
-  UG_BWD(32, 8)
-  UG_BWD(32, 16)
+  UG_TILE_SHAPES(UG_BWD)
 #undef UG_BWD
   return hipErrorInvalidValue;
 }

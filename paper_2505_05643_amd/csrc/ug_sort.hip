@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ cnt,
     const uint32_t* __restrict__ coltot, uint32_t G, int shift, const uint32_t* __restrict__ rec_of_key,
-    uint32_t* __restrict__ srec) {
+    uint32_t* __restrict__ srec, const uint32_t* __restrict__ kmask, uint32_t* __restrict__ smask) {
   __shared__ uint32_t s_key[kRound];
   __shared__ uint32_t s_val[kRound];
   __shared__ uint32_t run[256];      // global output position of the next key of each digit
@@ -173,7 +173,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       const uint32_t pos = run[d] + (i - loc[d]);
       kout[pos] = k;
       vout[pos] = v;
-      if (srec) srec[pos] = rec_of_key[v];
+      if (srec) {
+        srec[pos] = rec_of_key[v];
+        smask[pos] = kmask[v];
+      }
     }
     __syncthreads();
     run[tid] += cum[tid];
@@ -208,25 +211,26 @@ uint32_t sort_blocks_for(uint32_t key_cap) {
   return g;
 }
 
-hipError_t launch_sort(const Ctrl* ctrl, uint32_t* keys0, uint32_t* keys1, uint32_t* vals0, uint32_t* vals1,
-                       const uint32_t* rec_of_key, uint32_t* srec, uint32_t* hist, uint32_t G, int bits,
-                       int* final_buf, hipStream_t s) {
-  const int passes = (bits + 7) / 8 < 1 ? 1 : (bits + 7) / 8;
-  uint32_t* kb[2] = {keys0, keys1};
-  uint32_t* vb[2] = {vals0, vals1};
-  int cur = 0;
-  for (int pass = 0; pass < passes; ++pass) {
-    const int shift = 8 * pass;
-    const bool last = pass == passes - 1;
-    uint32_t* coltot = hist + (size_t)256 * G;
-    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, s, ctrl, kb[cur], G, shift, hist);
-    hipLaunchKernelGGL(k_radix_colscan, dim3(256), dim3(256), 0, s, hist, G, coltot);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kSortThreads), 0, s, ctrl, kb[cur],
-                       pass == 0 ? (const uint32_t*)nullptr : vb[cur], kb[cur ^ 1], vb[cur ^ 1], hist, coltot, G,
-                       shift, last ? rec_of_key : (const uint32_t*)nullptr, last ? srec : (uint32_t*)nullptr);
-    cur ^= 1;
-  }
-  *final_buf = cur;
+int sort_passes(int bits) { return (bits + 7) / 8 < 1 ? 1 : (bits + 7) / 8; }
+
+hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t G, int pass,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys, G, 8 * pass, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_colscan(uint32_t* hist, uint32_t G, hipStream_t s) {
+  hipLaunchKernelGGL(k_radix_colscan, dim3(256), dim3(256), 0, s, hist, G, hist + (size_t)256 * G);
+  return hipGetLastError();
+}
+
+hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
+                                uint32_t* vals_out, const uint32_t* hist, uint32_t G, int pass,
+                                const uint32_t* rec_of_key, uint32_t* srec, const uint32_t* kmask, uint32_t* smask,
+                                hipStream_t s) {
+  if ((srec == nullptr) != (smask == nullptr)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys_in, pass == 0 ? nullptr : vals_in,
+                     keys_out, vals_out, hist, hist + (size_t)256 * G, G, 8 * pass, rec_of_key, srec, kmask, smask);
   return hipGetLastError();
 }
 

@@ -197,12 +197,13 @@ class Plan:
 
     def status(self, counts: bool = False):
         """Device status of the last render (synchronises); with counts=True
-        (code, records, keys, in-support pairs or 0)."""
-        out = (ctypes.c_int64 * 3)()
+        (code, records, keys, in-support pairs, evaluated pairs), the last two
+        0 unless the plan counts them (flags=1)."""
+        out = (ctypes.c_int64 * 4)()
         code = lib.ug_plan_status(self._h, self._ws_ptr, out, _stream())
         if code == _lib.UG_ERR_HIP:
             check(code, "ug_plan_status")
-        return (code, int(out[0]), int(out[1]), int(out[2])) if counts else code
+        return (code, int(out[0]), int(out[1]), int(out[2]), int(out[3])) if counts else code
 
     # ---------------------------------------------------------------- measurement
     def profile_begin(self, stages=None, max_launches: int = 4096):

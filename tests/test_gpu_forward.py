@@ -74,16 +74,18 @@ def test_one_pixel_planes_and_far_planes(R):
 
 
 def test_tile_shapes_box_modes_batches(R):
-    """Within one tile shape, every pixels-per-lane, LDS batch and binning box
-    gives the same image bit for bit (each pixel sums its in-support Gaussians
-    in record order; a binned pair outside the support adds exactly zero).
-    Across tile shapes only the tile-relative coordinates round differently."""
+    """Within one tile shape, every LDS batch and binning box gives the same
+    image bit for bit (each pixel sums its in-support Gaussians in record
+    order; a binned pair outside the support adds exactly zero, and the
+    sub-block masks do not depend on the box).  Across tile shapes only the
+    tile-relative coordinates round differently."""
     g = synth.make_gaussians(500, 43, (0, 0, 0), (1, 1, 1), (0.02, 0.12), aniso_max=8.0, opacity="random")
     pl = synth.random_planes(3, 44, (8, 8), 1 / 48, 0.35, 0.65)
     pl.wh[:] = [[61, 47], [32, 32], [48, 17]]
     base, plan = _render(R, g, pl)
     check_image(base, g, pl, plan.params)
-    shapes = {(8, 8): (1,), (16, 8): (1, 2), (16, 16): (1, 2, 4), (32, 8): (1, 2, 4), (32, 16): (2, 4, 8)}
+    shapes = {(8, 8): (0, 1), (16, 8): (2,), (8, 16): (1,), (16, 16): (0,), (32, 8): (4,), (32, 16): (4,),
+              (16, 32): (2,), (32, 32): (0,)}
     for (tw, th), ppls in shapes.items():
         first = None
         for ppl in ppls:
