@@ -366,9 +366,9 @@ def kernel_bytes(name, n, p, r, k, t, m, passes, w, rows, g_sort) -> int:
     if name == "bwd_prep":
         return 20 * m
     if name == "record_adj":
-        return 12 * r + 32 * k + 44 * n + 48 * r
+        return 12 * r + 32 * k + 44 * n + 44 * n
     if name == "gauss_grad":
-        return 12 * n + 48 * r + 44 * n
+        return 12 * n + 44 * n
     return 0
 
 

@@ -16,7 +16,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t ctrl, pconst, pcull, cnt_rec, accbits, off_rec, blk_g, blk_r;
-  size_t rec_pair, racc, rgeo, rec_nkey, rec_koff, contrib;
+  size_t rec_pair, racc, rgeo, rec_nkey, rec_koff, side;
   size_t tile_start, dsave, gq, hist;
   size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, kmask, smask, partial;
   size_t total;
@@ -75,7 +75,7 @@ void compute_layout(ug_plan* pl) {
   L.rgeo = take(R * sizeof(RecGeo));
   L.rec_nkey = take(R * 4);
   L.rec_koff = take((R + 1) * 4);
-  L.contrib = take(R * 48);
+  L.side = take(adjoint_side_floats(pl->rec_cap) * 4);
   L.tile_start = take((T + 1) * 4);
   L.dsave = take(pl->num_pixels * 4);
   L.gq = take(T * tpx * 8);
@@ -424,12 +424,14 @@ int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const 
   {
     StageScope sc(plan, UG_STAGE_RECORD_ADJ, s);
     e = launch_record_adjoint(*g, at<PlaneConst>(ws, L.pconst), rp, ctrl, at<uint2>(ws, L.rec_pair),
-                              at<uint32_t>(ws, L.rec_koff), at<float>(ws, L.partial), at<float>(ws, L.contrib), s);
+                              at<uint32_t>(ws, L.rec_koff), at<float>(ws, L.partial), at<uint32_t>(ws, L.cnt_rec),
+                              at<unsigned long long>(ws, L.off_rec), at<float>(ws, L.side), d_means, d_lraw,
+                              d_intensity, d_opacity, accumulate, s);
   }
   if (e != hipSuccess) return UG_ERR_HIP;
   StageScope sc(plan, UG_STAGE_GAUSS_GRAD, s);
   e = launch_gauss_grad(*g, rp, ctrl, at<uint32_t>(ws, L.cnt_rec), at<unsigned long long>(ws, L.off_rec),
-                        at<float>(ws, L.contrib), d_means, d_lraw, d_intensity, d_opacity, accumulate, s);
+                        at<float>(ws, L.side), d_means, d_lraw, d_intensity, d_opacity, accumulate, s);
   return hip_status(e);
 }
 

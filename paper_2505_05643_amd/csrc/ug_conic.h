@@ -190,82 +190,44 @@ struct Footprint {
   uint32_t keys;
 };
 
-// Exact column range of the record's ellipse over the pixel rows [ya, yb],
-// clipped to columns [umin, umax].  Evaluated in double from the float32
-// record with contraction off so every kernel that calls it agrees bit for
-// bit.  The ellipse is (t11 du + t12 dv)^2 + (t22 dv)^2 <= e0 - emin; its
-// right edge is concave in dv and its left edge convex, so the extreme
-// columns over a row band sit at the clamped stationary points.
-__host__ __device__ __forceinline__ bool rows_band(const RecAcc& ra, int ub, int vb, int ya, int yb, int umin,
-                                          int umax, int& ua, int& uz) {
-#pragma clang fp contract(off)
-  const double thr = (double)ra.e0 - (double)ra.emin;
-  if (!(thr >= 0.0)) return false;
-  if (__builtin_isinf(thr)) {
-    ua = umin;
-    uz = umax;
-    return umin <= umax;
-  }
-  const double t11 = ra.t11, t12 = ra.t12, t22 = ra.t22;
-  const double u0 = (double)ub + (double)ra.fu, v0 = (double)vb + (double)ra.fv;
-  const double sq = sqrt(thr);
-  const double vext = sq / t22 * (1.0 + 1e-6) + 1e-3;
-  double lo = (double)ya - v0, hi = (double)yb - v0;
-  lo = lo > -vext ? lo : -vext;
-  hi = hi < vext ? hi : vext;
-  if (!(lo <= hi)) return false;
-  const double S = sqrt(t12 * t12 + t22 * t22);
-  double dvr = -t12 * sq / (t22 * S);
-  dvr = dvr < lo ? lo : (dvr > hi ? hi : dvr);
-  double dvl = t12 * sq / (t22 * S);
-  dvl = dvl < lo ? lo : (dvl > hi ? hi : dvl);
-  double qr = thr - t22 * t22 * dvr * dvr;
-  double ql = thr - t22 * t22 * dvl * dvl;
-  qr = qr > 0.0 ? qr : 0.0;
-  ql = ql > 0.0 ? ql : 0.0;
-  const double ur = u0 + (-t12 * dvr + sqrt(qr)) / t11;
-  const double ul = u0 + (-t12 * dvl - sqrt(ql)) / t11;
-  const double pad = 1e-3 + 1e-5 * (ur - ul);
-  double a = ul - pad, b = ur + pad;
-  a = a > (double)umin ? a : (double)umin;
-  b = b < (double)umax ? b : (double)umax;
-  if (!(a <= b)) return false;
-  ua = (int)ceil(a);
-  uz = (int)floor(b);
-  return ua <= uz;
-}
-
-// Sub-block coverage masks.  A tile is split into 8x8-pixel sub-blocks,
-// numbered row-major (bit band * (TW / 8) + column block).  A band is the
-// 8 pixel rows of one sub-block row; the column range of the ellipse over a
-// band (its projection, exact for a convex set) decides which sub-blocks of
-// the band it touches.  The per-record part is hoisted out of the band loop.
+// Column ranges of the record's ellipse over bands of pixel rows.  The
+// ellipse is (t11 du + t12 dv)^2 + (t22 dv)^2 <= e0 - emin (du, dv relative
+// to the record's centre); its right edge is concave in dv and its left edge
+// convex, so the extreme columns over a row band sit at the clamped
+// stationary points.  Evaluated in double from the float32 record (the
+// square roots of the per-band remainders in float: their rounding is far
+// below the padding) with contraction off, so every kernel that calls these
+// gets the same answer bit for bit.
 struct BandPrep {
-  double thr, t11, t12, t22, u0, v0, vext, dvr, dvl;
+  double thr, t12, t22, inv_t11, u0, v0, vext, dvr;
   bool inf;
 };
 
 __host__ __device__ __forceinline__ bool band_prep(const RecAcc& ra, int ub, int vb, BandPrep& b) {
+#pragma clang fp contract(off)
   b.thr = (double)ra.e0 - (double)ra.emin;
   if (!(b.thr >= 0.0)) return false;
   b.inf = __builtin_isinf(b.thr);
   if (b.inf) return true;
-  b.t11 = ra.t11;
+  const double t11 = ra.t11;
   b.t12 = ra.t12;
   b.t22 = ra.t22;
+  b.inv_t11 = 1.0 / t11;
   b.u0 = (double)ub + (double)ra.fu;
   b.v0 = (double)vb + (double)ra.fv;
   const double sq = sqrt(b.thr);
   b.vext = sq / b.t22 * (1.0 + 1e-6) + 1e-3;
   const double S = sqrt(b.t12 * b.t12 + b.t22 * b.t22);
-  b.dvr = -b.t12 * sq / (b.t22 * S);
-  b.dvl = -b.dvr;
+  b.dvr = -b.t12 * sq / (b.t22 * S);  // row offset of the rightmost point; the leftmost is -dvr
   return true;
 }
 
 // Column range [ua, uz] of the ellipse over pixel rows [ya, yb], clipped to
-// [umin, umax] and padded like rows_band; false if empty.
-__host__ __device__ __forceinline__ bool band_cols(const BandPrep& b, int ya, int yb, int umin, int umax, int& ua, int& uz) {
+// [umin, umax] and padded so float rounding in the accumulation never keeps
+// a pixel outside it; false if empty.
+__host__ __device__ __forceinline__ bool band_cols(const BandPrep& b, int ya, int yb, int umin, int umax, int& ua,
+                                                   int& uz) {
+#pragma clang fp contract(off)
   if (b.inf) {
     ua = umin;
     uz = umax;
@@ -276,13 +238,13 @@ __host__ __device__ __forceinline__ bool band_cols(const BandPrep& b, int ya, in
   hi = hi < b.vext ? hi : b.vext;
   if (!(lo <= hi)) return false;
   const double dvr = b.dvr < lo ? lo : (b.dvr > hi ? hi : b.dvr);
-  const double dvl = b.dvl < lo ? lo : (b.dvl > hi ? hi : b.dvl);
+  const double dvl = -b.dvr < lo ? lo : (-b.dvr > hi ? hi : -b.dvr);
   double qr = b.thr - b.t22 * b.t22 * dvr * dvr;
   double ql = b.thr - b.t22 * b.t22 * dvl * dvl;
   qr = qr > 0.0 ? qr : 0.0;
   ql = ql > 0.0 ? ql : 0.0;
-  const double ur = b.u0 + (-b.t12 * dvr + sqrt(qr)) / b.t11;
-  const double ul = b.u0 + (-b.t12 * dvl - sqrt(ql)) / b.t11;
+  const double ur = b.u0 + (-b.t12 * dvr + (double)sqrtf((float)qr)) * b.inv_t11;
+  const double ul = b.u0 + (-b.t12 * dvl - (double)sqrtf((float)ql)) * b.inv_t11;
   const double pad = 1e-3 + 1e-5 * (ur - ul);
   double a = ul - pad, c = ur + pad;
   a = a > (double)umin ? a : (double)umin;
@@ -335,11 +297,13 @@ __host__ __device__ __forceinline__ uint32_t tile_mask(const int (&ua)[kMaxBands
 __device__ __forceinline__ uint32_t rows_count(const RecAcc& ra, const RecGeo& geo, int W, int H, int TW, int TH) {
   const int umin = geo.tx0 * TW;
   const int umax = min(geo.tx1 * TW + TW - 1, W - 1);
+  BandPrep bp;
+  if (!band_prep(ra, geo.ub, geo.vb, bp)) return 0;
   uint32_t keys = 0;
   for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
     const int ya = ty * TH, yb = min(ya + TH - 1, H - 1);
     int ua, uz;
-    if (rows_band(ra, geo.ub, geo.vb, ya, yb, umin, umax, ua, uz)) keys += (uint32_t)(uz / TW - ua / TW + 1);
+    if (band_cols(bp, ya, yb, umin, umax, ua, uz)) keys += (uint32_t)(uz / TW - ua / TW + 1);
   }
   return keys;
 }

@@ -79,6 +79,9 @@ static_assert(sizeof(PlaneCull) == 32, "PlaneCull layout");
 // scaled by sqrt(log2(e)/2); e0 = log2(alpha) - log2(e)/2 * r^2 with r^2 the
 // squared distance of the plane from the Gaussian; emin = log2(alpha) -
 // log2(e)/2 * chi^2, so e >= emin is exactly d^2 <= chi^2 (Eq. 12).
+// Per-Gaussian gradient fields: dmu (3), dL (6), d opacity logit, d intensity.
+constexpr int kGradFields = 11;
+
 // Side of the square pixel sub-blocks that tiles are split into (tile widths
 // and heights are multiples of it).
 constexpr int kSubBlock = 8;

@@ -26,11 +26,18 @@ hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const Plan
 hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const RecAcc* racc,
                        const RecGeo* rgeo, const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
                        Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, uint32_t* kmask, hipStream_t s);
+// Backward of the record construction and the per-Gaussian sums: the record
+// adjoint finishes every Gaussian whose records sit in one wave of 64 and
+// leaves per-wave segment sums in side (adjoint_side_floats floats); the
+// Gaussian pass finishes the rest and zeroes Gaussians without records.
+size_t adjoint_side_floats(uint32_t rec_cap);
 hipError_t launch_record_adjoint(const ug_gaussians& g, const PlaneConst* pc, const RenderParams& rp,
                                  const Ctrl* ctrl, const uint2* rec_pair, const uint32_t* rec_koff,
-                                 const float* partial, float* contrib, hipStream_t s);
+                                 const float* partial, const uint32_t* cnt_rec, const unsigned long long* off_rec,
+                                 float* side, float* d_means, float* d_lraw, float* d_int, float* d_op,
+                                 int accumulate, hipStream_t s);
 hipError_t launch_gauss_grad(const ug_gaussians& g, const RenderParams& rp, const Ctrl* ctrl, const uint32_t* cnt_rec,
-                             const unsigned long long* off_rec, const float* contrib, float* d_means, float* d_lraw,
+                             const unsigned long long* off_rec, const float* side, float* d_means, float* d_lraw,
                              float* d_int, float* d_op, int accumulate, hipStream_t s);
 
 // ---- tile binning sort (ug_sort.hip)

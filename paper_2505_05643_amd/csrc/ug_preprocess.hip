@@ -233,12 +233,13 @@ __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, c
   const int umax = min(geo.tx1 * TW + TW - 1, PI.W - 1);
   BandPrep bp;
   const bool ok = band_prep(ra, geo.ub, geo.vb, bp);
+  if (box_mode == UG_BOX_ROWS && !ok) return;
   for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
     int tx0 = geo.tx0, tx1 = geo.tx1;
     if (box_mode == UG_BOX_ROWS) {
       const int ya = ty * TH, yb = min(ya + TH - 1, PI.H - 1);
       int ua, uz;
-      if (!rows_band(ra, geo.ub, geo.vb, ya, yb, umin, umax, ua, uz)) continue;
+      if (!band_cols(bp, ya, yb, umin, umax, ua, uz)) continue;
       tx0 = ua / TW;
       tx1 = uz / TW;
     }
@@ -337,82 +338,149 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
 }
 
 // ---------------------------------------------------------------- adjoint
-// One thread per record: sum of its keys' partial derivatives (its keys are
-// contiguous in emission order), then the chain rule through the record
-// construction (in FP32: the adjoint's tolerance is 1e-3, and FP32 keeps the
-// register footprint small); the Gaussian's share goes to contrib[r].
+// Final gradient of Gaussian i from the sum of its records' contributions
+// (dmu[3], dL[6], da, dc): dL_kk / dl_kk = 2 l_kk (Eq. 11).
+__device__ __forceinline__ void write_gauss_grad(const ug_gaussians& g, int i, const float (&acc)[kGradFields],
+                                                 float* __restrict__ d_means, float* __restrict__ d_lraw,
+                                                 float* __restrict__ d_int, float* __restrict__ d_op, int accumulate) {
+  float v[kGradFields];
+#pragma unroll
+  for (int j = 0; j < kGradFields; ++j) v[j] = acc[j];
+  v[3] *= 2.f * g.lraw[6 * i + 0];
+  v[6] *= 2.f * g.lraw[6 * i + 3];
+  v[8] *= 2.f * g.lraw[6 * i + 5];
+  if (accumulate) {
+    for (int j = 0; j < 3; ++j) d_means[3 * i + j] += v[j];
+    for (int j = 0; j < 6; ++j) d_lraw[6 * i + j] += v[3 + j];
+    d_op[i] += v[9];
+    d_int[i] += v[10];
+  } else {
+    for (int j = 0; j < 3; ++j) d_means[3 * i + j] = v[j];
+    for (int j = 0; j < 6; ++j) d_lraw[6 * i + j] = v[3 + j];
+    d_op[i] = v[9];
+    d_int[i] = v[10];
+  }
+}
+
+// Lanes = records, 64 consecutive records per wave: the sum of the record's
+// keys' partial derivatives (contiguous in emission order), the chain rule
+// through the record construction (FP32: the adjoint's tolerance is 1e-3),
+// then the per-Gaussian sum.  A Gaussian's records are contiguous, so equal
+// Gaussian ids are added with a segmented scan across the wave; a Gaussian
+// whose records all sit in one wave gets its gradient here.  Each wave also
+// leaves its first and last segment sums in side[] for the Gaussians that
+// span waves (k_gauss_grad).  Deterministic, no atomics.
 __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const PlaneConst* __restrict__ pc,
                                                         RenderParams rp, const Ctrl* __restrict__ ctrl,
                                                         const uint2* __restrict__ rec_pair,
                                                         const uint32_t* __restrict__ rec_koff,
                                                         const float4* __restrict__ partial,
-                                                        float* __restrict__ contrib) {
+                                                        const uint32_t* __restrict__ cnt_rec,
+                                                        const unsigned long long* __restrict__ off_rec,
+                                                        float* __restrict__ side, float* __restrict__ d_means,
+                                                        float* __restrict__ d_lraw, float* __restrict__ d_int,
+                                                        float* __restrict__ d_op, int accumulate) {
   const bool ok = (ctrl->flags & (kFlagRecCap | kFlagKeyCap)) == 0;
   const uint32_t nrec = ok ? ctrl->n_rec_eff : 0u;
+  const uint32_t nw = (nrec + 63u) / 64u;
   const float chi2 = rp.chi2;
-  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nrec; r += gridDim.x * blockDim.x) {
-    const uint32_t k0 = rec_koff[r], k1 = rec_koff[r + 1];
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), c = a;
-    for (uint32_t k = k0; k < k1; ++k) {
-      const float4 x = partial[2 * (size_t)k], y = partial[2 * (size_t)k + 1];
-      a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
-      c.x += y.x; c.y += y.y; c.z += y.z; c.w += y.w;
-    }
-    float dmu[3] = {0, 0, 0}, dL[6] = {0, 0, 0, 0, 0, 0}, da = 0.f, dc = 0.f;
-    if (k1 > k0) {
-      const float dr[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+  const int lane = threadIdx.x & 63;
+  for (uint32_t w = blockIdx.x * 4u + (threadIdx.x >> 6); w < nw; w += gridDim.x * 4u) {
+    const uint32_t r = w * 64u + (uint32_t)lane;
+    const bool act = r < nrec;
+    float v[kGradFields];
+#pragma unroll
+    for (int j = 0; j < kGradFields; ++j) v[j] = 0.f;
+    uint32_t gid = 0xffffffffu;
+    if (act) {
       const uint2 gp = rec_pair[r];
-      GaussT<float> G;
-      load_gauss<float>(g, (int)gp.x, rp.beta, G);
-      const PlaneT<float> P = plane_as<float>(pc[gp.y]);
-      ConicT<float> k;
-      conic_cull(G, P, chi2, k);
-      conic_full(G, P, k);
-      footprint_adjoint(G, P, k, dr, dmu, dL, da, dc);
+      gid = gp.x;
+      const uint32_t k0 = rec_koff[r], k1 = rec_koff[r + 1];
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), c = a;
+      for (uint32_t k = k0; k < k1; ++k) {
+        const float4 x = partial[2 * (size_t)k], y = partial[2 * (size_t)k + 1];
+        a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
+        c.x += y.x; c.y += y.y; c.z += y.z; c.w += y.w;
+      }
+      if (k1 > k0) {
+        const float dr[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+        GaussT<float> G;
+        load_gauss<float>(g, (int)gp.x, rp.beta, G);
+        const PlaneT<float> P = plane_as<float>(pc[gp.y]);
+        ConicT<float> k;
+        conic_cull(G, P, chi2, k);
+        conic_full(G, P, k);
+        float dmu[3] = {0, 0, 0}, dL[6] = {0, 0, 0, 0, 0, 0}, da = 0.f, dc = 0.f;
+        footprint_adjoint(G, P, k, dr, dmu, dL, da, dc);
+        v[0] = dmu[0]; v[1] = dmu[1]; v[2] = dmu[2];
+        for (int j = 0; j < 6; ++j) v[3 + j] = dL[j];
+        v[9] = da;
+        v[10] = dc;
+      }
     }
-    float4* out = reinterpret_cast<float4*>(contrib + 12 * (size_t)r);
-    out[0] = make_float4((float)dmu[0], (float)dmu[1], (float)dmu[2], (float)dL[0]);
-    out[1] = make_float4((float)dL[1], (float)dL[2], (float)dL[3], (float)dL[4]);
-    out[2] = make_float4((float)dL[5], (float)da, (float)dc, 0.f);
+    // segmented inclusive scan over equal Gaussian ids (ids are sorted)
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t gu = __shfl_up(gid, o, 64);
+      const bool add = lane >= o && gu == gid;
+#pragma unroll
+      for (int j = 0; j < kGradFields; ++j) {
+        const float y = __shfl_up(v[j], o, 64);
+        if (add) v[j] += y;
+      }
+    }
+    const uint32_t gnext = __shfl_down(gid, 1, 64);
+    const uint32_t g0 = __shfl(gid, 0, 64);
+    const bool seg_end = act && (lane == 63 || gnext != gid);
+    if (seg_end) {
+      const uint64_t o = off_rec[gid];
+      const uint64_t e = o + cnt_rec[gid];
+      if (o >= (uint64_t)w * 64u && e <= (uint64_t)w * 64u + 64u)
+        write_gauss_grad(g, (int)gid, v, d_means, d_lraw, d_int, d_op, accumulate);
+      float* sd = side + (size_t)w * 2 * kGradFields;
+      if (gid == g0) {
+#pragma unroll
+        for (int j = 0; j < kGradFields; ++j) sd[j] = v[j];
+      }
+      if (lane == 63 || r + 1 == nrec) {
+#pragma unroll
+        for (int j = 0; j < kGradFields; ++j) sd[kGradFields + j] = v[j];
+      }
+    }
   }
 }
 
-// One thread per Gaussian: sum of its records' contributions (contiguous),
-// then dL_kk / dl_kk = 2 l_kk (Eq. 11).  Deterministic, no atomics.
+// One thread per Gaussian: zero gradient for a Gaussian without records,
+// and the sum of the wave pieces for one whose records span waves (the
+// first wave's last segment, whole middle waves, the last wave's first
+// segment); the others were written by k_record_adjoint.
 __global__ __launch_bounds__(256) void k_gauss_grad(ug_gaussians g, RenderParams rp, const Ctrl* __restrict__ ctrl,
                                                     const uint32_t* __restrict__ cnt_rec,
                                                     const unsigned long long* __restrict__ off_rec,
-                                                    const float* __restrict__ contrib, float* __restrict__ d_means,
+                                                    const float* __restrict__ side, float* __restrict__ d_means,
                                                     float* __restrict__ d_lraw, float* __restrict__ d_int,
                                                     float* __restrict__ d_op, int accumulate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rp.n) return;
   const bool ok = (ctrl->flags & (kFlagRecCap | kFlagKeyCap)) == 0;
   const uint32_t nr = ok ? cnt_rec[i] : 0u;
-  double acc[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  float acc[kGradFields];
+#pragma unroll
+  for (int j = 0; j < kGradFields; ++j) acc[j] = 0.f;
   if (nr > 0) {
-    const float4* c = reinterpret_cast<const float4*>(contrib + 12 * (size_t)off_rec[i]);
-    for (uint32_t j = 0; j < nr; ++j) {
-      const float4 x = c[3 * j], y = c[3 * j + 1], z = c[3 * j + 2];
-      acc[0] += x.x; acc[1] += x.y; acc[2] += x.z; acc[3] += x.w;
-      acc[4] += y.x; acc[5] += y.y; acc[6] += y.z; acc[7] += y.w;
-      acc[8] += z.x; acc[9] += z.y; acc[10] += z.z;
+    const uint64_t o = off_rec[i];
+    const uint64_t wa = o / 64u, wb = (o + nr - 1u) / 64u;
+    if (wa == wb) return;  // finished by k_record_adjoint
+    const float* sa = side + (size_t)wa * 2 * kGradFields + kGradFields;
+#pragma unroll
+    for (int j = 0; j < kGradFields; ++j) acc[j] = sa[j];
+    for (uint64_t w = wa + 1; w <= wb; ++w) {
+      const float* sw = side + (size_t)w * 2 * kGradFields;
+#pragma unroll
+      for (int j = 0; j < kGradFields; ++j) acc[j] += sw[j];
     }
-    acc[3] *= 2.0 * (double)g.lraw[6 * i + 0];
-    acc[6] *= 2.0 * (double)g.lraw[6 * i + 3];
-    acc[8] *= 2.0 * (double)g.lraw[6 * i + 5];
   }
-  if (accumulate) {
-    for (int j = 0; j < 3; ++j) d_means[3 * i + j] += (float)acc[j];
-    for (int j = 0; j < 6; ++j) d_lraw[6 * i + j] += (float)acc[3 + j];
-    d_op[i] += (float)acc[9];
-    d_int[i] += (float)acc[10];
-  } else {
-    for (int j = 0; j < 3; ++j) d_means[3 * i + j] = (float)acc[j];
-    for (int j = 0; j < 6; ++j) d_lraw[6 * i + j] = (float)acc[3 + j];
-    d_op[i] = (float)acc[9];
-    d_int[i] = (float)acc[10];
-  }
+  write_gauss_grad(g, i, acc, d_means, d_lraw, d_int, d_op, accumulate);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -487,22 +555,27 @@ hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2
   return hipGetLastError();
 }
 
+size_t adjoint_side_floats(uint32_t rec_cap) { return ((size_t)rec_cap + 63) / 64 * 2 * kGradFields; }
+
 hipError_t launch_record_adjoint(const ug_gaussians& g, const PlaneConst* pc, const RenderParams& rp,
                                  const Ctrl* ctrl, const uint2* rec_pair, const uint32_t* rec_koff,
-                                 const float* partial, float* contrib, hipStream_t s) {
+                                 const float* partial, const uint32_t* cnt_rec, const unsigned long long* off_rec,
+                                 float* side, float* d_means, float* d_lraw, float* d_int, float* d_op,
+                                 int accumulate, hipStream_t s) {
   uint32_t want = (rp.rec_cap + 255u) / 256u;
   const uint32_t blocks = want < 1 ? 1 : (want > 8192 ? 8192 : want);
   hipLaunchKernelGGL(k_record_adjoint, dim3(blocks), dim3(256), 0, s, g, pc, rp, ctrl, rec_pair, rec_koff,
-                     reinterpret_cast<const float4*>(partial), contrib);
+                     reinterpret_cast<const float4*>(partial), cnt_rec, off_rec, side, d_means, d_lraw, d_int, d_op,
+                     accumulate);
   return hipGetLastError();
 }
 
 hipError_t launch_gauss_grad(const ug_gaussians& g, const RenderParams& rp, const Ctrl* ctrl, const uint32_t* cnt_rec,
-                             const unsigned long long* off_rec, const float* contrib, float* d_means, float* d_lraw,
+                             const unsigned long long* off_rec, const float* side, float* d_means, float* d_lraw,
                              float* d_int, float* d_op, int accumulate, hipStream_t s) {
   const int blocks = (rp.n + 255) / 256;
   if (blocks > 0)
-    hipLaunchKernelGGL(k_gauss_grad, dim3(blocks), dim3(256), 0, s, g, rp, ctrl, cnt_rec, off_rec, contrib, d_means,
+    hipLaunchKernelGGL(k_gauss_grad, dim3(blocks), dim3(256), 0, s, g, rp, ctrl, cnt_rec, off_rec, side, d_means,
                        d_lraw, d_int, d_op, accumulate);
   return hipGetLastError();
 }

@@ -266,38 +266,53 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
       const int bx = (sb % K) * kSubBlock, by = (sb / K) * kSubBlock;
       const float2* __restrict__ px = gq + (size_t)t * (TW * TH) + by * TW + bx;
       float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
+      // rows of gamma are fetched one row ahead of their use
+      const float4* __restrict__ pq = reinterpret_cast<const float4*>(px);
+      float4 cur[kSubBlock / 2];
+#pragma unroll
+      for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = pq[x2];
+#pragma unroll
       for (int y = 0; y < kSubBlock; ++y) {
+        float4 nxt[kSubBlock / 2];
+        if (y + 1 < kSubBlock) {
+#pragma unroll
+          for (int x2 = 0; x2 < kSubBlock / 2; ++x2) nxt[x2] = pq[(y + 1) * (TW / 2) + x2];
+        }
         const float dv = (float)(by + y) - b.y;
         const float B = fmaf(t12, dv, P);
         const float t2 = t22 * dv;
         const float erow = fmaf(-t2, t2, e0);
-        if (!__any(erow >= emin)) continue;  // no item's ellipse reaches this row
-        const float4* __restrict__ prow = reinterpret_cast<const float4*>(px + y * TW);
-        float rge = 0.f, ra = 0.f;
+        if (__any(erow >= emin)) {  // else no item's ellipse reaches this row
+          float rge = 0.f, ra = 0.f;
 #pragma unroll
-        for (int x2 = 0; x2 < kSubBlock / 2; ++x2) {
-          const float4 gg2 = prow[x2];
+          for (int x2 = 0; x2 < kSubBlock / 2; ++x2) {
+            const float4 gg2 = cur[x2];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const float gx = h ? gg2.z : gg2.x, gy = h ? gg2.w : gg2.y;
-            const float xf = (float)(bx + 2 * x2 + h);
-            const float t1 = fmaf(t11, xf, B);
-            const float ee = fmaf(-t1, t1, erow);
-            const float w = ee >= emin ? fast_exp2(ee) : 0.f;
-            const float gw = fmaf(gx, c, -gy);  // dL/dw = gamma (c - c_hat)
-            const float ge = w * gw;
-            rge += ge;
-            Sdc = fmaf(gx, w, Sdc);
-            const float av = ge * t1;
-            ra += av;
-            Sau = fmaf(av, xf, Sau);
+            for (int h = 0; h < 2; ++h) {
+              const float gx = h ? gg2.z : gg2.x, gy = h ? gg2.w : gg2.y;
+              const float xf = (float)(bx + 2 * x2 + h);
+              const float t1 = fmaf(t11, xf, B);
+              const float ee = fmaf(-t1, t1, erow);
+              const float w = ee >= emin ? fast_exp2(ee) : 0.f;
+              const float gw = fmaf(gx, c, -gy);  // dL/dw = gamma (c - c_hat)
+              const float ge = w * gw;
+              rge += ge;
+              Sdc = fmaf(gx, w, Sdc);
+              const float av = ge * t1;
+              ra += av;
+              Sau = fmaf(av, xf, Sau);
+            }
           }
+          Sge += rge;
+          Sa += ra;
+          S12 = fmaf(dv, ra, S12);
+          Sb = fmaf(t2, rge, Sb);
+          S22 = fmaf(t2 * dv, rge, S22);
         }
-        Sge += rge;
-        Sa += ra;
-        S12 = fmaf(dv, ra, S12);
-        Sb = fmaf(t2, rge, Sb);
-        S22 = fmaf(t2 * dv, rge, S22);
+        if (y + 1 < kSubBlock) {
+#pragma unroll
+          for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = nxt[x2];
+        }
       }
       if (has) {
         float* o = slot[wave][kl * Q + sb];

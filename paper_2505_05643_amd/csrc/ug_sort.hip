@@ -73,13 +73,24 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ cn
   if (t == 0) coltot[d] = total;
 }
 
-// Stable scatter.  The block's chunk is walked in rounds of 2048 keys (8
-// sub-rounds of 256).  Ranks: inside a wave, lanes holding the same digit
-// are found with eight ballots; waves and sub-rounds are ordered through
-// LDS counters.  The round is then reordered by digit in LDS and written out
-// as contiguous runs per digit, so the global writes coalesce.
+// Orders LDS accesses between the lanes of one wave (a wave's LDS operations
+// execute in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stable scatter.  The block's chunk is walked in rounds of 2048 keys; in a
+// round wave w owns the 512 consecutive keys [w * 512, (w + 1) * 512),
+// loaded 64 at a time.  Each wave ranks its keys on its own: lanes holding
+// the same digit are found with eight ballots, and a per-wave digit counter
+// in LDS orders the wave's loads.  One block step then orders the waves and
+// the digits, the round is reordered by digit in LDS and written out as
+// contiguous runs per digit, so the global writes coalesce.
 constexpr int kItems = 8;
 constexpr int kRound = kSortThreads * kItems;
+constexpr int kWaveKeys = 64 * kItems;
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
@@ -89,9 +100,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   __shared__ uint32_t s_key[kRound];
   __shared__ uint32_t s_val[kRound];
   __shared__ uint32_t run[256];      // global output position of the next key of each digit
-  __shared__ uint32_t cum[256];      // keys of each digit seen so far in this round
   __shared__ uint32_t loc[256];      // first LDS slot of each digit in this round
-  __shared__ uint32_t wcnt[4][256];  // per-wave digit counts of one sub-round
+  __shared__ uint32_t rcnt[256];     // keys of each digit in this round
+  __shared__ uint32_t wcnt[4][256];  // per-wave digit counts, then the waves' prefixes
   __shared__ uint32_t sh[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t s, e;
@@ -109,18 +120,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     uint32_t before = 0;
     for (int w = 0; w < wave; ++w) before += sh[w];
     run[tid] = before + x - tot + cnt[(size_t)blockIdx.x * 256 + tid];
-    cum[tid] = 0;
   }
   for (uint32_t base = s; base < e; base += kRound) {
+    // ---- per wave: ranks of its 512 keys among its own keys of each digit
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wcnt[wave][lane + 64 * j] = 0u;
+    wave_lds_sync();
     uint32_t kk[kItems], vv[kItems], rr[kItems];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-      for (int j = tid; j < 1024; j += kSortThreads) (&wcnt[0][0])[j] = 0u;
-      __syncthreads();
-      const uint32_t i = base + it * kSortThreads + tid;
+      const uint32_t i = base + (uint32_t)(wave * kWaveKeys + it * 64 + lane);
       const bool valid = i < e;
       const uint32_t k = valid ? kin[i] : 0u;
-      const uint32_t v = valid ? (vin ? vin[i] : i) : 0u;
       const uint32_t d = (k >> shift) & 255u;
       unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -129,21 +140,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const unsigned long long bm = __ballot(on);
         peers &= on ? bm : ~bm;
       }
-      const uint32_t rank = lanemask_lt_popc(peers);
-      if (valid && (peers >> lane) == 1ull) wcnt[wave][d] = (uint32_t)__popcll(peers);
-      __syncthreads();
-      uint32_t pre = 0;
-      for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
+      const uint32_t before = valid ? wcnt[wave][d] : 0u;
+      wave_lds_sync();
+      if (valid && lanemask_lt_popc(peers) == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
+      wave_lds_sync();
       kk[it] = k;
-      vv[it] = v;
-      rr[it] = valid ? cum[d] + pre + rank : 0xffffffffu;
-      __syncthreads();
-      cum[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-      __syncthreads();  // wcnt is cleared again at the top of the next sub-round
+      vv[it] = valid ? (vin ? vin[i] : i) : 0u;
+      rr[it] = valid ? before + lanemask_lt_popc(peers) : 0xffffffffu;
     }
-    // digit offsets inside the round
+    __syncthreads();
+    // ---- per digit: the waves' prefixes and the round's count
     {
-      const uint32_t c = cum[tid];
+      const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
+      wcnt[0][tid] = 0u;
+      wcnt[1][tid] = c0;
+      wcnt[2][tid] = c0 + c1;
+      wcnt[3][tid] = c0 + c1 + c2;
+      const uint32_t c = c0 + c1 + c2 + c3;
+      rcnt[tid] = c;
       uint32_t x = c;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
@@ -160,7 +174,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       if (rr[it] != 0xffffffffu) {
-        const uint32_t slot = loc[(kk[it] >> shift) & 255u] + rr[it];
+        const uint32_t d = (kk[it] >> shift) & 255u;
+        const uint32_t slot = loc[d] + wcnt[wave][d] + rr[it];
         s_key[slot] = kk[it];
         s_val[slot] = vv[it];
       }
@@ -179,8 +194,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       }
     }
     __syncthreads();
-    run[tid] += cum[tid];
-    cum[tid] = 0;
+    run[tid] += rcnt[tid];
     __syncthreads();
   }
 }
