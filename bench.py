@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch configuration")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
-                    help="finish with 5 device-to-device copies of MIB MiB (calibrates HBM counters)")
+                    help="finish with 5 elementwise copies (dst = -src) of MIB MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU (plane-sharded) path is a design, "
@@ -330,7 +330,7 @@ def main():
         src = torch.ones(args.copy_probe << 18, device=dev)
         dst = torch.empty_like(src)
         for _ in range(5):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
 
 

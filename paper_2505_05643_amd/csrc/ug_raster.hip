@@ -50,9 +50,11 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
   constexpr int PER = BG >= 64 ? BG / 64 : 1;
   constexpr int CAP = PER * 64;
   static_assert(TW % kSubBlock == 0 && TH % kSubBlock == 0 && K * NB <= 32, "tile shape");
+  // per kept record: (t11, emin, c, mask) and, per pixel row of the band,
+  // (exponent at the row, t1 offset of the row) -- the row set-up is done
+  // once per record while staging instead of once per record and lane
   __shared__ float4 cA[NB][CAP];
-  __shared__ float4 cB[NB][CAP];
-  __shared__ uint32_t cM[NB][CAP];
+  __shared__ float2 cR[NB][CAP][kSubBlock];
 
   const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t p = tile_plane[t];
@@ -60,8 +62,8 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
   const uint32_t lt = t - PI.tile_off;
   const int x0 = (int)(lt % (uint32_t)PI.ntx) * TW, y0 = (int)(lt / (uint32_t)PI.ntx) * TH;
   const int lane = threadIdx.x & 63, band = threadIdx.x >> 6;
-  const int row = band * kSubBlock + lane / kSubBlock, col0 = lane % kSubBlock;
-  const float vrow = (float)row;
+  const int lrow = lane / kSubBlock, col0 = lane % kSubBlock;
+  const int row = band * kSubBlock + lrow;
   const uint32_t bshift = (uint32_t)(band * K), bmask = (1u << K) - 1u;
   float ucol[K], Nacc[K], Dacc[K];
   uint32_t cnt[K];
@@ -106,36 +108,45 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
         const RecAcc& A = pa[q];
         const float du0 = (float)(pg[q].ub - x0) + A.fu;
         const float dv0 = (float)(pg[q].vb - y0) + A.fv;
-        cA[band][slot] = make_float4(A.t11, A.t12, A.t22, -A.t11 * du0);
-        cB[band][slot] = make_float4(dv0, A.e0, A.emin, A.c);
-        cM[band][slot] = m;
+        const float P = -A.t11 * du0;
+        cA[band][slot] = make_float4(A.t11, A.emin, A.c, __uint_as_float(m));
+#pragma unroll
+        for (int y = 0; y < kSubBlock; ++y) {
+          const float dv = (float)(band * kSubBlock + y) - dv0;
+          const float t2 = A.t22 * dv;
+          cR[band][slot][y] = make_float2(fmaf(-t2, t2, A.e0), fmaf(A.t12, dv, P));
+        }
       }
       n += (uint32_t)__popcll(bal);
     }
     if (base + BG < e) fetch(base + BG);
     wave_lds_sync();
-    for (uint32_t j = 0; j < n; ++j) {
-      const float4 a = cA[band][j];
-      const float4 b = cB[band][j];
-      const uint32_t m = __builtin_amdgcn_readfirstlane(cM[band][j]);
-      const float dv = vrow - b.x;
-      const float t2 = a.z * dv;
-      const float erow = fmaf(-t2, t2, b.y);
-      const float B = fmaf(a.y, dv, a.w);
+    auto eval_rec = [&](const float4& a, const float2& rb) {
+      const uint32_t m = __builtin_amdgcn_readfirstlane(__float_as_uint(a.w));
+      const float erow = rb.x, B = rb.y;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (K > 1 && !((m >> k) & 1u)) continue;  // uniform
         const float t1 = fmaf(a.x, ucol[k], B);
         const float ee = fmaf(-t1, t1, erow);
-        const float w = ee >= b.z ? fast_exp2(ee) : 0.f;
+        const float w = ee >= a.y ? fast_exp2(ee) : 0.f;
         Dacc[k] += w;
-        Nacc[k] = fmaf(w, b.w, Nacc[k]);
+        Nacc[k] = fmaf(w, a.z, Nacc[k]);
         if constexpr (CNT) {
-          cnt[k] += ee >= b.z ? 1u : 0u;
+          cnt[k] += ee >= a.y ? 1u : 0u;
           ++nexec;
         }
       }
+    };
+    // two records per iteration so their LDS reads overlap
+    uint32_t j = 0;
+    for (; j + 1 < n; j += 2) {
+      const float4 a0 = cA[band][j], a1 = cA[band][j + 1];
+      const float2 r0 = cR[band][j][lrow], r1 = cR[band][j + 1][lrow];
+      eval_rec(a0, r0);
+      eval_rec(a1, r1);
     }
+    if (j < n) eval_rec(cA[band][j], cR[band][j][lrow]);
     wave_lds_sync();
   }
   const int v = y0 + row;
