@@ -218,7 +218,7 @@ hipError_t enqueue_sort(const ug_plan* plan, void* ws, hipStream_t s) {
     const bool last = pass == passes - 1;
     {
       StageScope sc(plan, UG_STAGE_SORT_HIST, s);
-      e = launch_radix_hist(ctrl, kb[cur], hist, G, pass, s);
+      e = launch_radix_hist(ctrl, kb[cur], hist, G, plan->bits, pass, s);
     }
     if (e != hipSuccess) break;
     {
@@ -227,7 +227,7 @@ hipError_t enqueue_sort(const ug_plan* plan, void* ws, hipStream_t s) {
     }
     if (e != hipSuccess) break;
     StageScope sc(plan, UG_STAGE_SORT_SCATTER, s);
-    e = launch_radix_scatter(ctrl, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], hist, G, pass,
+    e = launch_radix_scatter(ctrl, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], hist, G, plan->bits, pass,
                              last ? at<uint32_t>(ws, L.rec_of_key) : nullptr, last ? at<uint32_t>(ws, L.srec) : nullptr,
                              last ? at<uint32_t>(ws, L.kmask) : nullptr, last ? at<uint32_t>(ws, L.smask) : nullptr, s);
   }

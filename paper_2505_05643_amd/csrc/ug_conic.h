@@ -194,39 +194,38 @@ struct Footprint {
 // ellipse is (t11 du + t12 dv)^2 + (t22 dv)^2 <= e0 - emin (du, dv relative
 // to the record's centre); its right edge is concave in dv and its left edge
 // convex, so the extreme columns over a row band sit at the clamped
-// stationary points.  Evaluated in double from the float32 record (the
-// square roots of the per-band remainders in float: their rounding is far
-// below the padding) with contraction off, so every kernel that calls these
-// gets the same answer bit for bit.
+// stationary points.  The per-record constants are float (relative error
+// ~1e-7, far inside the 1e-5 relative padding); the per-band remainders,
+// where cancellation happens near the ellipse's top and bottom, are double,
+// with their square roots in float.  Contraction is off, so every kernel
+// that calls these gets the same answer bit for bit.
 struct BandPrep {
   double thr, t12, t22, inv_t11, u0, v0, vext, dvr;
   bool inf;
 };
 
-__host__ __device__ __forceinline__ bool band_prep(const RecAcc& ra, int ub, int vb, BandPrep& b) {
+__device__ __forceinline__ bool band_prep(const RecAcc& ra, int ub, int vb, BandPrep& b) {
 #pragma clang fp contract(off)
-  b.thr = (double)ra.e0 - (double)ra.emin;
+  b.thr = (double)ra.e0 - (double)ra.emin;  // exact
   if (!(b.thr >= 0.0)) return false;
   b.inf = __builtin_isinf(b.thr);
   if (b.inf) return true;
-  const double t11 = ra.t11;
   b.t12 = ra.t12;
   b.t22 = ra.t22;
-  b.inv_t11 = 1.0 / t11;
+  b.inv_t11 = (double)(1.0f / ra.t11);
   b.u0 = (double)ub + (double)ra.fu;
   b.v0 = (double)vb + (double)ra.fv;
-  const double sq = sqrt(b.thr);
-  b.vext = sq / b.t22 * (1.0 + 1e-6) + 1e-3;
-  const double S = sqrt(b.t12 * b.t12 + b.t22 * b.t22);
-  b.dvr = -b.t12 * sq / (b.t22 * S);  // row offset of the rightmost point; the leftmost is -dvr
+  const float sq = __builtin_amdgcn_sqrtf((float)b.thr);
+  b.vext = (double)(sq / ra.t22) * (1.0 + 1e-6) + 1e-3;
+  const float S = __builtin_amdgcn_sqrtf(ra.t12 * ra.t12 + ra.t22 * ra.t22);
+  b.dvr = (double)(-ra.t12 * sq / (ra.t22 * S));  // row offset of the rightmost point; the leftmost is -dvr
   return true;
 }
 
 // Column range [ua, uz] of the ellipse over pixel rows [ya, yb], clipped to
 // [umin, umax] and padded so float rounding in the accumulation never keeps
 // a pixel outside it; false if empty.
-__host__ __device__ __forceinline__ bool band_cols(const BandPrep& b, int ya, int yb, int umin, int umax, int& ua,
-                                                   int& uz) {
+__device__ __forceinline__ bool band_cols(const BandPrep& b, int ya, int yb, int umin, int umax, int& ua, int& uz) {
 #pragma clang fp contract(off)
   if (b.inf) {
     ua = umin;
@@ -243,8 +242,8 @@ __host__ __device__ __forceinline__ bool band_cols(const BandPrep& b, int ya, in
   double ql = b.thr - b.t22 * b.t22 * dvl * dvl;
   qr = qr > 0.0 ? qr : 0.0;
   ql = ql > 0.0 ? ql : 0.0;
-  const double ur = b.u0 + (-b.t12 * dvr + (double)sqrtf((float)qr)) * b.inv_t11;
-  const double ul = b.u0 + (-b.t12 * dvl - (double)sqrtf((float)ql)) * b.inv_t11;
+  const double ur = b.u0 + (-b.t12 * dvr + (double)__builtin_amdgcn_sqrtf((float)qr)) * b.inv_t11;
+  const double ul = b.u0 + (-b.t12 * dvl - (double)__builtin_amdgcn_sqrtf((float)ql)) * b.inv_t11;
   const double pad = 1e-3 + 1e-5 * (ur - ul);
   double a = ul - pad, c = ur + pad;
   a = a > (double)umin ? a : (double)umin;
@@ -258,7 +257,7 @@ __host__ __device__ __forceinline__ bool band_cols(const BandPrep& b, int ya, in
 // Column ranges of the bands of tile row ty (TH / 8 <= kMaxBands bands) over
 // the record's column span [umin, umax].  Empty bands get ua > uz.
 constexpr int kMaxBands = 4;
-__host__ __device__ __forceinline__ void band_ranges(const BandPrep& bp, bool ok, int ty, int TH, int H, int umin, int umax,
+__device__ __forceinline__ void band_ranges(const BandPrep& bp, int ty, int TH, int H, int umin, int umax,
                                             int (&ua)[kMaxBands], int (&uz)[kMaxBands]) {
 #pragma unroll
   for (int b = 0; b < kMaxBands; ++b) {
@@ -266,7 +265,7 @@ __host__ __device__ __forceinline__ void band_ranges(const BandPrep& bp, bool ok
     const int yb = min(ya + kSubBlock - 1, H - 1);
     ua[b] = 1;
     uz[b] = 0;
-    if (ok && b * kSubBlock < TH && ya <= yb) {
+    if (b * kSubBlock < TH && ya <= yb) {
       int a, z;
       if (band_cols(bp, ya, yb, umin, umax, a, z)) {
         ua[b] = a;
@@ -278,7 +277,7 @@ __host__ __device__ __forceinline__ void band_ranges(const BandPrep& bp, bool ok
 
 // Mask of the sub-blocks of tile column tx touched by the band ranges
 // (TW / 8 column blocks per band).
-__host__ __device__ __forceinline__ uint32_t tile_mask(const int (&ua)[kMaxBands], const int (&uz)[kMaxBands], int tx, int TW) {
+__device__ __forceinline__ uint32_t tile_mask(const int (&ua)[kMaxBands], const int (&uz)[kMaxBands], int tx, int TW) {
   const int K = TW / kSubBlock;
   const int x0 = tx * TW;
   uint32_t m = 0;
@@ -293,7 +292,8 @@ __host__ __device__ __forceinline__ uint32_t tile_mask(const int (&ua)[kMaxBands
   return m;
 }
 
-// Key count of a ROWS-mode record over its tile rectangle.
+// Key count of a ROWS-mode record over its tile rectangle: per tile row, the
+// tiles under the column range of the ellipse over the whole tile row.
 __device__ __forceinline__ uint32_t rows_count(const RecAcc& ra, const RecGeo& geo, int W, int H, int TW, int TH) {
   const int umin = geo.tx0 * TW;
   const int umax = min(geo.tx1 * TW + TW - 1, W - 1);

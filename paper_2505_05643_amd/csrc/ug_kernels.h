@@ -41,18 +41,19 @@ hipError_t launch_gauss_grad(const ug_gaussians& g, const RenderParams& rp, cons
                              float* d_int, float* d_op, int accumulate, hipStream_t s);
 
 // ---- tile binning sort (ug_sort.hip)
-// Stable LSD radix sort of (tile id, emission index) pairs, 8 key bits per
-// pass (sort_passes(bits) passes over ping-pong buffers; pass k reads buffer
+// Stable LSD radix sort of (tile id, emission index) pairs on `bits` key
+// bits, at most 8 per pass (sort_passes(bits) passes over ping-pong buffers,
+// the bits split evenly between them; pass k reads buffer
 // k%2 and writes buffer (k+1)%2).  Per pass: block-major digit histograms
 // (hist holds 256 * (nblocks + 1) words), their column scan, then the stable
 // scatter; the last pass also gathers rec_of_key[] and kmask[] into srec and
 // smask in sorted order.
 int sort_passes(int bits);
-hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t nblocks, int pass,
-                             hipStream_t s);
+hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t nblocks, int bits,
+                             int pass, hipStream_t s);
 hipError_t launch_radix_colscan(uint32_t* hist, uint32_t nblocks, hipStream_t s);
 hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
-                                uint32_t* vals_out, const uint32_t* hist, uint32_t nblocks, int pass,
+                                uint32_t* vals_out, const uint32_t* hist, uint32_t nblocks, int bits, int pass,
                                 const uint32_t* rec_of_key, uint32_t* srec, const uint32_t* kmask, uint32_t* smask,
                                 hipStream_t s);
 hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, uint32_t* tile_start,

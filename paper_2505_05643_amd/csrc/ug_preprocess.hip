@@ -244,7 +244,15 @@ __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, c
       tx1 = uz / TW;
     }
     int bua[kMaxBands], buz[kMaxBands];
-    band_ranges(bp, ok, ty, TH, PI.H, umin, umax, bua, buz);
+    if (ok) {
+      band_ranges(bp, ty, TH, PI.H, umin, umax, bua, buz);
+    } else {
+#pragma unroll
+      for (int b = 0; b < kMaxBands; ++b) {
+        bua[b] = 1;
+        buz[b] = 0;
+      }
+    }
     const uint32_t rowbase = PI.tile_off + (uint32_t)ty * (uint32_t)PI.ntx;
     for (int tx = tx0; tx <= tx1; ++tx) {
       if (e < e_end) {

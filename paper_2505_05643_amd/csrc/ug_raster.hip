@@ -14,9 +14,9 @@
 // list: per pixel-record pair two FMAs give the exponent, one compare
 // applies the cut-off and one v_exp_f32 gives the weight.
 //
-// Adjoint: a wave takes a chunk of keys and expands them into (key,
-// sub-block) items through an LDS queue; lanes = items, each walking its 64
-// pixels and accumulating the record's seven partial derivatives in
+// Adjoint: a wave takes 64 keys and expands them into (key, sub-block)
+// items through an LDS queue in key order; lanes = items, each walking its
+// 64 pixels and accumulating the record's seven partial derivatives in
 // registers.  The items of a key are summed in sub-block order into the
 // key's partial, so no atomic is needed and the result is deterministic.
 #include "ug_kernels.h"
@@ -199,13 +199,13 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const PlaneInt* __restrict__ p
 }
 
 // ---------------------------------------------------------------- backward
-// Keys per wave chunk: the chunk's (key, sub-block) slots fit 256 entries.
-template <int TW, int TH>
-struct BwdShape {
-  static constexpr int K = TW / kSubBlock, NB = TH / kSubBlock, Q = K * NB;
-  static constexpr int KC = Q <= 4 ? 64 : 256 / Q;
-  static constexpr int SLOTS = KC * Q;
-};
+// A wave loads 64 keys; their touched 8x8 sub-blocks become items (key,
+// sub-block), queued in key order, and lanes = items (64 pixels each).  An
+// item's seven sums go to an LDS slot; once a sub-chunk's items are done
+// each key adds its slots in sub-block order.  A sub-chunk is the longest
+// run of the wave's keys whose items fit the slots (at least one key: a key
+// has at most 16 items).
+constexpr int kBwdSlots = 256;
 
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl, const PlaneInt* __restrict__ pint,
@@ -216,25 +216,25 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
                                                    const uint32_t* __restrict__ smask,
                                                    const RecAcc* __restrict__ racc, const RecGeo* __restrict__ rgeo,
                                                    const float2* __restrict__ gq, float4* __restrict__ partial) {
-  using S = BwdShape<TW, TH>;
-  constexpr int K = S::K, Q = S::Q, KC = S::KC, SLOTS = S::SLOTS;
-  // per wave: key parameters, the item queue and one 7-sum slot per item
-  __shared__ float4 kpA[4][KC];      // t11, t12, t22, -t11 du0
-  __shared__ float4 kpB[4][KC];      // du0, dv0, e0, emin
-  __shared__ float kpC[4][KC];       // c
-  __shared__ uint32_t kpT[4][KC];    // tile
-  __shared__ uint16_t queue[4][SLOTS];
-  __shared__ float slot[4][SLOTS][7];
+  constexpr int K = TW / kSubBlock, Q = K * (TH / kSubBlock);
+  static_assert(Q <= 32 && kBwdSlots >= Q, "sub-blocks per tile");
+  __shared__ float4 kpA[4][64];     // t11, t12, t22, -t11 du0
+  __shared__ float4 kpB[4][64];     // du0, dv0, e0, emin
+  __shared__ float kpC[4][64];      // c
+  __shared__ uint32_t kpT[4][64];   // tile
+  __shared__ uint32_t qoff[4][65];  // first item of each key
+  __shared__ uint16_t queue[4][kBwdSlots];
+  __shared__ float slot[4][7][kBwdSlots];
   const uint32_t n = ctrl->n_key_eff;
   const float ln2 = (float)kLn2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t nchunks = (n + KC - 1u) / KC;
+  const uint32_t nchunks = (n + 63u) / 64u;
   const uint32_t W = gridDim.x * 4u;
   const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x) * 4u + (uint32_t)wave;
   for (uint32_t chunk = wid; chunk < nchunks; chunk += W) {
-    // ---- load the chunk's keys and queue their touched sub-blocks
-    const uint32_t i = chunk * KC + (uint32_t)lane;
-    const bool act = lane < KC && i < n;
+    // ---- load the chunk's keys; item offsets in key order
+    const uint32_t i = chunk * 64u + (uint32_t)lane;
+    const bool act = i < n;
     uint32_t m = 0u;
     if (act) {
       m = smask[i];
@@ -253,106 +253,122 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
       kpC[wave][lane] = A.c;
       kpT[wave][lane] = t;
     }
-    uint32_t L = 0;
+    const uint32_t pop = (uint32_t)__popc(m);
+    uint32_t x = pop;
 #pragma unroll
-    for (int sb = 0; sb < Q; ++sb) {
-      const bool on = (m >> sb) & 1u;
-      const unsigned long long bal = __ballot(on);
-      if (on) queue[wave][L + lanemask_lt_popc(bal)] = (uint16_t)(lane | (sb << 8));
-      L += (uint32_t)__popcll(bal);
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
     }
+    const uint32_t off = x - pop;
+    qoff[wave][lane] = off;
+    if (lane == 63) qoff[wave][64] = x;
     wave_lds_sync();
-    // ---- lanes = items: 8x8 pixels of one key each
-    for (uint32_t q0 = 0; q0 < L; q0 += 64) {
-      const uint32_t q = q0 + (uint32_t)lane;
-      const bool has = q < L;
-      const uint32_t ent = has ? (uint32_t)queue[wave][q] : 0u;
-      const int kl = (int)(ent & 255u), sb = (int)(ent >> 8);
-      const float4 a = kpA[wave][kl];
-      const float4 b = kpB[wave][kl];
-      const float c = kpC[wave][kl];
-      const uint32_t t = kpT[wave][kl];
-      const float t11 = a.x, t12 = a.y, t22 = a.z, P = a.w;
-      const float e0 = b.z, emin = has ? b.w : INFINITY;
-      const int bx = (sb % K) * kSubBlock, by = (sb / K) * kSubBlock;
-      const float2* __restrict__ px = gq + (size_t)t * (TW * TH) + by * TW + bx;
-      float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
-      // rows of gamma are fetched one row ahead of their use
-      const float4* __restrict__ pq = reinterpret_cast<const float4*>(px);
-      float4 cur[kSubBlock / 2];
-#pragma unroll
-      for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = pq[x2];
-#pragma unroll
-      for (int y = 0; y < kSubBlock; ++y) {
-        float4 nxt[kSubBlock / 2];
-        if (y + 1 < kSubBlock) {
-#pragma unroll
-          for (int x2 = 0; x2 < kSubBlock / 2; ++x2) nxt[x2] = pq[(y + 1) * (TW / 2) + x2];
+    float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < 64;) {
+      // ---- the sub-chunk: keys [k0, k1) whose items fit the slots
+      const uint32_t base = qoff[wave][k0];
+      const bool fits = lane >= k0 && qoff[wave][lane + 1] - base <= (uint32_t)kBwdSlots;
+      const int k1 = k0 + (int)__popcll(__ballot(fits));
+      const uint32_t L = qoff[wave][k1] - base;
+      if (lane >= k0 && lane < k1) {
+        uint32_t mm = m;
+        uint32_t q = off - base;
+        while (mm) {
+          const uint32_t sb = (uint32_t)__builtin_ctz(mm);
+          queue[wave][q++] = (uint16_t)((uint32_t)lane | (sb << 8));
+          mm &= mm - 1u;
         }
-        const float dv = (float)(by + y) - b.y;
-        const float B = fmaf(t12, dv, P);
-        const float t2 = t22 * dv;
-        const float erow = fmaf(-t2, t2, e0);
-        if (__any(erow >= emin)) {  // else no item's ellipse reaches this row
-          float rge = 0.f, ra = 0.f;
+      }
+      wave_lds_sync();
+      // ---- lanes = items: 8x8 pixels of one key each
+      for (uint32_t q0 = 0; q0 < L; q0 += 64) {
+        const uint32_t q = q0 + (uint32_t)lane;
+        const bool has = q < L;
+        const uint32_t ent = has ? (uint32_t)queue[wave][q] : (uint32_t)k0;
+        const int kl = (int)(ent & 255u), sb = (int)(ent >> 8);
+        const float4 a = kpA[wave][kl];
+        const float4 b = kpB[wave][kl];
+        const float c = kpC[wave][kl];
+        const uint32_t t = kpT[wave][kl];
+        const float t11 = a.x, t12 = a.y, t22 = a.z, P = a.w;
+        const float e0 = b.z, emin = has ? b.w : INFINITY;
+        const int bx = (sb % K) * kSubBlock, by = (sb / K) * kSubBlock;
+        const float4* __restrict__ pq = reinterpret_cast<const float4*>(gq + (size_t)t * (TW * TH) + by * TW + bx);
+        float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
+        // rows of gamma are fetched one row ahead of their use
+        float4 cur[kSubBlock / 2];
 #pragma unroll
-          for (int x2 = 0; x2 < kSubBlock / 2; ++x2) {
-            const float4 gg2 = cur[x2];
+        for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = pq[x2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const float gx = h ? gg2.z : gg2.x, gy = h ? gg2.w : gg2.y;
-              const float xf = (float)(bx + 2 * x2 + h);
-              const float t1 = fmaf(t11, xf, B);
-              const float ee = fmaf(-t1, t1, erow);
-              const float w = ee >= emin ? fast_exp2(ee) : 0.f;
-              const float gw = fmaf(gx, c, -gy);  // dL/dw = gamma (c - c_hat)
-              const float ge = w * gw;
-              rge += ge;
-              Sdc = fmaf(gx, w, Sdc);
-              const float av = ge * t1;
-              ra += av;
-              Sau = fmaf(av, xf, Sau);
-            }
+        for (int y = 0; y < kSubBlock; ++y) {
+          float4 nxt[kSubBlock / 2];
+          if (y + 1 < kSubBlock) {
+#pragma unroll
+            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) nxt[x2] = pq[(y + 1) * (TW / 2) + x2];
           }
-          Sge += rge;
-          Sa += ra;
-          S12 = fmaf(dv, ra, S12);
-          Sb = fmaf(t2, rge, Sb);
-          S22 = fmaf(t2 * dv, rge, S22);
-        }
-        if (y + 1 < kSubBlock) {
+          const float dv = (float)(by + y) - b.y;
+          const float B = fmaf(t12, dv, P);
+          const float t2 = t22 * dv;
+          const float erow = fmaf(-t2, t2, e0);
+          if (__any(erow >= emin)) {  // else no item's ellipse reaches this row
+            float rge = 0.f, ra = 0.f;
 #pragma unroll
-          for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = nxt[x2];
+            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) {
+              const float4 gg2 = cur[x2];
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const float gx = h ? gg2.z : gg2.x, gy = h ? gg2.w : gg2.y;
+                const float xf = (float)(bx + 2 * x2 + h);
+                const float t1 = fmaf(t11, xf, B);
+                const float ee = fmaf(-t1, t1, erow);
+                const float w = ee >= emin ? fast_exp2(ee) : 0.f;
+                const float gw = fmaf(gx, c, -gy);  // dL/dw = gamma (c - c_hat)
+                const float ge = w * gw;
+                rge += ge;
+                Sdc = fmaf(gx, w, Sdc);
+                const float av = ge * t1;
+                ra += av;
+                Sau = fmaf(av, xf, Sau);
+              }
+            }
+            Sge += rge;
+            Sa += ra;
+            S12 = fmaf(dv, ra, S12);
+            Sb = fmaf(t2, rge, Sb);
+            S22 = fmaf(t2 * dv, rge, S22);
+          }
+          if (y + 1 < kSubBlock) {
+#pragma unroll
+            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = nxt[x2];
+          }
+        }
+        if (has) {
+          slot[wave][0][q] = Sge;
+          slot[wave][1][q] = Sa;
+          slot[wave][2][q] = Sau;
+          slot[wave][3][q] = S12;
+          slot[wave][4][q] = S22;
+          slot[wave][5][q] = Sb;
+          slot[wave][6][q] = Sdc;
         }
       }
-      if (has) {
-        float* o = slot[wave][kl * Q + sb];
-        o[0] = Sge;
-        o[1] = Sa;
-        o[2] = Sau;
-        o[3] = S12;
-        o[4] = S22;
-        o[5] = Sb;
-        o[6] = Sdc;
+      wave_lds_sync();
+      // ---- each key adds its items in sub-block order
+      if (lane >= k0 && lane < k1) {
+        const uint32_t q1 = off - base + pop;
+        for (uint32_t q = off - base; q < q1; ++q) {
+#pragma unroll
+          for (int f = 0; f < 7; ++f) acc[f] += slot[wave][f][q];
+        }
       }
+      wave_lds_sync();  // the next sub-chunk rewrites the queue and the slots
+      k0 = k1;
     }
-    wave_lds_sync();
-    // ---- per key: its items in sub-block order, then the partials
     if (act) {
-      float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
-      for (int sb = 0; sb < Q; ++sb) {
-        if (!((m >> sb) & 1u)) continue;
-        const float* o = slot[wave][lane * Q + sb];
-        Sge += o[0];
-        Sa += o[1];
-        Sau += o[2];
-        S12 += o[3];
-        S22 += o[4];
-        Sb += o[5];
-        Sdc += o[6];
-      }
       const float4 a = kpA[wave][lane];
       const float du0 = kpB[wave][lane].x;
+      const float Sge = acc[0], Sa = acc[1], Sau = acc[2], S12 = acc[3], S22 = acc[4], Sb = acc[5], Sdc = acc[6];
       // w = 2^(e0 - t1^2 - t2^2):  dL/ds = -ln2 w dL/dw, s = t1^2 + t2^2.
       const float k2 = 2.f * ln2;
       const uint32_t eidx = sval[i];
@@ -452,11 +468,10 @@ hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const Plan
                             const float* gq, float* partial, uint32_t key_cap, hipStream_t s) {
   const float2* g2 = reinterpret_cast<const float2*>(gq);
   float4* p4 = reinterpret_cast<float4*>(partial);
+  uint32_t want = (key_cap / 64u + 4u) / 4u;
+  const uint32_t blocks = want < 1u ? 1u : (want > 16384u ? 16384u : want);
 #define UG_BWD(W, H)                                                                                          \
   if (tile_w == W && tile_h == H) {                                                                           \
-    const uint32_t kc = (uint32_t)BwdShape<W, H>::KC;                                                         \
-    uint32_t want = (key_cap / kc + 4u) / 4u;                                                                 \
-    const uint32_t blocks = want < 1u ? 1u : (want > 16384u ? 16384u : want);                                 \
     hipLaunchKernelGGL((k_accum_bwd<W, H>), dim3(blocks), dim3(256), 0, s, ctrl, pint, tile_plane, skey, sval, \
                        srec, smask, racc, rgeo, g2, p4);                                                      \
     return hipGetLastError();                                                                                 \

@@ -6,6 +6,7 @@
 namespace ug {
 
 constexpr int kSortThreads = 256;
+constexpr uint32_t kSortMaxBlocks = 2048;
 
 // Contiguous chunk of the n keys owned by block b of G (multiple of 256).
 __device__ __forceinline__ void sort_chunk(uint32_t n, uint32_t G, uint32_t b, uint32_t& s, uint32_t& e) {
@@ -20,14 +21,14 @@ __device__ __forceinline__ void sort_chunk(uint32_t n, uint32_t G, uint32_t b, u
 // Per-block digit histogram, block-major: cnt[b * 256 + d].
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Ctrl* __restrict__ ctrl,
                                                               const uint32_t* __restrict__ keys, uint32_t G,
-                                                              int shift, uint32_t* __restrict__ cnt) {
+                                                              int shift, uint32_t dmask, uint32_t* __restrict__ cnt) {
   __shared__ uint32_t h[4][256];
   for (int j = threadIdx.x; j < 1024; j += kSortThreads) (&h[0][0])[j] = 0u;
   __syncthreads();
   uint32_t s, e;
   sort_chunk(ctrl->n_key_eff, G, blockIdx.x, s, e);
   const int wave = threadIdx.x >> 6;
-  for (uint32_t i = s + threadIdx.x; i < e; i += kSortThreads) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
+  for (uint32_t i = s + threadIdx.x; i < e; i += kSortThreads) atomicAdd(&h[wave][(keys[i] >> shift) & dmask], 1u);
   __syncthreads();
   const int d = threadIdx.x;
   cnt[(size_t)blockIdx.x * 256 + d] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
@@ -81,22 +82,23 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Stable scatter.  The block's chunk is walked in rounds of 2048 keys; in a
-// round wave w owns the 512 consecutive keys [w * 512, (w + 1) * 512),
-// loaded 64 at a time.  Each wave ranks its keys on its own: lanes holding
-// the same digit are found with eight ballots, and a per-wave digit counter
+// Stable scatter.  The block's chunk is walked in rounds of up to 4096 keys;
+// in a round wave w owns the w-th quarter of the round's keys (rounded up to
+// whole loads of 64), loaded 64 at a time.  Each wave ranks its keys on its own: lanes holding
+// the same digit are found with one ballot per digit bit, and a per-wave digit counter
 // in LDS orders the wave's loads.  One block step then orders the waves and
 // the digits, the round is reordered by digit in LDS and written out as
 // contiguous runs per digit, so the global writes coalesce.
-constexpr int kItems = 8;
-constexpr int kRound = kSortThreads * kItems;
-constexpr int kWaveKeys = 64 * kItems;
+// kItems keys per thread and round: 8 for small inputs (more blocks, less
+// LDS), 16 when every block walks several rounds.
 
+template <int kItems>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ cnt,
-    const uint32_t* __restrict__ coltot, uint32_t G, int shift, const uint32_t* __restrict__ rec_of_key,
+    const uint32_t* __restrict__ coltot, uint32_t G, int shift, int dbits, const uint32_t* __restrict__ rec_of_key,
     uint32_t* __restrict__ srec, const uint32_t* __restrict__ kmask, uint32_t* __restrict__ smask) {
+  constexpr int kRound = kSortThreads * kItems;
   __shared__ uint32_t s_key[kRound];
   __shared__ uint32_t s_val[kRound];
   __shared__ uint32_t run[256];      // global output position of the next key of each digit
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   __shared__ uint32_t wcnt[4][256];  // per-wave digit counts, then the waves' prefixes
   __shared__ uint32_t sh[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t dmask = (1u << dbits) - 1u;
   uint32_t s, e;
   sort_chunk(ctrl->n_key_eff, G, blockIdx.x, s, e);
   {
@@ -126,16 +129,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 #pragma unroll
     for (int j = 0; j < 4; ++j) wcnt[wave][lane + 64 * j] = 0u;
     wave_lds_sync();
+    // the round's keys split evenly over the waves, in whole loads of 64
+    const uint32_t n_round = min((uint32_t)kRound, e - base);
+    const uint32_t seg = ((n_round + 255u) / 256u) * 64u;
     uint32_t kk[kItems], vv[kItems], rr[kItems];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-      const uint32_t i = base + (uint32_t)(wave * kWaveKeys + it * 64 + lane);
-      const bool valid = i < e;
+      const uint32_t i = base + (uint32_t)wave * seg + (uint32_t)(it * 64 + lane);
+      const bool valid = (uint32_t)(it * 64) < seg && i < e;
       const uint32_t k = valid ? kin[i] : 0u;
-      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t d = (k >> shift) & dmask;
       unsigned long long peers = __ballot(valid);
-#pragma unroll
-      for (int bit = 0; bit < 8; ++bit) {
+      for (int bit = 0; bit < dbits; ++bit) {
         const bool on = (d >> bit) & 1u;
         const unsigned long long bm = __ballot(on);
         peers &= on ? bm : ~bm;
@@ -174,17 +179,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       if (rr[it] != 0xffffffffu) {
-        const uint32_t d = (kk[it] >> shift) & 255u;
+        const uint32_t d = (kk[it] >> shift) & dmask;
         const uint32_t slot = loc[d] + wcnt[wave][d] + rr[it];
         s_key[slot] = kk[it];
         s_val[slot] = vv[it];
       }
     }
     __syncthreads();
-    const uint32_t n_round = min((uint32_t)kRound, e - base);
     for (uint32_t i = tid; i < n_round; i += kSortThreads) {
       const uint32_t k = s_key[i], v = s_val[i];
-      const uint32_t d = (k >> shift) & 255u;
+      const uint32_t d = (k >> shift) & dmask;
       const uint32_t pos = run[d] + (i - loc[d]);
       kout[pos] = k;
       vout[pos] = v;
@@ -218,18 +222,29 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const Ctrl* __restrict__ ct
   }
 }
 
+// Blocks of the sort: chunks of at least 2048 keys (half a round), at most
+// 2048 blocks (larger inputs walk several full rounds per block).
 uint32_t sort_blocks_for(uint32_t key_cap) {
   uint32_t g = (key_cap + 2047u) / 2048u;
   if (g < 1) g = 1;
-  if (g > 4096) g = 4096;
+  if (g > kSortMaxBlocks) g = kSortMaxBlocks;
   return g;
 }
 
 int sort_passes(int bits) { return (bits + 7) / 8 < 1 ? 1 : (bits + 7) / 8; }
 
-hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t G, int pass,
+// Digit width: the key bits split evenly over the passes (at most 8), so
+// small tile counts get fewer digits and longer runs per digit.
+static int digit_bits(int bits) {
+  const int p = sort_passes(bits);
+  const int d = (bits + p - 1) / p;
+  return d < 1 ? 1 : d;
+}
+
+hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t G, int bits, int pass,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys, G, 8 * pass, hist);
+  const int db = digit_bits(bits);
+  hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys, G, db * pass, (1u << db) - 1u, hist);
   return hipGetLastError();
 }
 
@@ -239,12 +254,19 @@ hipError_t launch_radix_colscan(uint32_t* hist, uint32_t G, hipStream_t s) {
 }
 
 hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
-                                uint32_t* vals_out, const uint32_t* hist, uint32_t G, int pass,
+                                uint32_t* vals_out, const uint32_t* hist, uint32_t G, int bits, int pass,
                                 const uint32_t* rec_of_key, uint32_t* srec, const uint32_t* kmask, uint32_t* smask,
                                 hipStream_t s) {
   if ((srec == nullptr) != (smask == nullptr)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys_in, pass == 0 ? nullptr : vals_in,
-                     keys_out, vals_out, hist, hist + (size_t)256 * G, G, 8 * pass, rec_of_key, srec, kmask, smask);
+  const int db = digit_bits(bits);
+  if (G >= kSortMaxBlocks)
+    hipLaunchKernelGGL(k_radix_scatter<16>, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys_in,
+                       pass == 0 ? nullptr : vals_in, keys_out, vals_out, hist, hist + (size_t)256 * G, G, db * pass, db,
+                       rec_of_key, srec, kmask, smask);
+  else
+    hipLaunchKernelGGL(k_radix_scatter<8>, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys_in,
+                       pass == 0 ? nullptr : vals_in, keys_out, vals_out, hist, hist + (size_t)256 * G, G, db * pass, db,
+                       rec_of_key, srec, kmask, smask);
   return hipGetLastError();
 }
 
