@@ -372,24 +372,25 @@ def kernel_bytes(name, n, p, r, k, t, m, passes, w, rows, g_sort) -> int:
     return 0
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_per_kernel_c1.md")
 
 
 def stored_traffic(kernel, k, params, plan):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    runs (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), if they were
-    taken on this workload and launch configuration with the current kernel
-    sources; else None."""
+    runs (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a plain
+    copy kernel), if they were taken on this workload and launch configuration
+    with the current kernel sources; else None.  The summary file carries them
+    on a line starting with "traffic-json: "."""
     try:
         with open(TRAFFIC_FILE) as f:
-            rec = json.load(f)
+            line = next((ln for ln in f if ln.startswith("traffic-json: ")), None)
+        rec = json.loads(line[len("traffic-json: "):]) if line else {}
     except (OSError, ValueError):
         return None
     key = f"c{k}:{kernel}:{params.tile_w}x{params.tile_h}x{plan_ppl(params)}:{params.lds_batch}:{params.box_mode}"
-    ent = rec.get(key)
-    if not ent or ent.get("sources") != sources_digest():
+    if rec.get("sources") != sources_digest():
         return None
-    return ent.get("bytes_per_launch")
+    return rec.get("bytes_per_launch", {}).get(key)
 
 
 def sources_digest() -> str:

@@ -120,6 +120,8 @@ void ug_params_default(ug_params *out);
  * render; ug_plan_measure returns the exact numbers for given inputs.
  * Allocates the plan's small device tables on the current device.
  * Errors: UG_ERR_INVALID_ARG (n < 0, p < 1, W or H outside [1, 32767],
+ * more than 2^(32 - Q) tiles in the launch, Q = (tile_w / 8) (tile_h / 8)
+ * (a key word carries the tile id and the tile's Q-bit sub-block mask),
  * bad params, capacities < 0 or >= 2^31, null out), UG_ERR_HIP. */
 int ug_plan_create(int32_t n, int32_t p, const int32_t *wh_host, const ug_params *params,
                    int64_t record_capacity, int64_t key_capacity, ug_plan **out);

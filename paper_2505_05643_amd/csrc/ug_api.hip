@@ -18,7 +18,7 @@ struct Layout {
   size_t ctrl, pconst, pcull, cnt_rec, accbits, off_rec, blk_g, blk_r;
   size_t rec_pair, racc, rgeo, rec_nkey, rec_koff, side;
   size_t tile_start, dsave, gq, hist;
-  size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, kmask, smask, partial;
+  size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, partial;
   size_t total;
 };
 
@@ -86,8 +86,6 @@ void compute_layout(ug_plan* pl) {
   L.key_val1 = take(K * 4);
   L.rec_of_key = take(K * 4);
   L.srec = take(K * 4);
-  L.kmask = take(K * 4);
-  L.smask = take(K * 4);
   L.partial = take(K * 32);
   L.total = o;
 }
@@ -201,24 +199,25 @@ hipError_t enqueue_preprocess(const ug_plan* plan, const ug_gaussians& g, const 
   StageScope sc(plan, UG_STAGE_EMIT, s);
   return launch_emit(plan->d_pint, rp, at<uint2>(ws, L.rec_pair), at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo),
                      at<uint32_t>(ws, L.rec_nkey), at<uint32_t>(ws, L.blk_r), at<uint32_t>(ws, L.rec_koff), ctrl,
-                     at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.rec_of_key), at<uint32_t>(ws, L.kmask), s);
+                     at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.rec_of_key), s);
 }
 
-// The radix sort of the emitted keys, one launch per kernel and pass.
+// The radix sort of the emitted keys, one launch per kernel and pass.  Set 0
+// = (key_tile0, key_val0, rec_of_key) holds the emitted keys; passes
+// alternate between set 0 and set 1 = (key_tile1, key_val1, srec).
 hipError_t enqueue_sort(const ug_plan* plan, void* ws, hipStream_t s) {
   const Layout& L = plan->lay;
   const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
-  uint32_t* kb[2] = {at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.key_tile1)};
-  uint32_t* vb[2] = {at<uint32_t>(ws, L.key_val0), at<uint32_t>(ws, L.key_val1)};
+  uint32_t* set[2][3] = {{at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.key_val0), at<uint32_t>(ws, L.rec_of_key)},
+                         {at<uint32_t>(ws, L.key_tile1), at<uint32_t>(ws, L.key_val1), at<uint32_t>(ws, L.srec)}};
   uint32_t* hist = at<uint32_t>(ws, L.hist);
   const uint32_t G = plan->sort_blocks;
   const int passes = sort_passes(plan->bits);
   hipError_t e = hipSuccess;
   for (int pass = 0, cur = 0; pass < passes && e == hipSuccess; ++pass, cur ^= 1) {
-    const bool last = pass == passes - 1;
     {
       StageScope sc(plan, UG_STAGE_SORT_HIST, s);
-      e = launch_radix_hist(ctrl, kb[cur], hist, G, plan->bits, pass, s);
+      e = launch_radix_hist(ctrl, set[cur][0], hist, G, plan->bits, pass, s);
     }
     if (e != hipSuccess) break;
     {
@@ -227,11 +226,20 @@ hipError_t enqueue_sort(const ug_plan* plan, void* ws, hipStream_t s) {
     }
     if (e != hipSuccess) break;
     StageScope sc(plan, UG_STAGE_SORT_SCATTER, s);
-    e = launch_radix_scatter(ctrl, kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], hist, G, plan->bits, pass,
-                             last ? at<uint32_t>(ws, L.rec_of_key) : nullptr, last ? at<uint32_t>(ws, L.srec) : nullptr,
-                             last ? at<uint32_t>(ws, L.kmask) : nullptr, last ? at<uint32_t>(ws, L.smask) : nullptr, s);
+    const uint32_t* in[3] = {set[cur][0], set[cur][1], set[cur][2]};
+    e = launch_radix_scatter(ctrl, in, set[cur ^ 1], hist, G, plan->bits, pass, s);
   }
   return e;
+}
+
+// Sorted arrays {key word, emission index, record id} left by the sort.
+struct Sorted {
+  const uint32_t *key, *val, *rec;
+};
+Sorted sorted_set(const ug_plan* plan, void* ws) {
+  const Layout& L = plan->lay;
+  if (plan->final_buf) return {at<uint32_t>(ws, L.key_tile1), at<uint32_t>(ws, L.key_val1), at<uint32_t>(ws, L.srec)};
+  return {at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.key_val0), at<uint32_t>(ws, L.rec_of_key)};
 }
 
 }  // namespace
@@ -278,7 +286,8 @@ int ug_plan_create(int32_t n, int32_t p, const int32_t* wh_host, const ug_params
     q.pad = 0;
     tiles += (uint64_t)q.ntx * q.nty;
     pix += (uint64_t)W * H;
-    if (tiles >= (uint64_t(1) << 31)) return UG_ERR_INVALID_ARG;
+    // tile ids share the key word with the tile's sub-block mask
+    if (tiles > (uint64_t(1) << key_mask_shift(TW, TH))) return UG_ERR_INVALID_ARG;
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return UG_ERR_NO_DEVICE;
@@ -374,18 +383,17 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
   if (e != hipSuccess) return UG_ERR_HIP;
   e = enqueue_sort(plan, ws, s);
   if (e != hipSuccess) return UG_ERR_HIP;
-  const int fb = plan->final_buf;
-  const uint32_t* skeys = at<uint32_t>(ws, fb ? L.key_tile1 : L.key_tile0);
+  const Sorted so = sorted_set(plan, ws);
   {
     StageScope sc(plan, UG_STAGE_RANGES, s);
-    e = launch_tile_ranges(ctrl, skeys, plan->num_tiles, at<uint32_t>(ws, L.tile_start), s);
+    e = launch_tile_ranges(ctrl, so.key, plan->num_tiles, key_mask_shift(plan->prm.tile_w, plan->prm.tile_h),
+                           at<uint32_t>(ws, L.tile_start), s);
   }
   if (e != hipSuccess) return UG_ERR_HIP;
   unsigned long long* n_eval = (plan->prm.flags & UG_FLAG_COUNT_EVALS) ? &ctrl->n_eval : nullptr;
   StageScope sc(plan, UG_STAGE_ACCUM, s);
   e = launch_accum_fwd(plan->prm.tile_w, plan->prm.tile_h, plan->prm.lds_batch, plan->d_pint, plan->d_tile_plane,
-                       at<uint32_t>(ws, L.tile_start), at<uint32_t>(ws, L.srec), at<uint32_t>(ws, L.smask),
-                       at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), image, at<float>(ws, L.dsave),
+                       at<uint32_t>(ws, L.tile_start), so.key, so.rec, at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), image, at<float>(ws, L.dsave),
                        plan->prm.bg_alpha, plan->prm.bg_color, plan->num_tiles, n_eval, s);
   return hip_status(e);
 }
@@ -404,7 +412,7 @@ int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const 
   void* ws = workspace;
   const RenderParams rp = make_rp(plan);
   const Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
-  const int fb = plan->final_buf;
+  const Sorted so = sorted_set(plan, ws);
   hipError_t e;
   {
     StageScope sc(plan, UG_STAGE_BWD_PREP, s);
@@ -415,9 +423,8 @@ int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const 
   {
     StageScope sc(plan, UG_STAGE_ACCUM_BWD, s);
     e = launch_accum_bwd(plan->prm.tile_w, plan->prm.tile_h, ctrl, plan->d_pint, plan->d_tile_plane,
-                         at<uint32_t>(ws, fb ? L.key_tile1 : L.key_tile0),
-                         at<uint32_t>(ws, fb ? L.key_val1 : L.key_val0), at<uint32_t>(ws, L.srec),
-                         at<uint32_t>(ws, L.smask), at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<float>(ws, L.gq),
+                         so.key, so.val, so.rec, at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo),
+                         at<float>(ws, L.gq),
                          at<float>(ws, L.partial), plan->key_cap, s);
   }
   if (e != hipSuccess) return UG_ERR_HIP;

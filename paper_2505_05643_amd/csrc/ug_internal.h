@@ -86,6 +86,13 @@ constexpr int kGradFields = 11;
 // and heights are multiples of it).
 constexpr int kSubBlock = 8;
 
+// A key word holds the tile id in its low bits and the tile's sub-block
+// coverage mask (Q = (TW / 8) (TH / 8) bits) in its top Q bits, so the sort
+// moves the mask with the key; tile ids must stay below 2^(32 - Q).
+__host__ __device__ constexpr int key_mask_shift(int tile_w, int tile_h) {
+  return 32 - (tile_w / kSubBlock) * (tile_h / kSubBlock);
+}
+
 struct RecAcc {
   float t11, t12, t22, fu;
   float fv, e0, emin, c;

@@ -19,13 +19,14 @@ hipError_t launch_cull_write(const RenderParams& rp, const uint32_t* cnt_rec, co
                              const uint32_t* blk_tot, unsigned long long* off_rec, uint2* rec_pair, Ctrl* ctrl,
                              hipStream_t s);
 // Records (conic + footprint and per-record key counts), then key offsets and
-// key emission: per key its tile id, record id and sub-block mask.
+// key emission: per key its key word (tile id and sub-block mask) and record
+// id.
 hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
                          const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* blk_tot,
                          Ctrl* ctrl, hipStream_t s);
 hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const RecAcc* racc,
                        const RecGeo* rgeo, const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
-                       Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, uint32_t* kmask, hipStream_t s);
+                       Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, hipStream_t s);
 // Backward of the record construction and the per-Gaussian sums: the record
 // adjoint finishes every Gaussian whose records sit in one wave of 64 and
 // leaves per-wave segment sums in side (adjoint_side_floats floats); the
@@ -41,30 +42,30 @@ hipError_t launch_gauss_grad(const ug_gaussians& g, const RenderParams& rp, cons
                              float* d_int, float* d_op, int accumulate, hipStream_t s);
 
 // ---- tile binning sort (ug_sort.hip)
-// Stable LSD radix sort of (tile id, emission index) pairs on `bits` key
-// bits, at most 8 per pass (sort_passes(bits) passes over ping-pong buffers,
-// the bits split evenly between them; pass k reads buffer
-// k%2 and writes buffer (k+1)%2).  Per pass: block-major digit histograms
-// (hist holds 256 * (nblocks + 1) words), their column scan, then the stable
-// scatter; the last pass also gathers rec_of_key[] and kmask[] into srec and
-// smask in sorted order.
+// Stable LSD radix sort of the key words on their low `bits` bits (the tile
+// id), at most 8 per pass (sort_passes(bits) passes, the bits split evenly
+// between them), moving two payload words per key: emission index
+// (generated in the first pass) and record id.  Arrays are given as {key,
+// val, rec}; passes alternate between two such sets.  Per pass:
+// block-major digit histograms (hist holds 256 * (nblocks + 1) words),
+// their column scan, then the stable scatter.
 int sort_passes(int bits);
 hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t nblocks, int bits,
                              int pass, hipStream_t s);
 hipError_t launch_radix_colscan(uint32_t* hist, uint32_t nblocks, hipStream_t s);
-hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
-                                uint32_t* vals_out, const uint32_t* hist, uint32_t nblocks, int bits, int pass,
-                                const uint32_t* rec_of_key, uint32_t* srec, const uint32_t* kmask, uint32_t* smask,
-                                hipStream_t s);
-hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, uint32_t* tile_start,
-                              hipStream_t s);
+hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], uint32_t* const out[3],
+                                const uint32_t* hist, uint32_t nblocks, int bits, int pass, hipStream_t s);
+// tile_start[t] for t in [0, T] from the sorted key words (tile id = the key
+// word's bits below mask_shift).
+hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, int mask_shift,
+                              uint32_t* tile_start, hipStream_t s);
 uint32_t sort_blocks_for(uint32_t key_cap);
 
 // ---- accumulate (ug_raster.hip)
 int accum_default_ppl(int tile_w, int tile_h);
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);
 hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneInt* pint, const uint32_t* tile_plane,
-                            const uint32_t* tile_start, const uint32_t* srec, const uint32_t* smask,
+                            const uint32_t* tile_start, const uint32_t* skey, const uint32_t* srec,
                             const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave, float bg_alpha,
                             float bg_color, uint32_t num_tiles, unsigned long long* n_eval, hipStream_t s);
 hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const uint32_t* tile_plane,
@@ -72,7 +73,7 @@ hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const u
                            uint32_t num_tiles, hipStream_t s);
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const PlaneInt* pint,
                             const uint32_t* tile_plane, const uint32_t* skey, const uint32_t* sval,
-                            const uint32_t* srec, const uint32_t* smask, const RecAcc* racc, const RecGeo* rgeo,
+                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo,
                             const float* gq, float* partial, uint32_t key_cap, hipStream_t s);
 
 // ---- training helpers (ug_train.hip)

@@ -227,8 +227,8 @@ __global__ __launch_bounds__(256) void k_cull_write(RenderParams rp, int gpb, ui
 // covers rpb consecutive records in rounds of 256.
 __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, const PlaneInt& PI, int box_mode,
                                           int TW, int TH, uint32_t r, uint32_t e, uint32_t e_end,
-                                          uint32_t* __restrict__ key_tile, uint32_t* __restrict__ rec_of_key,
-                                          uint32_t* __restrict__ kmask) {
+                                          uint32_t* __restrict__ key_tile, uint32_t* __restrict__ rec_of_key) {
+  const int mshift = key_mask_shift(TW, TH);
   const int umin = geo.tx0 * TW;
   const int umax = min(geo.tx1 * TW + TW - 1, PI.W - 1);
   BandPrep bp;
@@ -256,9 +256,8 @@ __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, c
     const uint32_t rowbase = PI.tile_off + (uint32_t)ty * (uint32_t)PI.ntx;
     for (int tx = tx0; tx <= tx1; ++tx) {
       if (e < e_end) {
-        key_tile[e] = rowbase + (uint32_t)tx;
+        key_tile[e] = (rowbase + (uint32_t)tx) | (tile_mask(bua, buz, tx, TW) << mshift);
         rec_of_key[e] = r;
-        kmask[e] = tile_mask(bua, buz, tx, TW);
       }
       ++e;
     }
@@ -314,7 +313,7 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
                                               const RecGeo* __restrict__ rgeo, const uint32_t* __restrict__ rec_nkey,
                                               const uint32_t* __restrict__ blk_tot, uint32_t* __restrict__ rec_koff,
                                               Ctrl* __restrict__ ctrl, uint32_t* __restrict__ key_tile,
-                                              uint32_t* __restrict__ rec_of_key, uint32_t* __restrict__ kmask) {
+                                              uint32_t* __restrict__ rec_of_key) {
   __shared__ unsigned long long s_sh[4];
   const uint32_t nrec = ctrl->n_rec_eff;
   const uint32_t r_begin = blockIdx.x * (uint32_t)rpb;
@@ -333,7 +332,7 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
       rec_koff[r] = (uint32_t)(koff < rp.key_cap ? koff : rp.key_cap);
       if (nk > 0 && koff + nk <= rp.key_cap)
         emit_keys(racc[r], rgeo[r], pint[rec_pair[r].y], rp.box_mode, rp.tile_w, rp.tile_h, r, (uint32_t)koff,
-                  (uint32_t)(koff + nk), key_tile, rec_of_key, kmask);
+                  (uint32_t)(koff + nk), key_tile, rec_of_key);
     }
   }
   if (blockIdx.x == nact - 1 && threadIdx.x == 0) {
@@ -557,9 +556,9 @@ hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const Plan
 
 hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const RecAcc* racc,
                        const RecGeo* rgeo, const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
-                       Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, uint32_t* kmask, hipStream_t s) {
+                       Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, hipStream_t s) {
   hipLaunchKernelGGL(k_emit, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, pint, rp, record_rpb(rp.rec_cap),
-                     rec_pair, racc, rgeo, rec_nkey, blk_tot, rec_koff, ctrl, key_tile, rec_of_key, kmask);
+                     rec_pair, racc, rgeo, rec_nkey, blk_tot, rec_koff, ctrl, key_tile, rec_of_key);
   return hipGetLastError();
 }
 

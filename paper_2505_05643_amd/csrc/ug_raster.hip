@@ -42,7 +42,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <int TW, int TH, int BG, bool CNT>
 __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
     const PlaneInt* __restrict__ pint, const uint32_t* __restrict__ tile_plane,
-    const uint32_t* __restrict__ tile_start, const uint32_t* __restrict__ srec, const uint32_t* __restrict__ smask,
+    const uint32_t* __restrict__ tile_start, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ srec,
     const RecAcc* __restrict__ racc, const RecGeo* __restrict__ rgeo, float* __restrict__ image,
     float* __restrict__ dsave, float bg_alpha, float bg_color, unsigned long long* __restrict__ counters) {
   constexpr int K = TW / kSubBlock;   // pixels per lane = sub-blocks per band
@@ -64,7 +64,8 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
   const int lane = threadIdx.x & 63, band = threadIdx.x >> 6;
   const int lrow = lane / kSubBlock, col0 = lane % kSubBlock;
   const int row = band * kSubBlock + lrow;
-  const uint32_t bshift = (uint32_t)(band * K), bmask = (1u << K) - 1u;
+  constexpr int kMaskShift = key_mask_shift(TW, TH);
+  const uint32_t bshift = (uint32_t)(kMaskShift + band * K), bmask = (1u << K) - 1u;
   float ucol[K], Nacc[K], Dacc[K];
   uint32_t cnt[K];
   uint32_t nexec = 0;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
       const uint32_t j = base + (uint32_t)(q * 64 + lane);
       pm[q] = 0u;
       if (q * 64 + lane < BG && j < e) {
-        const uint32_t m = (smask[j] >> bshift) & bmask;
+        const uint32_t m = (skey[j] >> bshift) & bmask;
         pm[q] = m;
         if (m) {
           const uint32_t r = srec[j];
@@ -213,11 +214,11 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
                                                    const uint32_t* __restrict__ skey,
                                                    const uint32_t* __restrict__ sval,
                                                    const uint32_t* __restrict__ srec,
-                                                   const uint32_t* __restrict__ smask,
                                                    const RecAcc* __restrict__ racc, const RecGeo* __restrict__ rgeo,
                                                    const float2* __restrict__ gq, float4* __restrict__ partial) {
   constexpr int K = TW / kSubBlock, Q = K * (TH / kSubBlock);
-  static_assert(Q <= 32 && kBwdSlots >= Q, "sub-blocks per tile");
+  constexpr int kMaskShift = key_mask_shift(TW, TH);
+  static_assert(Q <= 16 && kBwdSlots >= Q, "sub-blocks per tile");
   __shared__ float4 kpA[4][64];     // t11, t12, t22, -t11 du0
   __shared__ float4 kpB[4][64];     // du0, dv0, e0, emin
   __shared__ float kpC[4][64];      // c
@@ -237,8 +238,9 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
     const bool act = i < n;
     uint32_t m = 0u;
     if (act) {
-      m = smask[i];
-      const uint32_t t = skey[i];
+      const uint32_t kw = skey[i];
+      m = kw >> kMaskShift;
+      const uint32_t t = kw & ((1u << kMaskShift) - 1u);
       const uint32_t r = srec[i];
       const RecAcc A = racc[r];
       const RecGeo Gg = rgeo[r];
@@ -393,17 +395,17 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
 
 template <int TW, int TH>
 static hipError_t fwd_bg(int bg, dim3 grid, hipStream_t s, const PlaneInt* pint, const uint32_t* tp,
-                         const uint32_t* ts, const uint32_t* srec, const uint32_t* smask, const RecAcc* ra,
+                         const uint32_t* ts, const uint32_t* skey, const uint32_t* srec, const RecAcc* ra,
                          const RecGeo* rg, float* img, float* ds, float ba, float bc, unsigned long long* n_eval) {
   constexpr int NT = 64 * (TH / kSubBlock);
   switch (bg) {
 #define UG_BG(B)                                                                                                   \
   case B:                                                                                                          \
     if (n_eval)                                                                                                    \
-      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, true>), grid, dim3(NT), 0, s, pint, tp, ts, srec, smask, ra, rg, \
+      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, true>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec, ra, rg, \
                          img, ds, ba, bc, n_eval);                                                                 \
     else                                                                                                           \
-      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, false>), grid, dim3(NT), 0, s, pint, tp, ts, srec, smask, ra, rg, \
+      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, false>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec, ra, rg, \
                          img, ds, ba, bc, n_eval);                                                                 \
     return hipGetLastError();
     UG_BG(32)
@@ -432,13 +434,13 @@ bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch) {
 }
 
 hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneInt* pint, const uint32_t* tile_plane,
-                            const uint32_t* tile_start, const uint32_t* srec, const uint32_t* smask,
+                            const uint32_t* tile_start, const uint32_t* skey, const uint32_t* srec,
                             const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave, float bg_alpha,
                             float bg_color, uint32_t num_tiles, unsigned long long* n_eval, hipStream_t s) {
   const dim3 grid(num_tiles);
 #define UG_LAUNCH_SHAPE(W, H)                                                                                   \
   if (tile_w == W && tile_h == H)                                                                               \
-    return fwd_bg<W, H>(lds_batch, grid, s, pint, tile_plane, tile_start, srec, smask, racc, rgeo, image, dsave, \
+    return fwd_bg<W, H>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, racc, rgeo, image, dsave, \
                         bg_alpha, bg_color, n_eval);
   UG_TILE_SHAPES(UG_LAUNCH_SHAPE)
 #undef UG_LAUNCH_SHAPE
@@ -464,7 +466,7 @@ hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const u
 
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const PlaneInt* pint,
                             const uint32_t* tile_plane, const uint32_t* skey, const uint32_t* sval,
-                            const uint32_t* srec, const uint32_t* smask, const RecAcc* racc, const RecGeo* rgeo,
+                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo,
                             const float* gq, float* partial, uint32_t key_cap, hipStream_t s) {
   const float2* g2 = reinterpret_cast<const float2*>(gq);
   float4* p4 = reinterpret_cast<float4*>(partial);
@@ -473,7 +475,7 @@ hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const Plan
 #define UG_BWD(W, H)                                                                                          \
   if (tile_w == W && tile_h == H) {                                                                           \
     hipLaunchKernelGGL((k_accum_bwd<W, H>), dim3(blocks), dim3(256), 0, s, ctrl, pint, tile_plane, skey, sval, \
-                       srec, smask, racc, rgeo, g2, p4);                                                      \
+                       srec, racc, rgeo, g2, p4);                                                             \
     return hipGetLastError();                                                                                 \
   }
   UG_TILE_SHAPES(UG_BWD)

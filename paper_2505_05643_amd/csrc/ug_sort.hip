@@ -92,15 +92,25 @@ __device__ __forceinline__ void wave_lds_sync() {
 // kItems keys per thread and round: 8 for small inputs (more blocks, less
 // LDS), 16 when every block walks several rounds.
 
+// Every key carries two payload words (emission index, record id).  The
+// ranking touches only the keys; the payload is read when the reordered
+// round is written out, from the round's own input window.
+struct SortSet {
+  uint32_t* key;
+  uint32_t* val;  // emission index; generated (= position) in the first pass
+  uint32_t* rec;
+};
+
 template <int kItems>
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const Ctrl* __restrict__ ctrl, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ cnt,
-    const uint32_t* __restrict__ coltot, uint32_t G, int shift, int dbits, const uint32_t* __restrict__ rec_of_key,
-    uint32_t* __restrict__ srec, const uint32_t* __restrict__ kmask, uint32_t* __restrict__ smask) {
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __restrict__ ctrl, SortSet in,
+                                                                SortSet out, bool gen_val,
+                                                                const uint32_t* __restrict__ cnt,
+                                                                const uint32_t* __restrict__ coltot, uint32_t G,
+                                                                int shift, int dbits) {
   constexpr int kRound = kSortThreads * kItems;
+  const uint32_t* __restrict__ kin = in.key;
   __shared__ uint32_t s_key[kRound];
-  __shared__ uint32_t s_val[kRound];
+  __shared__ uint32_t s_src[kRound];  // input position of the key in each slot
   __shared__ uint32_t run[256];      // global output position of the next key of each digit
   __shared__ uint32_t loc[256];      // first LDS slot of each digit in this round
   __shared__ uint32_t rcnt[256];     // keys of each digit in this round
@@ -150,7 +160,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       if (valid && lanemask_lt_popc(peers) == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
       wave_lds_sync();
       kk[it] = k;
-      vv[it] = valid ? (vin ? vin[i] : i) : 0u;
+      vv[it] = i;
       rr[it] = valid ? before + lanemask_lt_popc(peers) : 0xffffffffu;
     }
     __syncthreads();
@@ -182,20 +192,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const uint32_t d = (kk[it] >> shift) & dmask;
         const uint32_t slot = loc[d] + wcnt[wave][d] + rr[it];
         s_key[slot] = kk[it];
-        s_val[slot] = vv[it];
+        s_src[slot] = vv[it];
       }
     }
     __syncthreads();
     for (uint32_t i = tid; i < n_round; i += kSortThreads) {
-      const uint32_t k = s_key[i], v = s_val[i];
+      const uint32_t k = s_key[i], src = s_src[i];
       const uint32_t d = (k >> shift) & dmask;
       const uint32_t pos = run[d] + (i - loc[d]);
-      kout[pos] = k;
-      vout[pos] = v;
-      if (srec) {
-        srec[pos] = rec_of_key[v];
-        smask[pos] = kmask[v];
-      }
+      out.key[pos] = k;
+      out.val[pos] = gen_val ? src : in.val[src];
+      out.rec[pos] = in.rec[src];
     }
     __syncthreads();
     run[tid] += rcnt[tid];
@@ -205,7 +212,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 
 // tile_start[t] = first sorted key index whose tile id is >= t (t in [0, T]).
 __global__ __launch_bounds__(256) void k_tile_ranges(const Ctrl* __restrict__ ctrl,
-                                                     const uint32_t* __restrict__ skeys, uint32_t T,
+                                                     const uint32_t* __restrict__ skeys, uint32_t T, uint32_t tmask,
                                                      uint32_t* __restrict__ tile_start) {
   const uint32_t n = ctrl->n_key_eff;
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
@@ -214,8 +221,8 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const Ctrl* __restrict__ ct
     return;
   }
   for (uint32_t i = gid; i < n; i += stride) {
-    const uint32_t k = min(skeys[i], T - 1);  // keys are < T; the clamp only keeps writes in bounds
-    const uint32_t t0 = i ? min(skeys[i - 1], T - 1) + 1u : 0u;
+    const uint32_t k = min(skeys[i] & tmask, T - 1);  // tiles are < T; the clamp only keeps writes in bounds
+    const uint32_t t0 = i ? min(skeys[i - 1] & tmask, T - 1) + 1u : 0u;
     for (uint32_t t = t0; t <= k; ++t) tile_start[t] = i;
     if (i == n - 1)
       for (uint32_t t = k + 1; t <= T; ++t) tile_start[t] = n;
@@ -253,26 +260,24 @@ hipError_t launch_radix_colscan(uint32_t* hist, uint32_t G, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
-                                uint32_t* vals_out, const uint32_t* hist, uint32_t G, int bits, int pass,
-                                const uint32_t* rec_of_key, uint32_t* srec, const uint32_t* kmask, uint32_t* smask,
-                                hipStream_t s) {
-  if ((srec == nullptr) != (smask == nullptr)) return hipErrorInvalidValue;
+hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], uint32_t* const out[3],
+                                const uint32_t* hist, uint32_t G, int bits, int pass, hipStream_t s) {
   const int db = digit_bits(bits);
+  const SortSet si{const_cast<uint32_t*>(in[0]), const_cast<uint32_t*>(in[1]), const_cast<uint32_t*>(in[2])};
+  const SortSet so{out[0], out[1], out[2]};
   if (G >= kSortMaxBlocks)
-    hipLaunchKernelGGL(k_radix_scatter<16>, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys_in,
-                       pass == 0 ? nullptr : vals_in, keys_out, vals_out, hist, hist + (size_t)256 * G, G, db * pass, db,
-                       rec_of_key, srec, kmask, smask);
+    hipLaunchKernelGGL(k_radix_scatter<16>, dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0, hist,
+                       hist + (size_t)256 * G, G, db * pass, db);
   else
-    hipLaunchKernelGGL(k_radix_scatter<8>, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys_in,
-                       pass == 0 ? nullptr : vals_in, keys_out, vals_out, hist, hist + (size_t)256 * G, G, db * pass, db,
-                       rec_of_key, srec, kmask, smask);
+    hipLaunchKernelGGL(k_radix_scatter<8>, dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0, hist,
+                       hist + (size_t)256 * G, G, db * pass, db);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, uint32_t* tile_start,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_ranges, dim3(1024), dim3(256), 0, s, ctrl, skeys, num_tiles, tile_start);
+hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, int mask_shift,
+                              uint32_t* tile_start, hipStream_t s) {
+  const uint32_t tmask = mask_shift >= 32 ? 0xffffffffu : (1u << mask_shift) - 1u;
+  hipLaunchKernelGGL(k_tile_ranges, dim3(1024), dim3(256), 0, s, ctrl, skeys, num_tiles, tmask, tile_start);
   return hipGetLastError();
 }
 

@@ -64,7 +64,9 @@ def _create(L, n=10, wh=((16, 16),), **kw):
                                 dict(beta=float("nan")), dict(chi2=-1.0), dict(chi2=float("nan")),
                                 dict(bg_alpha=0.0), dict(box_mode=7), dict(flags=2), dict(tile_w=12),
                                 dict(lds_batch=48), dict(tile_w=8, tile_h=8, px_per_lane=2),
-                                dict(bg_color=float("inf"))])
+                                dict(bg_color=float("inf")),
+                                # 32x32 tiles leave 16 bits of the key word for the tile id: 257 x 256 tiles
+                                dict(tile_w=32, tile_h=32, wh=((8200, 8192),))])
 def test_plan_create_rejects_invalid(L, kw):
     code, out = _create(L, **kw)
     assert code == L.UG_ERR_INVALID_ARG and not out.value
@@ -72,6 +74,11 @@ def test_plan_create_rejects_invalid(L, kw):
 
 def test_plan_create_without_device_or_ok(L):
     code, out = _create(L, chi2=math.inf)
+    assert code in (L.UG_OK, L.UG_ERR_NO_DEVICE)
+    if code == L.UG_OK:
+        L.lib.ug_plan_destroy(out)
+    # exactly 2^16 tiles of 32x32 still fit the key word
+    code, out = _create(L, tile_w=32, tile_h=32, wh=((8192, 8192),))
     assert code in (L.UG_OK, L.UG_ERR_NO_DEVICE)
     if code == L.UG_OK:
         L.lib.ug_plan_destroy(out)
