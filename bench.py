@@ -134,7 +134,7 @@ def main():
     n_rec, n_key = plan.fit(gd, pd)
     image = torch.empty(plan.num_pixels, device=dev)
     d_image = torch.empty_like(image)
-    loss_buf = torch.empty(1025, device=dev)
+    loss_buf = torch.zeros(1026, device=dev)
     grads = R.GaussianTensors(torch.empty_like(gd.means), torch.empty_like(gd.lraw),
                               torch.empty_like(gd.intensity), torch.empty_like(gd.opacity))
 
@@ -190,6 +190,29 @@ def main():
     ms_step = graph_ms_step if graph_ms_step is not None else eager_ms_step
     ms_total = ms_step * args.steps
     planes_s = pl.p * args.steps / (ms_total / 1e3)
+
+    # ---- context figures: the forward alone, and the full training step ----
+    fwd_ms = None
+    train_ms = None
+    if not args.no_graph:
+        fwd_ms = replay_ms(lambda: plan.render(gd, pd, image, check_status=False), args.warmup, args.steps)
+        fwd_img = image.clone()
+        assert torch.equal(fwd_img, eager_image), "the forward alone must render the same image"
+        from paper_2505_05643_amd.step import TrainStep
+        tparams = R.GaussianTensors(*(t.clone() for t in gd))
+        # the Gaussians grow while they train: room for the timed steps
+        ts = TrainStep(tparams, pd, pl.wh, target, plan.params, headroom=4.0)
+        ts.run(max(args.warmup, 1))  # captures the step as a hipGraph and replays it
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(args.steps):
+            ts.replay()
+        t1.record()
+        torch.cuda.synchronize()
+        train_ms = t0.elapsed_time(t1) / args.steps
+        if ts.plan.status() != 0:  # a step that overflowed skipped its update: no valid time
+            train_ms = None
+        del ts, tparams
 
     # in-support pairs of one forward, counted by the kernel itself
     cparams = R.Params(**{**params.__dict__, "flags": 1})
@@ -298,6 +321,8 @@ def main():
         "autotune": tuned,
         "eager_ms_per_step": eager_ms_step,
         "graph_ms_per_step": graph_ms_step,
+        "forward_only_ms": fwd_ms,
+        "train_step_ms": train_ms,
         "evals_per_s": evals_s,
         "in_support_pairs": n_eval,
         "records": n_rec,
@@ -332,6 +357,30 @@ def main():
         for _ in range(5):
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
+
+
+def replay_ms(fn, warmup, steps):
+    """Average ms of fn captured once as a hipGraph and replayed."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fn()
+    for _ in range(max(warmup, 1)):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        graph.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
 
 
 def plan_bits(plan) -> int:

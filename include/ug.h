@@ -188,8 +188,11 @@ int ug_profile_read(ug_plan *plan, float *ms_host, int32_t *launches_host);
  * and d_image = 2 (image - target) / m (the training loss; the paper trains
  * the Gaussians by gradient descent on rendered slices, Section 4.5).
  * loss_dev must hold UG_MSE_SCRATCH_FLOATS floats: [0] receives the loss,
- * the rest is scratch for the deterministic two-level reduction. */
-#define UG_MSE_SCRATCH_FLOATS 1025
+ * the rest is scratch for the deterministic one-launch reduction and must
+ * be zero-filled before the first call (every call leaves it usable: its
+ * completion counter returns to zero).  Calls sharing one loss_dev must
+ * not overlap. */
+#define UG_MSE_SCRATCH_FLOATS 1026
 int ug_mse_grad(const float *image, const float *target, int64_t m, float *d_image,
                 float *loss_dev, void *stream);
 

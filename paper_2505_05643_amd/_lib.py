@@ -23,7 +23,7 @@ UG_BOX_PAPER = 0
 UG_BOX_CONIC = 1
 UG_BOX_ROWS = 2
 
-UG_MSE_SCRATCH_FLOATS = 1025
+UG_MSE_SCRATCH_FLOATS = 1026
 UG_FLAG_COUNT_EVALS = 1
 
 STAGES = ("setup", "cull_count", "cull_write", "record", "emit", "sort_hist", "sort_scan", "sort_scatter", "ranges",

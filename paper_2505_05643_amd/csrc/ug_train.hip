@@ -6,10 +6,14 @@ namespace ug {
 constexpr int kMseBlocks = 1024;
 
 // Each block: d_image over a contiguous chunk and the chunk's squared-error
-// sum (fixed-order tree), written to loss[1 + block].
-__global__ __launch_bounds__(256) void k_mse_part(const float* __restrict__ image, const float* __restrict__ target,
-                                                  int64_t m, float* __restrict__ d_image, float* __restrict__ loss) {
+// sum (fixed-order tree), written to loss[1 + block]; the last block to
+// finish (a counter in loss[1 + kMseBlocks], left at zero) adds the block
+// sums in block order in double and writes the mean to loss[0].
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ image, const float* __restrict__ target,
+                                             int64_t m, float* __restrict__ d_image, float* __restrict__ loss) {
   __shared__ float sh[256];
+  __shared__ double shd[256];
+  __shared__ bool last;
   const int64_t chunk = (m + gridDim.x - 1) / gridDim.x;
   const int64_t a = (int64_t)blockIdx.x * chunk;
   const int64_t b = a + chunk < m ? a + chunk : m;
@@ -26,20 +30,28 @@ __global__ __launch_bounds__(256) void k_mse_part(const float* __restrict__ imag
     if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) loss[1 + blockIdx.x] = sh[0];
-}
-
-__global__ __launch_bounds__(256) void k_mse_final(int nparts, int64_t m, float* __restrict__ loss) {
-  __shared__ double sh[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += 256) acc += (double)loss[1 + i];
-  sh[threadIdx.x] = acc;
+  unsigned int* counter = reinterpret_cast<unsigned int*>(loss + 1 + kMseBlocks);
+  if (threadIdx.x == 0) {
+    loss[1 + blockIdx.x] = sh[0];
+    __threadfence();
+    last = atomicAdd(counter, 1u) == gridDim.x - 1u;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double s = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += 256)
+    s += (double)__hip_atomic_load(&loss[1 + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  shd[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    if (threadIdx.x < o) shd[threadIdx.x] += shd[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) loss[0] = (float)(sh[0] / (double)m);
+  if (threadIdx.x == 0) {
+    loss[0] = (float)(shd[0] / (double)m);
+    *counter = 0u;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
@@ -126,8 +138,7 @@ hipError_t launch_mse(const float* image, const float* target, int64_t m, float*
                       hipStream_t s) {
   int64_t want = (m + 4095) / 4096;
   const int blocks = (int)(want < 1 ? 1 : (want > kMseBlocks ? kMseBlocks : want));
-  hipLaunchKernelGGL(k_mse_part, dim3(blocks), dim3(256), 0, s, image, target, m, d_image, loss);
-  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, s, blocks, m, loss);
+  hipLaunchKernelGGL(k_mse, dim3(blocks), dim3(256), 0, s, image, target, m, d_image, loss);
   return hipGetLastError();
 }
 

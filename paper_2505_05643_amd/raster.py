@@ -243,7 +243,7 @@ def mse_grad(image: torch.Tensor, target: torch.Tensor, d_image: torch.Tensor | 
     if d_image is None:
         d_image = torch.empty_like(image)
     if loss_buf is None:
-        loss_buf = torch.empty(_lib.UG_MSE_SCRATCH_FLOATS, dtype=torch.float32, device=image.device)
+        loss_buf = torch.zeros(_lib.UG_MSE_SCRATCH_FLOATS, dtype=torch.float32, device=image.device)
     check(lib.ug_mse_grad(image.data_ptr(), target.data_ptr(), m, d_image.data_ptr(), loss_buf.data_ptr(),
                           _stream()), "ug_mse_grad")
     return loss_buf[:1], d_image
