@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const PlaneInt* __restrict__ p
 // each key adds its slots in sub-block order.  A sub-chunk is the longest
 // run of the wave's keys whose items fit the slots (at least one key: a key
 // has at most 16 items).
-constexpr int kBwdSlots = 256;
+constexpr int kBwdSlots = 192;
 
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl, const PlaneInt* __restrict__ pint,
