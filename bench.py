@@ -278,9 +278,13 @@ def main():
         del per
 
     # ---- roofline of every kernel; the dominant one is the headline ----
-    sizes = dict(n=g.n, p=pl.p, r=n_rec, k=n_key, t=plan.num_tiles, m=int(pl.npix),
-                 passes=(plan_bits(plan) + 7) // 8, w=(pl.p + 63) // 64, rows=params.box_mode == 2,
-                 g_sort=min(4096, max(1, (plan.key_capacity + 2047) // 2048)))
+    # sort passes as launched (one histogram launch per pass); digit slots
+    # per block histogram: 2^ceil(bits / passes) rounded up to 256 or 1024
+    passes = max(1, round(stages["sort_hist"][1] / args.steps)) if "sort_hist" in stages else 1
+    g_sort = min(2048, max(1, (plan.key_capacity + 2047) // 2048))
+    dslots = 1024 if -(-plan_bits(plan) // passes) > 8 else 256
+    sizes = dict(n=g.n, p=pl.p, r=n_rec, k=n_key, t=plan.num_tiles, m=int(pl.npix), passes=passes,
+                 w=(pl.p + 63) // 64, rows=params.box_mode == 2, g_sort=g_sort, dslots=dslots)
     kernels = {}
     for nm, (ms, n) in stages.items():
         avg = ms / max(n, 1)
@@ -391,11 +395,13 @@ def plan_bits(plan) -> int:
     return int(np.ceil(np.log2(t)))
 
 
-def kernel_bytes(name, n, p, r, k, t, m, passes, w, rows, g_sort) -> int:
+def kernel_bytes(name, n, p, r, k, t, m, passes, w, rows, g_sort, dslots) -> int:
     """Algorithmic HBM bytes of one launch of an HBM-bound kernel: what the
     kernel must read and write once (N Gaussians, R records, K keys, T tiles,
-    M pixels; W = 64-plane words per Gaussian; a sort pass moves the keys
-    and their indices once; the last pass also gathers the record ids)."""
+    M pixels; W = 64-plane words per Gaussian; a sort pass reads and writes
+    the key word, emission index and record id once, the first pass reading
+    no emission index; the column scan reads and writes the block
+    histograms of g_sort blocks x dslots digits)."""
     if name == "setup":
         return p * (56 + 160)
     if name == "cull_count":
@@ -409,9 +415,9 @@ def kernel_bytes(name, n, p, r, k, t, m, passes, w, rows, g_sort) -> int:
     if name == "sort_hist":
         return 4 * k
     if name == "sort_scan":
-        return 8 * 256 * g_sort
+        return 8 * dslots * g_sort
     if name == "sort_scatter":
-        total = 4 * k + 8 * k + (passes - 1) * 16 * k + 8 * k
+        total = 20 * k + (passes - 1) * 24 * k
         return total // max(passes, 1)
     if name == "ranges":
         return 4 * k + 4 * t

@@ -51,7 +51,10 @@ struct ug_plan {
 
 namespace {
 
+// Workspace regions for the current capacities; also the sort's set that
+// holds the result (the passes alternate between two sets).
 void compute_layout(ug_plan* pl) {
+  pl->final_buf = sort_passes(pl->bits, pl->sort_blocks) % 2;
   Layout& L = pl->lay;
   size_t o = 0;
   auto take = [&o](size_t bytes) {
@@ -79,7 +82,7 @@ void compute_layout(ug_plan* pl) {
   L.tile_start = take((T + 1) * 4);
   L.dsave = take(pl->num_pixels * 4);
   L.gq = take(T * tpx * 8);
-  L.hist = take((size_t)256 * (pl->sort_blocks + 1) * 4);
+  L.hist = take((size_t)sort_digit_slots(pl->bits, pl->sort_blocks) * (pl->sort_blocks + 1) * 4);
   L.key_tile0 = take(K * 4);
   L.key_tile1 = take(K * 4);
   L.key_val0 = take(K * 4);
@@ -212,7 +215,7 @@ hipError_t enqueue_sort(const ug_plan* plan, void* ws, hipStream_t s) {
                          {at<uint32_t>(ws, L.key_tile1), at<uint32_t>(ws, L.key_val1), at<uint32_t>(ws, L.srec)}};
   uint32_t* hist = at<uint32_t>(ws, L.hist);
   const uint32_t G = plan->sort_blocks;
-  const int passes = sort_passes(plan->bits);
+  const int passes = sort_passes(plan->bits, G);
   hipError_t e = hipSuccess;
   for (int pass = 0, cur = 0; pass < passes && e == hipSuccess; ++pass, cur ^= 1) {
     {
@@ -222,7 +225,7 @@ hipError_t enqueue_sort(const ug_plan* plan, void* ws, hipStream_t s) {
     if (e != hipSuccess) break;
     {
       StageScope sc(plan, UG_STAGE_SORT_SCAN, s);
-      e = launch_radix_colscan(hist, G, s);
+      e = launch_radix_colscan(hist, G, plan->bits, s);
     }
     if (e != hipSuccess) break;
     StageScope sc(plan, UG_STAGE_SORT_SCATTER, s);
@@ -308,7 +311,6 @@ int ug_plan_create(int32_t n, int32_t p, const int32_t* wh_host, const ug_params
   int bits = 1;
   while (bits < 32 && (uint64_t(1) << bits) < tiles) ++bits;
   pl->bits = bits;
-  pl->final_buf = sort_passes(bits) % 2;
   pl->device = dev;
   pl->rec_cap = (uint32_t)record_capacity;
   pl->key_cap = (uint32_t)key_capacity;

@@ -292,8 +292,20 @@ __device__ __forceinline__ uint32_t tile_mask(const int (&ua)[kMaxBands], const 
   return m;
 }
 
-// Key count of a ROWS-mode record over its tile rectangle: per tile row, the
-// tiles under the column range of the ellipse over the whole tile row.
+// Tiles [tx0, tx1] of tile row ty that a ROWS-mode record covers: those under
+// the column range of the ellipse over the whole tile row; false if none.
+__device__ __forceinline__ bool rows_span(const BandPrep& bp, int ty, int TW, int TH, int H, int umin, int umax,
+                                          int& tx0, int& tx1) {
+  const int ya = ty * TH, yb = min(ya + TH - 1, H - 1);
+  int ua, uz;
+  if (!band_cols(bp, ya, yb, umin, umax, ua, uz)) return false;
+  tx0 = ua / TW;
+  tx1 = uz / TW;
+  return true;
+}
+
+// Key count of a ROWS-mode record over its tile rectangle (rows_span summed
+// over its tile rows).
 __device__ __forceinline__ uint32_t rows_count(const RecAcc& ra, const RecGeo& geo, int W, int H, int TW, int TH) {
   const int umin = geo.tx0 * TW;
   const int umax = min(geo.tx1 * TW + TW - 1, W - 1);
@@ -301,9 +313,8 @@ __device__ __forceinline__ uint32_t rows_count(const RecAcc& ra, const RecGeo& g
   if (!band_prep(ra, geo.ub, geo.vb, bp)) return 0;
   uint32_t keys = 0;
   for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
-    const int ya = ty * TH, yb = min(ya + TH - 1, H - 1);
-    int ua, uz;
-    if (band_cols(bp, ya, yb, umin, umax, ua, uz)) keys += (uint32_t)(uz / TW - ua / TW + 1);
+    int tx0, tx1;
+    if (rows_span(bp, ty, TW, TH, H, umin, umax, tx0, tx1)) keys += (uint32_t)(tx1 - tx0 + 1);
   }
   return keys;
 }

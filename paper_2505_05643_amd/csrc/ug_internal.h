@@ -138,4 +138,12 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nblocks) {
 
 __device__ __forceinline__ bool isfinite_d(double v) { return __builtin_isfinite(v); }
 
+// Orders LDS writes and reads between the lanes of one wave (LDS operations
+// of a wave execute in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 }  // namespace ug

@@ -43,16 +43,20 @@ hipError_t launch_gauss_grad(const ug_gaussians& g, const RenderParams& rp, cons
 
 // ---- tile binning sort (ug_sort.hip)
 // Stable LSD radix sort of the key words on their low `bits` bits (the tile
-// id), at most 8 per pass (sort_passes(bits) passes, the bits split evenly
-// between them), moving two payload words per key: emission index
-// (generated in the first pass) and record id.  Arrays are given as {key,
-// val, rec}; passes alternate between two such sets.  Per pass:
-// block-major digit histograms (hist holds 256 * (nblocks + 1) words),
-// their column scan, then the stable scatter.
-int sort_passes(int bits);
+// id), moving two payload words per key: emission index (generated in the
+// first pass) and record id.  Digits: the whole tile id in one pass when it
+// has at most 10 bits and there are at most 256 sort blocks, else at most 8
+// bits per pass with the bits split evenly (sort_digit_bits, sort_passes).
+// Arrays are given as {key, val, rec}; passes alternate between two such
+// sets.  Per pass: block-major digit histograms (hist holds
+// sort_digit_slots * (nblocks + 1) words), their column scan, then the
+// stable scatter.
+int sort_digit_bits(int bits, uint32_t nblocks);
+int sort_passes(int bits, uint32_t nblocks);
+uint32_t sort_digit_slots(int bits, uint32_t nblocks);
 hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t nblocks, int bits,
                              int pass, hipStream_t s);
-hipError_t launch_radix_colscan(uint32_t* hist, uint32_t nblocks, hipStream_t s);
+hipError_t launch_radix_colscan(uint32_t* hist, uint32_t nblocks, int bits, hipStream_t s);
 hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], uint32_t* const out[3],
                                 const uint32_t* hist, uint32_t nblocks, int bits, int pass, hipStream_t s);
 // tile_start[t] for t in [0, T] from the sorted key words (tile id = the key

@@ -236,13 +236,7 @@ __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, c
   if (box_mode == UG_BOX_ROWS && !ok) return;
   for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
     int tx0 = geo.tx0, tx1 = geo.tx1;
-    if (box_mode == UG_BOX_ROWS) {
-      const int ya = ty * TH, yb = min(ya + TH - 1, PI.H - 1);
-      int ua, uz;
-      if (!band_cols(bp, ya, yb, umin, umax, ua, uz)) continue;
-      tx0 = ua / TW;
-      tx1 = uz / TW;
-    }
+    if (box_mode == UG_BOX_ROWS && !rows_span(bp, ty, TW, TH, PI.H, umin, umax, tx0, tx1)) continue;
     int bua[kMaxBands], buz[kMaxBands];
     if (ok) {
       band_ranges(bp, ty, TH, PI.H, umin, umax, bua, buz);

@@ -25,14 +25,6 @@ namespace ug {
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// Orders LDS writes and reads between the lanes of one wave (LDS operations
-// of a wave execute in order; this keeps the compiler from moving them).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // ---------------------------------------------------------------- forward
 // CNT: also count the in-support pairs of pixels inside the plane and the
 // evaluated pairs (64 per evaluated wave sub-block) into counters[0] and

@@ -1,12 +1,16 @@
-// Tile binning: stable LSD radix sort of the (tile id, emission index) key
-// pairs, 8 bits per pass, with the key count read from device memory (so
-// the host never synchronises), and the per-tile [start, end) ranges.
+// Tile binning: stable LSD radix sort of the key words on their tile id,
+// carrying the emission index and the record id, with the key count read
+// from device memory (so the host never synchronises), and the per-tile
+// [start, end) ranges.  Digits are at most 8 bits (256 per pass), or, for
+// small inputs whose tile id has at most 10 bits, the whole tile id in one
+// pass (up to 1024 digits).
 #include "ug_kernels.h"
 
 namespace ug {
 
 constexpr int kSortThreads = 256;
 constexpr uint32_t kSortMaxBlocks = 2048;
+constexpr uint32_t kWideMaxBlocks = 256;  // one wide pass only up to this many blocks
 
 // Contiguous chunk of the n keys owned by block b of G (multiple of 256).
 __device__ __forceinline__ void sort_chunk(uint32_t n, uint32_t G, uint32_t b, uint32_t& s, uint32_t& e) {
@@ -18,25 +22,27 @@ __device__ __forceinline__ void sort_chunk(uint32_t n, uint32_t G, uint32_t b, u
   e = (uint32_t)(e64 < n ? e64 : n);
 }
 
-// Per-block digit histogram, block-major: cnt[b * 256 + d].
+// Per-block digit histogram, block-major: cnt[b * D + d] (D digit slots).
+template <int D>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Ctrl* __restrict__ ctrl,
                                                               const uint32_t* __restrict__ keys, uint32_t G,
                                                               int shift, uint32_t dmask, uint32_t* __restrict__ cnt) {
-  __shared__ uint32_t h[4][256];
-  for (int j = threadIdx.x; j < 1024; j += kSortThreads) (&h[0][0])[j] = 0u;
+  __shared__ uint32_t h[4][D];
+  for (int j = threadIdx.x; j < 4 * D; j += kSortThreads) (&h[0][0])[j] = 0u;
   __syncthreads();
   uint32_t s, e;
   sort_chunk(ctrl->n_key_eff, G, blockIdx.x, s, e);
   const int wave = threadIdx.x >> 6;
   for (uint32_t i = s + threadIdx.x; i < e; i += kSortThreads) atomicAdd(&h[wave][(keys[i] >> shift) & dmask], 1u);
   __syncthreads();
-  const int d = threadIdx.x;
-  cnt[(size_t)blockIdx.x * 256 + d] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+  for (int d = threadIdx.x; d < D; d += kSortThreads)
+    cnt[(size_t)blockIdx.x * D + d] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
 // One block per digit d: exclusive scan of column d over the G blocks
 // (in place), and the column total coltot[d].  G <= 4096.
 constexpr int kColPer = 16;
+template <int D>
 __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ cnt, uint32_t G,
                                                        uint32_t* __restrict__ coltot) {
   __shared__ uint32_t sh[4];
@@ -47,7 +53,7 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ cn
 #pragma unroll
   for (int j = 0; j < kColPer; ++j) {
     const uint32_t b = kColPer * t + j;
-    v[j] = b < G ? cnt[(size_t)b * 256 + d] : 0u;
+    v[j] = b < G ? cnt[(size_t)b * D + d] : 0u;
     sum += v[j];
   }
   uint32_t x = sum;
@@ -68,18 +74,10 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ cn
 #pragma unroll
   for (int j = 0; j < kColPer; ++j) {
     const uint32_t b = kColPer * t + j;
-    if (b < G) cnt[(size_t)b * 256 + d] = run;
+    if (b < G) cnt[(size_t)b * D + d] = run;
     run += v[j];
   }
   if (t == 0) coltot[d] = total;
-}
-
-// Orders LDS accesses between the lanes of one wave (a wave's LDS operations
-// execute in order; this keeps the compiler from moving them).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Stable scatter.  The block's chunk is walked in rounds of up to 4096 keys;
@@ -101,7 +99,7 @@ struct SortSet {
   uint32_t* rec;
 };
 
-template <int kItems>
+template <int kItems, int D>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __restrict__ ctrl, SortSet in,
                                                                 SortSet out, bool gen_val,
                                                                 const uint32_t* __restrict__ cnt,
@@ -111,18 +109,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
   const uint32_t* __restrict__ kin = in.key;
   __shared__ uint32_t s_key[kRound];
   __shared__ uint32_t s_src[kRound];  // input position of the key in each slot
-  __shared__ uint32_t run[256];      // global output position of the next key of each digit
-  __shared__ uint32_t loc[256];      // first LDS slot of each digit in this round
-  __shared__ uint32_t rcnt[256];     // keys of each digit in this round
-  __shared__ uint32_t wcnt[4][256];  // per-wave digit counts, then the waves' prefixes
+  constexpr int kPer = D / kSortThreads;  // digits per thread, consecutive
+  __shared__ uint32_t run[D];      // global output position of the next key of each digit
+  __shared__ uint32_t loc[D];      // first LDS slot of each digit in this round
+  __shared__ uint32_t rcnt[D];     // keys of each digit in this round
+  __shared__ uint32_t wcnt[4][D];  // per-wave digit counts, then the waves' prefixes
   __shared__ uint32_t sh[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t dmask = (1u << dbits) - 1u;
   uint32_t s, e;
   sort_chunk(ctrl->n_key_eff, G, blockIdx.x, s, e);
   {
-    const uint32_t tot = coltot[tid];
-    uint32_t x = tot;
+    uint32_t tot[kPer], sum = 0u;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      tot[k] = coltot[tid * kPer + k];
+      sum += tot[k];
+    }
+    uint32_t x = sum;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t y = __shfl_up(x, o, 64);
@@ -132,12 +136,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
     __syncthreads();
     uint32_t before = 0;
     for (int w = 0; w < wave; ++w) before += sh[w];
-    run[tid] = before + x - tot + cnt[(size_t)blockIdx.x * 256 + tid];
+    uint32_t at = before + x - sum;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int d = tid * kPer + k;
+      run[d] = at + cnt[(size_t)blockIdx.x * D + d];
+      at += tot[k];
+    }
   }
   for (uint32_t base = s; base < e; base += kRound) {
     // ---- per wave: ranks of its 512 keys among its own keys of each digit
 #pragma unroll
-    for (int j = 0; j < 4; ++j) wcnt[wave][lane + 64 * j] = 0u;
+    for (int j = 0; j < D / 64; ++j) wcnt[wave][lane + 64 * j] = 0u;
     wave_lds_sync();
     // the round's keys split evenly over the waves, in whole loads of 64
     const uint32_t n_round = min((uint32_t)kRound, e - base);
@@ -166,14 +176,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
     __syncthreads();
     // ---- per digit: the waves' prefixes and the round's count
     {
-      const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-      wcnt[0][tid] = 0u;
-      wcnt[1][tid] = c0;
-      wcnt[2][tid] = c0 + c1;
-      wcnt[3][tid] = c0 + c1 + c2;
-      const uint32_t c = c0 + c1 + c2 + c3;
-      rcnt[tid] = c;
-      uint32_t x = c;
+      uint32_t c[kPer], sum = 0u;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int d = tid * kPer + k;
+        const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
+        wcnt[0][d] = 0u;
+        wcnt[1][d] = c0;
+        wcnt[2][d] = c0 + c1;
+        wcnt[3][d] = c0 + c1 + c2;
+        c[k] = c0 + c1 + c2 + c3;
+        rcnt[d] = c[k];
+        sum += c[k];
+      }
+      uint32_t x = sum;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(x, o, 64);
@@ -183,7 +199,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
       __syncthreads();
       uint32_t before = 0;
       for (int w = 0; w < wave; ++w) before += sh[w];
-      loc[tid] = before + x - c;
+      uint32_t at = before + x - sum;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        loc[tid * kPer + k] = at;
+        at += c[k];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -205,7 +226,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
       out.rec[pos] = in.rec[src];
     }
     __syncthreads();
-    run[tid] += rcnt[tid];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) run[tid * kPer + k] += rcnt[tid * kPer + k];
     __syncthreads();
   }
 }
@@ -238,39 +260,63 @@ uint32_t sort_blocks_for(uint32_t key_cap) {
   return g;
 }
 
-int sort_passes(int bits) { return (bits + 7) / 8 < 1 ? 1 : (bits + 7) / 8; }
-
-// Digit width: the key bits split evenly over the passes (at most 8), so
-// small tile counts get fewer digits and longer runs per digit.
-static int digit_bits(int bits) {
-  const int p = sort_passes(bits);
-  const int d = (bits + p - 1) / p;
-  return d < 1 ? 1 : d;
+// Digit width of every pass: the whole tile id in one pass when it has at
+// most 10 bits and the input is small (at most kWideMaxBlocks blocks, so the
+// block-major histograms stay small); otherwise the bits split evenly over
+// passes of at most 8 bits, so small tile counts get fewer digits and longer
+// runs per digit.
+int sort_digit_bits(int bits, uint32_t G) {
+  if (bits < 1) bits = 1;
+  if (bits <= 10 && G <= kWideMaxBlocks) return bits;
+  const int p = (bits + 7) / 8;
+  return (bits + p - 1) / p;
 }
+
+int sort_passes(int bits, uint32_t G) {
+  if (bits < 1) bits = 1;
+  const int d = sort_digit_bits(bits, G);
+  return (bits + d - 1) / d;
+}
+
+uint32_t sort_digit_slots(int bits, uint32_t G) { return sort_digit_bits(bits, G) > 8 ? 1024u : 256u; }
 
 hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t G, int bits, int pass,
                              hipStream_t s) {
-  const int db = digit_bits(bits);
-  hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys, G, db * pass, (1u << db) - 1u, hist);
+  const int db = sort_digit_bits(bits, G);
+  if (db > 8)
+    hipLaunchKernelGGL(k_radix_hist<1024>, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys, G, db * pass,
+                       (1u << db) - 1u, hist);
+  else
+    hipLaunchKernelGGL(k_radix_hist<256>, dim3(G), dim3(kSortThreads), 0, s, ctrl, keys, G, db * pass,
+                       (1u << db) - 1u, hist);
   return hipGetLastError();
 }
 
-hipError_t launch_radix_colscan(uint32_t* hist, uint32_t G, hipStream_t s) {
-  hipLaunchKernelGGL(k_radix_colscan, dim3(256), dim3(256), 0, s, hist, G, hist + (size_t)256 * G);
+hipError_t launch_radix_colscan(uint32_t* hist, uint32_t G, int bits, hipStream_t s) {
+  const uint32_t D = sort_digit_slots(bits, G);
+  if (D == 1024u)
+    hipLaunchKernelGGL(k_radix_colscan<1024>, dim3(D), dim3(256), 0, s, hist, G, hist + (size_t)D * G);
+  else
+    hipLaunchKernelGGL(k_radix_colscan<256>, dim3(D), dim3(256), 0, s, hist, G, hist + (size_t)D * G);
   return hipGetLastError();
 }
 
 hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], uint32_t* const out[3],
                                 const uint32_t* hist, uint32_t G, int bits, int pass, hipStream_t s) {
-  const int db = digit_bits(bits);
+  const int db = sort_digit_bits(bits, G);
+  const uint32_t D = sort_digit_slots(bits, G);
   const SortSet si{const_cast<uint32_t*>(in[0]), const_cast<uint32_t*>(in[1]), const_cast<uint32_t*>(in[2])};
   const SortSet so{out[0], out[1], out[2]};
-  if (G >= kSortMaxBlocks)
-    hipLaunchKernelGGL(k_radix_scatter<16>, dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0, hist,
-                       hist + (size_t)256 * G, G, db * pass, db);
+  const uint32_t* coltot = hist + (size_t)D * G;
+  if (D == 1024u)  // only for G <= kWideMaxBlocks
+    hipLaunchKernelGGL((k_radix_scatter<8, 1024>), dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
+                       hist, coltot, G, db * pass, db);
+  else if (G >= kSortMaxBlocks)
+    hipLaunchKernelGGL((k_radix_scatter<16, 256>), dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
+                       hist, coltot, G, db * pass, db);
   else
-    hipLaunchKernelGGL(k_radix_scatter<8>, dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0, hist,
-                       hist + (size_t)256 * G, G, db * pass, db);
+    hipLaunchKernelGGL((k_radix_scatter<8, 256>), dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
+                       hist, coltot, G, db * pass, db);
   return hipGetLastError();
 }
 
