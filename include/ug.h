@@ -65,7 +65,7 @@ extern "C" {
 #define UG_STAGE_SORT_HIST 5     /* radix sort: digit histograms (once per pass)        */
 #define UG_STAGE_SORT_SCAN 6     /* radix sort: histogram column scan (once per pass)   */
 #define UG_STAGE_SORT_SCATTER 7  /* radix sort: stable scatter (once per pass)          */
-#define UG_STAGE_RANGES 8        /* per-tile key ranges                                 */
+#define UG_STAGE_RANGES 8        /* per-tile key ranges (a one-pass sort writes them)   */
 #define UG_STAGE_ACCUM 9         /* per-tile accumulation, Eq. 5-8 and 12               */
 #define UG_STAGE_BWD_PREP 10     /* per-pixel adjoint inputs                            */
 #define UG_STAGE_ACCUM_BWD 11    /* per-key adjoint of the accumulation                 */

@@ -71,7 +71,7 @@ void compute_layout(ug_plan* pl) {
   L.cnt_rec = take(n * 4);
   L.accbits = take(accbits_words(pl->n, pl->p) * 8);
   L.off_rec = take(n * 8);
-  L.blk_g = take((size_t)cull_blocks(pl->n) * 4);
+  L.blk_g = take((size_t)cull_blocks(pl->n, pl->p) * 4);
   L.blk_r = take((size_t)record_blocks(pl->rec_cap) * 4);
   L.rec_pair = take(R * 8);
   L.racc = take(R * sizeof(RecAcc));
@@ -230,7 +230,8 @@ hipError_t enqueue_sort(const ug_plan* plan, void* ws, hipStream_t s) {
     if (e != hipSuccess) break;
     StageScope sc(plan, UG_STAGE_SORT_SCATTER, s);
     const uint32_t* in[3] = {set[cur][0], set[cur][1], set[cur][2]};
-    e = launch_radix_scatter(ctrl, in, set[cur ^ 1], hist, G, plan->bits, pass, s);
+    e = launch_radix_scatter(ctrl, in, set[cur ^ 1], hist, G, plan->bits, pass,
+                             passes == 1 ? at<uint32_t>(ws, L.tile_start) : nullptr, plan->num_tiles, s);
   }
   return e;
 }
@@ -386,7 +387,7 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
   e = enqueue_sort(plan, ws, s);
   if (e != hipSuccess) return UG_ERR_HIP;
   const Sorted so = sorted_set(plan, ws);
-  {
+  if (sort_passes(plan->bits, plan->sort_blocks) > 1) {  // one pass wrote the ranges itself
     StageScope sc(plan, UG_STAGE_RANGES, s);
     e = launch_tile_ranges(ctrl, so.key, plan->num_tiles, key_mask_shift(plan->prm.tile_w, plan->prm.tile_h),
                            at<uint32_t>(ws, L.tile_start), s);

@@ -6,7 +6,7 @@
 namespace ug {
 
 // ---- preprocess (ug_preprocess.hip)
-uint32_t cull_blocks(int n);
+uint32_t cull_blocks(int n, int p);
 uint32_t record_blocks(uint32_t rec_cap);
 hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, PlaneCull* pcf, Ctrl* ctrl,
                        hipStream_t s);
@@ -57,8 +57,12 @@ uint32_t sort_digit_slots(int bits, uint32_t nblocks);
 hipError_t launch_radix_hist(const Ctrl* ctrl, const uint32_t* keys, uint32_t* hist, uint32_t nblocks, int bits,
                              int pass, hipStream_t s);
 hipError_t launch_radix_colscan(uint32_t* hist, uint32_t nblocks, int bits, hipStream_t s);
+// With a single pass (the digit is the whole tile id) the scatter also
+// writes tile_start (if not null; num_tiles + 1 entries), which the column
+// totals give directly.
 hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], uint32_t* const out[3],
-                                const uint32_t* hist, uint32_t nblocks, int bits, int pass, hipStream_t s);
+                                const uint32_t* hist, uint32_t nblocks, int bits, int pass, uint32_t* tile_start,
+                                uint32_t num_tiles, hipStream_t s);
 // tile_start[t] for t in [0, T] from the sorted key words (tile id = the key
 // word's bits below mask_shift).
 hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, int mask_shift,

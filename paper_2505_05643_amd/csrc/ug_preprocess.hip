@@ -131,14 +131,18 @@ __device__ __forceinline__ unsigned long long block_prefix(const uint32_t* __res
 }
 
 // ---------------------------------------------------------------- cull pass
-// Lanes = Gaussians; a block covers gpb Gaussians in rounds of 256 and every
-// lane walks all planes in the same order, so the plane data is uniform
-// (scalar loads).  A pair becomes a record iff the conservative float test
+// A group of LPG lanes per Gaussian, lane k of a group testing planes k,
+// k + LPG, ...; the group ORs its bits.  A block covers gpb Gaussians in
+// rounds of 256 / LPG.  Small inputs spread a Gaussian over several lanes
+// (and blocks over fewer Gaussians) so enough waves run; large ones use one
+// lane per Gaussian, whose plane loads are then uniform (scalar).  A pair
+// becomes a record iff the conservative float test
 // of Phase 1 (Eq. 13's box along the normal meets the plane, i.e. the plane
 // meets the Eq. 12 ellipsoid) passes; the test only errs towards accepting a
 // pair whose plane narrowly misses the ellipsoid, and such a record has an
 // empty support, so it adds exactly zero everywhere.  Acceptance is kept as
 // one bit per (Gaussian, plane), 64 planes per word.
+template <int LPG>
 __global__ __launch_bounds__(256) void k_cull_count(ug_gaussians g, const PlaneCull* __restrict__ pcf,
                                                     RenderParams rp, int gpb, uint32_t* __restrict__ cnt_rec,
                                                     unsigned long long* __restrict__ accbits,
@@ -154,27 +158,30 @@ __global__ __launch_bounds__(256) void k_cull_count(ug_gaussians g, const PlaneC
   }
   __syncthreads();
   const int nch = (rp.p + 63) / 64;
+  const int sub = LPG == 1 ? 0 : (int)threadIdx.x % LPG;
   uint32_t mine = 0;
-  for (int r0 = 0; r0 < gpb; r0 += 256) {
-    const int gi = blockIdx.x * gpb + r0 + threadIdx.x;
+  for (int r0 = 0; r0 < gpb; r0 += 256 / LPG) {
+    const int gi = blockIdx.x * gpb + r0 + (int)threadIdx.x / LPG;
     const bool has = gi < rp.n;
     GaussT<float> G;
     G.finite = false;
     if (has) load_gauss<float>(g, gi, rp.beta, G);
-    if (has && !G.finite) atomicOr(&ctrl->flags, kFlagNonfinite);
+    if (has && sub == 0 && !G.finite) atomicOr(&ctrl->flags, kFlagNonfinite);
     const bool live = has && G.finite;
     uint32_t count = 0;
     for (int c = 0; c < nch; ++c) {
       const int pend = min(64, rp.p - c * 64);
       unsigned long long bits = 0;
-      for (int j = 0; j < pend; ++j) {
+      for (int j = sub; j < pend; j += LPG) {
         const PlaneCull pf = pcf[c * 64 + j];
         if (live && pf.valid && cull_maybe(G, pf, rp.chi2)) bits |= 1ull << j;
       }
-      if (has) accbits[(size_t)gi * nch + c] = bits;
+#pragma unroll
+      for (int o = 1; o < LPG; o <<= 1) bits |= __shfl_xor(bits, o, 64);
+      if (has && sub == 0) accbits[(size_t)gi * nch + c] = bits;
       count += (uint32_t)__popcll(bits);
     }
-    if (has) {
+    if (has && sub == 0) {
       cnt_rec[gi] = count;
       mine += count;
     }
@@ -185,19 +192,20 @@ __global__ __launch_bounds__(256) void k_cull_count(ug_gaussians g, const PlaneC
 }
 
 // Offsets and the compact (Gaussian, plane) list, Gaussian-major with planes
-// ascending.  The last block publishes the total and the capacity check.
-__global__ __launch_bounds__(256) void k_cull_write(RenderParams rp, int gpb, uint32_t nblk,
+// ascending.  A block covers m consecutive count blocks (gpb Gaussians in
+// all).  The last block publishes the total and the capacity check.
+__global__ __launch_bounds__(256) void k_cull_write(RenderParams rp, int gpb, uint32_t m, uint32_t nblk,
                                                     const uint32_t* __restrict__ cnt_rec,
                                                     const unsigned long long* __restrict__ accbits,
                                                     const uint32_t* __restrict__ blk_tot,
                                                     unsigned long long* __restrict__ off_rec,
                                                     uint2* __restrict__ rec_pair, Ctrl* __restrict__ ctrl) {
   __shared__ unsigned long long s_sh[4];
-  unsigned long long carry = block_prefix(blk_tot, blockIdx.x, s_sh);
+  unsigned long long carry = block_prefix(blk_tot, blockIdx.x * m, s_sh);
   const int nch = (rp.p + 63) / 64;
   for (int r0 = 0; r0 < gpb; r0 += 256) {
     const int gi = blockIdx.x * gpb + r0 + threadIdx.x;
-    const bool has = gi < rp.n;
+    const bool has = r0 + (int)threadIdx.x < gpb && gi < rp.n;
     const unsigned long long cnt = has ? cnt_rec[gi] : 0ull;
     unsigned long long tot;
     const unsigned long long base = carry + block_exscan_256<unsigned long long>(cnt, s_sh, tot);
@@ -487,15 +495,25 @@ __global__ __launch_bounds__(256) void k_gauss_grad(ug_gaussians g, RenderParams
 // ---------------------------------------------------------------- launchers
 constexpr uint32_t kMaxScanBlocks = 2048;
 
-// Gaussians per cull block: whole rounds of 256, at most 2048 blocks.
-int cull_gpb(int n) {
-  const long rounds = ((long)n + 255) / 256;
-  const long per = (rounds + kMaxScanBlocks - 1) / kMaxScanBlocks;
-  return (int)((per < 1 ? 1 : per) * 256);
+// Lanes per Gaussian (log2) in the cull count: doubled while the lanes stay
+// under 2^18 (a few waves per SIMD), up to one lane per plane and 64.
+int cull_lpg_log2(int n, int p) {
+  int l = 0;
+  while (l < 6 && (1 << l) < p && ((long)n << l) < (1L << 18)) ++l;
+  return l;
 }
 
-uint32_t cull_blocks(int n) {
-  const int gpb = cull_gpb(n);
+// Gaussians per cull block: whole count rounds (256 lanes), at most 2048
+// blocks.
+int cull_gpb(int n, int p) {
+  const long unit = 256 >> cull_lpg_log2(n, p);
+  const long rounds = ((long)n + unit - 1) / unit;
+  const long per = (rounds + kMaxScanBlocks - 1) / kMaxScanBlocks;
+  return (int)((per < 1 ? 1 : per) * unit);
+}
+
+uint32_t cull_blocks(int n, int p) {
+  const int gpb = cull_gpb(n, p);
   return (uint32_t)((n + gpb - 1) / gpb);
 }
 
@@ -523,19 +541,39 @@ size_t accbits_words(int n, int p) { return (size_t)n * (size_t)((p + 63) / 64);
 
 hipError_t launch_cull_count(const ug_gaussians& g, const PlaneCull* pcf, const RenderParams& rp, uint32_t* cnt_rec,
                              unsigned long long* accbits, uint32_t* blk_tot, Ctrl* ctrl, hipStream_t s) {
-  const uint32_t nb = cull_blocks(rp.n);
+  const uint32_t nb = cull_blocks(rp.n, rp.p);
   if (nb == 0) return hipGetLastError();  // no Gaussians: the zeroed totals stand
-  hipLaunchKernelGGL(k_cull_count, dim3(nb), dim3(256), 0, s, g, pcf, rp, cull_gpb(rp.n), cnt_rec, accbits, blk_tot,
-                     ctrl);
+  const int gpb = cull_gpb(rp.n, rp.p);
+  switch (cull_lpg_log2(rp.n, rp.p)) {
+#define UG_CULL(L)                                                                                              \
+  case L:                                                                                                       \
+    hipLaunchKernelGGL(k_cull_count<(1 << L)>, dim3(nb), dim3(256), 0, s, g, pcf, rp, gpb, cnt_rec, accbits, \
+                       blk_tot, ctrl);                                                                          \
+    break;
+    UG_CULL(0)
+    UG_CULL(1)
+    UG_CULL(2)
+    UG_CULL(3)
+    UG_CULL(4)
+    UG_CULL(5)
+    UG_CULL(6)
+#undef UG_CULL
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_cull_write(const RenderParams& rp, const uint32_t* cnt_rec, const unsigned long long* accbits,
                              const uint32_t* blk_tot, unsigned long long* off_rec, uint2* rec_pair, Ctrl* ctrl,
                              hipStream_t s) {
-  const uint32_t nb = cull_blocks(rp.n);
+  const uint32_t nb = cull_blocks(rp.n, rp.p);
   if (nb == 0) return hipGetLastError();
-  hipLaunchKernelGGL(k_cull_write, dim3(nb), dim3(256), 0, s, rp, cull_gpb(rp.n), nb, cnt_rec, accbits, blk_tot,
+  // count blocks of fewer than 256 Gaussians are written m at a time
+  const int gpb = cull_gpb(rp.n, rp.p);
+  const uint32_t m = gpb < 256 ? (uint32_t)(256 / gpb) : 1u;
+  const uint32_t nbw = (nb + m - 1) / m;
+  hipLaunchKernelGGL(k_cull_write, dim3(nbw), dim3(256), 0, s, rp, gpb * (int)m, m, nbw, cnt_rec, accbits, blk_tot,
                      off_rec, rec_pair, ctrl);
   return hipGetLastError();
 }

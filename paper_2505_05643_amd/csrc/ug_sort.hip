@@ -104,7 +104,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
                                                                 SortSet out, bool gen_val,
                                                                 const uint32_t* __restrict__ cnt,
                                                                 const uint32_t* __restrict__ coltot, uint32_t G,
-                                                                int shift, int dbits) {
+                                                                int shift, int dbits, uint32_t* __restrict__ tile_start,
+                                                                uint32_t T) {
   constexpr int kRound = kSortThreads * kItems;
   const uint32_t* __restrict__ kin = in.key;
   __shared__ uint32_t s_key[kRound];
@@ -140,9 +141,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int d = tid * kPer + k;
+      // one pass over the whole tile id: a digit's first output position is
+      // its tile's start
+      if (tile_start && blockIdx.x == 0 && (uint32_t)d < T) tile_start[d] = at;
       run[d] = at + cnt[(size_t)blockIdx.x * D + d];
       at += tot[k];
     }
+    if (tile_start && blockIdx.x == 0 && tid == 0) tile_start[T] = ctrl->n_key_eff;
   }
   for (uint32_t base = s; base < e; base += kRound) {
     // ---- per wave: ranks of its 512 keys among its own keys of each digit
@@ -302,7 +307,8 @@ hipError_t launch_radix_colscan(uint32_t* hist, uint32_t G, int bits, hipStream_
 }
 
 hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], uint32_t* const out[3],
-                                const uint32_t* hist, uint32_t G, int bits, int pass, hipStream_t s) {
+                                const uint32_t* hist, uint32_t G, int bits, int pass, uint32_t* tile_start,
+                                uint32_t num_tiles, hipStream_t s) {
   const int db = sort_digit_bits(bits, G);
   const uint32_t D = sort_digit_slots(bits, G);
   const SortSet si{const_cast<uint32_t*>(in[0]), const_cast<uint32_t*>(in[1]), const_cast<uint32_t*>(in[2])};
@@ -310,13 +316,13 @@ hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], u
   const uint32_t* coltot = hist + (size_t)D * G;
   if (D == 1024u)  // only for G <= kWideMaxBlocks
     hipLaunchKernelGGL((k_radix_scatter<8, 1024>), dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
-                       hist, coltot, G, db * pass, db);
+                       hist, coltot, G, db * pass, db, tile_start, num_tiles);
   else if (G >= kSortMaxBlocks)
     hipLaunchKernelGGL((k_radix_scatter<16, 256>), dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
-                       hist, coltot, G, db * pass, db);
+                       hist, coltot, G, db * pass, db, tile_start, num_tiles);
   else
     hipLaunchKernelGGL((k_radix_scatter<8, 256>), dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
-                       hist, coltot, G, db * pass, db);
+                       hist, coltot, G, db * pass, db, tile_start, num_tiles);
   return hipGetLastError();
 }
 
