@@ -86,6 +86,11 @@ def main():
     ap.add_argument("--cpu-px", type=int, default=640)
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch configuration")
+    ap.add_argument("--retune", action="store_true",
+                    help="search launch configurations even if the autotune cache has this workload")
+    ap.add_argument("--tune-cache", type=str, default=None,
+                    help="autotune cache file (default: the package's autotune_cache.json); a search stores its "
+                         "pick there")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="finish with 5 elementwise copies (dst = -src) of MIB MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -109,12 +114,20 @@ def main():
     tuned = None
     if not (args.tile or args.lds_batch or args.box is not None or args.no_autotune):
         from paper_2505_05643_amd import autotune
-        params, results = autotune.tune(gd, pd, pl.wh, steps=3)
-        default = next((r for r in results if (r["tile_w"], r["tile_h"], r["px_per_lane"], r["lds_batch"],
-                                               r["box_mode"]) == (16, 16, 2, 64, 0)), None)
-        best = min(results, key=lambda r: r["ms"])
-        tuned = {"candidates": len(results), "best_ms": best["ms"],
-                 "default_16x16_paper_ms": default["ms"] if default else None}
+        cache = args.tune_cache or autotune.CACHE
+        sig = autotune.signature(g.n, pl.wh)
+        cached = None if args.retune else autotune.cached_params(sig, cache)
+        if cached is not None:
+            params = cached
+            tuned = {"source": "cache", "signature": sig}
+        else:
+            params, results = autotune.tune(gd, pd, pl.wh, steps=3)
+            default = next((r for r in results if (r["tile_w"], r["tile_h"], r["px_per_lane"], r["lds_batch"],
+                                                   r["box_mode"]) == (16, 16, 2, 64, 0)), None)
+            best = min(results, key=lambda r: r["ms"])
+            tuned = {"source": "search", "signature": sig, "candidates": len(results), "best_ms": best["ms"],
+                     "default_16x16_paper_ms": default["ms"] if default else None}
+            autotune.store(sig, params, best["ms"], cache)
     if args.tile:
         parts = [int(x) for x in args.tile.lower().split("x")]
         params.tile_w, params.tile_h = parts[0], parts[1]
