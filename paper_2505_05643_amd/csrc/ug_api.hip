@@ -389,8 +389,8 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
   const Sorted so = sorted_set(plan, ws);
   if (sort_passes(plan->bits, plan->sort_blocks) > 1) {  // one pass wrote the ranges itself
     StageScope sc(plan, UG_STAGE_RANGES, s);
-    e = launch_tile_ranges(ctrl, so.key, plan->num_tiles, key_mask_shift(plan->prm.tile_w, plan->prm.tile_h),
-                           at<uint32_t>(ws, L.tile_start), s);
+    e = launch_tile_ranges(ctrl, so.key, plan->num_tiles, plan->key_cap,
+                           key_mask_shift(plan->prm.tile_w, plan->prm.tile_h), at<uint32_t>(ws, L.tile_start), s);
   }
   if (e != hipSuccess) return UG_ERR_HIP;
   unsigned long long* n_eval = (plan->prm.flags & UG_FLAG_COUNT_EVALS) ? &ctrl->n_eval : nullptr;

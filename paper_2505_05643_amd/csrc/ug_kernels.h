@@ -65,8 +65,8 @@ hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], u
                                 uint32_t num_tiles, hipStream_t s);
 // tile_start[t] for t in [0, T] from the sorted key words (tile id = the key
 // word's bits below mask_shift).
-hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, int mask_shift,
-                              uint32_t* tile_start, hipStream_t s);
+hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, uint32_t key_cap,
+                              int mask_shift, uint32_t* tile_start, hipStream_t s);
 uint32_t sort_blocks_for(uint32_t key_cap);
 
 // ---- accumulate (ug_raster.hip)

@@ -33,7 +33,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const Ctrl* __restr
   uint32_t s, e;
   sort_chunk(ctrl->n_key_eff, G, blockIdx.x, s, e);
   const int wave = threadIdx.x >> 6;
-  for (uint32_t i = s + threadIdx.x; i < e; i += kSortThreads) atomicAdd(&h[wave][(keys[i] >> shift) & dmask], 1u);
+  // eight loads in flight per thread, then their counts
+  for (uint32_t i0 = s + threadIdx.x; i0 < e; i0 += 8 * kSortThreads) {
+    uint32_t kv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t i = i0 + (uint32_t)(j * kSortThreads);
+      kv[j] = i < e ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (i0 + (uint32_t)(j * kSortThreads) < e) atomicAdd(&h[wave][(kv[j] >> shift) & dmask], 1u);
+  }
   __syncthreads();
   for (int d = threadIdx.x; d < D; d += kSortThreads)
     cnt[(size_t)blockIdx.x * D + d] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
@@ -158,11 +169,19 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
     const uint32_t n_round = min((uint32_t)kRound, e - base);
     const uint32_t seg = ((n_round + 255u) / 256u) * 64u;
     uint32_t kk[kItems], vv[kItems], rr[kItems];
+    // all of the round's loads first: the ranking's wave fences would
+    // otherwise keep each load behind the previous key's LDS update
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const uint32_t i = base + (uint32_t)wave * seg + (uint32_t)(it * 64 + lane);
       const bool valid = (uint32_t)(it * 64) < seg && i < e;
-      const uint32_t k = valid ? kin[i] : 0u;
+      kk[it] = valid ? kin[i] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const uint32_t i = base + (uint32_t)wave * seg + (uint32_t)(it * 64 + lane);
+      const bool valid = (uint32_t)(it * 64) < seg && i < e;
+      const uint32_t k = kk[it];
       const uint32_t d = (k >> shift) & dmask;
       unsigned long long peers = __ballot(valid);
       for (int bit = 0; bit < dbits; ++bit) {
@@ -174,7 +193,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
       wave_lds_sync();
       if (valid && lanemask_lt_popc(peers) == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
       wave_lds_sync();
-      kk[it] = k;
       vv[it] = i;
       rr[it] = valid ? before + lanemask_lt_popc(peers) : 0xffffffffu;
     }
@@ -222,13 +240,30 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
       }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < n_round; i += kSortThreads) {
-      const uint32_t k = s_key[i], src = s_src[i];
-      const uint32_t d = (k >> shift) & dmask;
-      const uint32_t pos = run[d] + (i - loc[d]);
-      out.key[pos] = k;
-      out.val[pos] = gen_val ? src : in.val[src];
-      out.rec[pos] = in.rec[src];
+    // write-out: every slot's payload is gathered before any store (the
+    // input and output sets are different arrays, which the compiler cannot
+    // know, so interleaved loads would wait for the stores before them)
+    uint32_t opos[kItems], oval[kItems], orec[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint32_t i = (uint32_t)tid + (uint32_t)(j * kSortThreads);
+      opos[j] = 0xffffffffu;
+      if (i < n_round) {
+        const uint32_t k = s_key[i], src = s_src[i];
+        const uint32_t d = (k >> shift) & dmask;
+        opos[j] = run[d] + (i - loc[d]);
+        kk[j] = k;
+        oval[j] = gen_val ? src : in.val[src];
+        orec[j] = in.rec[src];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      if (opos[j] != 0xffffffffu) {
+        out.key[opos[j]] = kk[j];
+        out.val[opos[j]] = oval[j];
+        out.rec[opos[j]] = orec[j];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -238,21 +273,46 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
 }
 
 // tile_start[t] = first sorted key index whose tile id is >= t (t in [0, T]).
+// Eight consecutive keys per thread (two 16-byte loads; the grid covers the
+// key capacity); the key before a thread's first comes from its neighbour
+// lane.  Each key writes the starts of the tiles after the previous key's
+// tile up to its own.
+constexpr uint32_t kRangeKeys = 8;
 __global__ __launch_bounds__(256) void k_tile_ranges(const Ctrl* __restrict__ ctrl,
                                                      const uint32_t* __restrict__ skeys, uint32_t T, uint32_t tmask,
                                                      uint32_t* __restrict__ tile_start) {
   const uint32_t n = ctrl->n_key_eff;
-  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (n == 0) {
-    for (uint32_t t = gid; t <= T; t += stride) tile_start[t] = 0u;
+    for (uint32_t t = g; t <= T; t += gridDim.x * blockDim.x) tile_start[t] = 0u;
     return;
   }
-  for (uint32_t i = gid; i < n; i += stride) {
-    const uint32_t k = min(skeys[i] & tmask, T - 1);  // tiles are < T; the clamp only keeps writes in bounds
-    const uint32_t t0 = i ? min(skeys[i - 1] & tmask, T - 1) + 1u : 0u;
-    for (uint32_t t = t0; t <= k; ++t) tile_start[t] = i;
-    if (i == n - 1)
-      for (uint32_t t = k + 1; t <= T; ++t) tile_start[t] = n;
+  const uint32_t i0 = g * kRangeKeys;
+  uint32_t k[kRangeKeys];
+  if (i0 + kRangeKeys <= n) {
+    const uint4* p = reinterpret_cast<const uint4*>(skeys + i0);  // i0 is a multiple of 8: 32-byte aligned
+    const uint4 a = p[0], b = p[1];
+    k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+    k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+  } else {
+#pragma unroll
+    for (uint32_t j = 0; j < kRangeKeys; ++j) k[j] = i0 + j < n ? skeys[i0 + j] : 0u;
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < kRangeKeys; ++j) k[j] = min(k[j] & tmask, T - 1);  // tiles are < T; keeps writes in bounds
+  uint32_t kp = __shfl_up(k[kRangeKeys - 1], 1, 64);
+  if ((threadIdx.x & 63) == 0 && i0 > 0 && i0 < n) kp = min(skeys[i0 - 1] & tmask, T - 1);
+  if (i0 >= n) return;
+#pragma unroll
+  for (uint32_t j = 0; j < kRangeKeys; ++j) {
+    const uint32_t i = i0 + j;
+    if (i < n) {
+      const uint32_t t0 = i ? kp + 1u : 0u;
+      for (uint32_t t = t0; t <= k[j]; ++t) tile_start[t] = i;
+      if (i == n - 1)
+        for (uint32_t t = k[j] + 1; t <= T; ++t) tile_start[t] = n;
+      kp = k[j];
+    }
   }
 }
 
@@ -326,10 +386,12 @@ hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], u
   return hipGetLastError();
 }
 
-hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, int mask_shift,
-                              uint32_t* tile_start, hipStream_t s) {
+hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t num_tiles, uint32_t key_cap,
+                              int mask_shift, uint32_t* tile_start, hipStream_t s) {
   const uint32_t tmask = mask_shift >= 32 ? 0xffffffffu : (1u << mask_shift) - 1u;
-  hipLaunchKernelGGL(k_tile_ranges, dim3(1024), dim3(256), 0, s, ctrl, skeys, num_tiles, tmask, tile_start);
+  const uint32_t blocks = (key_cap + 256u * kRangeKeys - 1u) / (256u * kRangeKeys);
+  hipLaunchKernelGGL(k_tile_ranges, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, ctrl, skeys, num_tiles, tmask,
+                     tile_start);
   return hipGetLastError();
 }
 
