@@ -37,6 +37,7 @@ struct ug_plan {
   int device = 0;
   PlaneInt* d_pint = nullptr;
   uint32_t* d_tile_plane = nullptr;
+  uint32_t* d_tile_org = nullptr;  // pixel origin of each tile, x0 | y0 << 16 (W, H < 2^15)
   Layout lay{};
   // Measurement hooks: event pairs around the launches of selected stages.
   struct Prof {
@@ -316,15 +317,22 @@ int ug_plan_create(int32_t n, int32_t p, const int32_t* wh_host, const ug_params
   pl->rec_cap = (uint32_t)record_capacity;
   pl->key_cap = (uint32_t)key_capacity;
   pl->sort_blocks = sort_blocks_for(pl->key_cap);
-  std::vector<uint32_t> tile_plane((size_t)tiles);
+  std::vector<uint32_t> tile_plane((size_t)tiles), tile_org((size_t)tiles);
   for (int32_t i = 0; i < p; ++i) {
-    const uint32_t nt = (uint32_t)(pint[(size_t)i].ntx * pint[(size_t)i].nty);
-    for (uint32_t t = 0; t < nt; ++t) tile_plane[pint[(size_t)i].tile_off + t] = (uint32_t)i;
+    const PlaneInt& q = pint[(size_t)i];
+    const uint32_t nt = (uint32_t)(q.ntx * q.nty);
+    for (uint32_t t = 0; t < nt; ++t) {
+      tile_plane[q.tile_off + t] = (uint32_t)i;
+      tile_org[q.tile_off + t] = (t % (uint32_t)q.ntx) * (uint32_t)TW | ((t / (uint32_t)q.ntx) * (uint32_t)TH) << 16;
+    }
   }
   if (hipMalloc(&pl->d_pint, sizeof(PlaneInt) * (size_t)p) != hipSuccess ||
       hipMalloc(&pl->d_tile_plane, sizeof(uint32_t) * (size_t)tiles) != hipSuccess ||
+      hipMalloc(&pl->d_tile_org, sizeof(uint32_t) * (size_t)tiles) != hipSuccess ||
       hipMemcpy(pl->d_pint, pint.data(), sizeof(PlaneInt) * (size_t)p, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(pl->d_tile_plane, tile_plane.data(), sizeof(uint32_t) * (size_t)tiles, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(pl->d_tile_org, tile_org.data(), sizeof(uint32_t) * (size_t)tiles, hipMemcpyHostToDevice) !=
           hipSuccess) {
     ug_plan_destroy(pl);
     return UG_ERR_HIP;
@@ -425,8 +433,7 @@ int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const 
   if (e != hipSuccess) return UG_ERR_HIP;
   {
     StageScope sc(plan, UG_STAGE_ACCUM_BWD, s);
-    e = launch_accum_bwd(plan->prm.tile_w, plan->prm.tile_h, ctrl, plan->d_pint, plan->d_tile_plane,
-                         so.key, so.val, so.rec, at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo),
+    e = launch_accum_bwd(plan->prm.tile_w, plan->prm.tile_h, ctrl, plan->d_tile_org, so.key, so.val, so.rec, at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo),
                          at<float>(ws, L.gq),
                          at<float>(ws, L.partial), plan->key_cap, s);
   }
@@ -571,6 +578,7 @@ void ug_plan_destroy(ug_plan* plan) {
   prof_release(plan);
   if (plan->d_pint) (void)hipFree(plan->d_pint);
   if (plan->d_tile_plane) (void)hipFree(plan->d_tile_plane);
+  if (plan->d_tile_org) (void)hipFree(plan->d_tile_org);
   delete plan;
 }
 

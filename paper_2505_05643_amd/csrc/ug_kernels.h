@@ -79,8 +79,9 @@ hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneIn
 hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const uint32_t* tile_plane,
                            const float* image, const float* d_image, const float* dsave, float* gq,
                            uint32_t num_tiles, hipStream_t s);
-hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const PlaneInt* pint,
-                            const uint32_t* tile_plane, const uint32_t* skey, const uint32_t* sval,
+// tile_org[t] = pixel origin of tile t, x0 | y0 << 16.
+hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint32_t* tile_org,
+                            const uint32_t* skey, const uint32_t* sval,
                             const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo,
                             const float* gq, float* partial, uint32_t key_cap, hipStream_t s);
 

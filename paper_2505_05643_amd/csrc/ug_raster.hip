@@ -72,19 +72,24 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
   RecAcc pa[PER];
   RecGeo pg[PER];
   uint32_t pm[PER];
+  // key words and record ids are loaded together (not the id behind the
+  // mask test), then the records whose mask touches the band
   auto fetch = [&](uint32_t base) {
+    uint32_t kw[PER], rid[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const uint32_t j = base + (uint32_t)(q * 64 + lane);
-      pm[q] = 0u;
-      if (q * 64 + lane < BG && j < e) {
-        const uint32_t m = (skey[j] >> bshift) & bmask;
-        pm[q] = m;
-        if (m) {
-          const uint32_t r = srec[j];
-          pa[q] = racc[r];
-          pg[q] = rgeo[r];
-        }
+      const bool in = q * 64 + lane < BG && j < e;
+      kw[q] = in ? skey[j] : 0u;
+      rid[q] = in ? srec[j] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const uint32_t m = (kw[q] >> bshift) & bmask;
+      pm[q] = m;
+      if (m) {
+        pa[q] = racc[rid[q]];
+        pg[q] = rgeo[rid[q]];
       }
     }
   };
@@ -201,8 +206,8 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const PlaneInt* __restrict__ p
 constexpr int kBwdSlots = 192;
 
 template <int TW, int TH>
-__global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl, const PlaneInt* __restrict__ pint,
-                                                   const uint32_t* __restrict__ tile_plane,
+__global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl,
+                                                   const uint32_t* __restrict__ tile_org,
                                                    const uint32_t* __restrict__ skey,
                                                    const uint32_t* __restrict__ sval,
                                                    const uint32_t* __restrict__ srec,
@@ -236,10 +241,8 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
       const uint32_t r = srec[i];
       const RecAcc A = racc[r];
       const RecGeo Gg = rgeo[r];
-      const PlaneInt PI = pint[tile_plane[t]];
-      const uint32_t lt = t - PI.tile_off;
-      const int x0 = (int)(lt % (uint32_t)PI.ntx) * TW;
-      const int y0 = (int)(lt / (uint32_t)PI.ntx) * TH;
+      const uint32_t org = tile_org[t];  // x0 | y0 << 16
+      const int x0 = (int)(org & 0xffffu), y0 = (int)(org >> 16);
       const float du0 = (float)(Gg.ub - x0) + A.fu;
       const float dv0 = (float)(Gg.vb - y0) + A.fv;
       kpA[wave][lane] = make_float4(A.t11, A.t12, A.t22, -A.t11 * du0);
@@ -456,8 +459,8 @@ hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const u
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const PlaneInt* pint,
-                            const uint32_t* tile_plane, const uint32_t* skey, const uint32_t* sval,
+hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint32_t* tile_org,
+                            const uint32_t* skey, const uint32_t* sval,
                             const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo,
                             const float* gq, float* partial, uint32_t key_cap, hipStream_t s) {
   const float2* g2 = reinterpret_cast<const float2*>(gq);
@@ -466,8 +469,8 @@ hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const Plan
   const uint32_t blocks = want < 1u ? 1u : (want > 16384u ? 16384u : want);
 #define UG_BWD(W, H)                                                                                          \
   if (tile_w == W && tile_h == H) {                                                                           \
-    hipLaunchKernelGGL((k_accum_bwd<W, H>), dim3(blocks), dim3(256), 0, s, ctrl, pint, tile_plane, skey, sval, \
-                       srec, racc, rgeo, g2, p4);                                                             \
+    hipLaunchKernelGGL((k_accum_bwd<W, H>), dim3(blocks), dim3(256), 0, s, ctrl, tile_org, skey, sval, srec, \
+                       racc, rgeo, g2, p4);                                                                   \
     return hipGetLastError();                                                                                 \
   }
   UG_TILE_SHAPES(UG_BWD)
