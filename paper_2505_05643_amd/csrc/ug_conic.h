@@ -41,7 +41,7 @@ struct ConicT {
   T m1, m2, m3;
   T g1[3], g2[3], g3[3];
   T b1[3], b2[3];
-  T S11, S22, S33, S13, S23;
+  T S11, S22, S33, S13, S23, iS;  // iS = 1 / S33
   T T11, T12, T22, detL, n3;
   T c1, c2, r2;
 };
@@ -97,11 +97,13 @@ __device__ __forceinline__ void load_gauss(const ug_gaussians& g, int i, T beta,
   G.iL11 = (T)1 / G.L11;
   G.iL22 = (T)1 / G.L22;
   G.iL33 = (T)1 / G.L33;
-  // alpha = sigmoid(a); log2(alpha) = -softplus(-a) / ln 2, stable for any a.
-  const T na = -G.a;
-  const T sp = (na > (T)0 ? na : (T)0) + log1p(exp(-fabs(na)));
-  G.log2a = -sp / (T)kLn2;
-  G.alpha = (T)1 / ((T)1 + exp(na));
+  // alpha = sigmoid(a); log2(alpha) = -softplus(-a) / ln 2, stable for any
+  // a.  In single precision for both types: the records hold it in float
+  // (e0 and emin), so a double evaluation would only cost time.
+  const float na = -(float)G.a;
+  const float sp = fmaxf(na, 0.f) + log1pf(expf(-fabsf(na)));
+  G.log2a = (T)(-sp * (float)(1.0 / kLn2));
+  G.alpha = (T)(1.f / (1.f + expf(na)));
 }
 
 // Forward substitution y = L^-1 q.
@@ -141,6 +143,7 @@ __device__ __forceinline__ void conic_full(const GaussT<T>& G, const PlaneT<T>& 
   fsub(G, P.rinv[0], P.rinv[1], P.rinv[2], k.g1);
   fsub(G, P.rinv[3], P.rinv[4], P.rinv[5], k.g2);
   const T iS = (T)1 / k.S33;
+  k.iS = iS;
   k.r2 = k.m3 * k.m3 * iS;
   k.S11 = k.g1[0] * k.g1[0] + k.g1[1] * k.g1[1] + k.g1[2] * k.g1[2];
   k.S22 = k.g2[0] * k.g2[0] + k.g2[1] * k.g2[1] + k.g2[2] * k.g2[2];
@@ -337,8 +340,8 @@ __device__ __forceinline__ bool make_footprint(const GaussIn& G, const PlaneCons
     // Sigma'_kk - Sigma'_k3^2 / Sigma'_33 = |g_k x g3|^2 / |g3|^2.
     double q = chi2 - k.r2;
     q = q > 0.0 ? q : 0.0;
-    if (!pixel_range(u0, sqrt(q * cross_norm2(k.g1, k.g3) / k.S33) / P.sx, PI.W, ulo, uhi)) return false;
-    if (!pixel_range(v0, sqrt(q * cross_norm2(k.g2, k.g3) / k.S33) / P.sy, PI.H, vlo, vhi)) return false;
+    if (!pixel_range(u0, sqrt(q * cross_norm2(k.g1, k.g3) * k.iS) / P.sx, PI.W, ulo, uhi)) return false;
+    if (!pixel_range(v0, sqrt(q * cross_norm2(k.g2, k.g3) * k.iS) / P.sy, PI.H, vlo, vhi)) return false;
   }
   double ubd = floor(u0 + 0.5), vbd = floor(v0 + 0.5);
   ubd = ubd < -1.0e9 ? -1.0e9 : (ubd > 1.0e9 ? 1.0e9 : ubd);
@@ -396,7 +399,7 @@ __device__ __forceinline__ void footprint_adjoint(const GaussT<T>& G, const Plan
     db2[j] = dT12 * k.b1[j] * iT11;
   }
   // c1 = m1 - m3 S13/S33, c2 = m2 - m3 S23/S33, r2 = m3^2 / S33
-  const T iS = (T)1 / k.S33;
+  const T iS = k.iS;
   T dm[3];
   dm[0] = dc1;
   dm[1] = dc2;

@@ -233,6 +233,17 @@ __global__ __launch_bounds__(256) void k_cull_write(RenderParams rp, int gpb, ui
 // ---------------------------------------------------------------- record pass
 // Lanes = records (every lane an accepted pair: no divergence); a block
 // covers rpb consecutive records in rounds of 256.
+
+// Records per block from the device-side record count: whole rounds of 256
+// spread evenly over the grid (sized by the host for the capacity), so every
+// block has a share whatever the head-room.  The record and emission kernels
+// use the same split (the emission's block prefix reads the record blocks'
+// totals).
+__device__ __forceinline__ uint32_t record_rpb_dev(uint32_t nrec, uint32_t grid) {
+  const uint32_t rounds = (nrec + 255u) / 256u;
+  const uint32_t per = (rounds + grid - 1u) / grid;
+  return (per < 1u ? 1u : per) * 256u;
+}
 __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, const PlaneInt& PI, int box_mode,
                                           int TW, int TH, uint32_t r, uint32_t e, uint32_t e_end,
                                           uint32_t* __restrict__ key_tile, uint32_t* __restrict__ rec_of_key) {
@@ -269,19 +280,20 @@ __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, c
 // FP64 in-plane conic and footprint of each record; key counts and the
 // block's total.
 __global__ __launch_bounds__(256) void k_record(ug_gaussians g, const PlaneConst* __restrict__ pc,
-                                                const PlaneInt* __restrict__ pint, RenderParams rp, int rpb,
+                                                const PlaneInt* __restrict__ pint, RenderParams rp,
                                                 const uint2* __restrict__ rec_pair, RecAcc* __restrict__ racc,
                                                 RecGeo* __restrict__ rgeo, uint32_t* __restrict__ rec_nkey,
                                                 uint32_t* __restrict__ blk_tot, const Ctrl* __restrict__ ctrl) {
   __shared__ uint32_t s_tot;
   const uint32_t nrec = ctrl->n_rec_eff;
-  const uint32_t r_begin = blockIdx.x * (uint32_t)rpb;
+  const uint32_t rpb = record_rpb_dev(nrec, gridDim.x);
+  const uint32_t r_begin = blockIdx.x * rpb;
   if (r_begin >= nrec) return;  // uniform
   if (threadIdx.x == 0) s_tot = 0;
   __syncthreads();
   const double chi2 = (double)rp.chi2;
   uint32_t mine = 0;
-  const uint32_t r_end = min(r_begin + (uint32_t)rpb, nrec);
+  const uint32_t r_end = min(r_begin + rpb, nrec);
   for (uint32_t r = r_begin + threadIdx.x; r < r_end; r += 256) {
     const uint2 gp = rec_pair[r];
     GaussIn G;
@@ -310,7 +322,7 @@ __global__ __launch_bounds__(256) void k_record(ug_gaussians g, const PlaneConst
 
 // Key offsets (block prefix + in-block scan) and key emission.  The last
 // active block publishes the key total and the capacity check.
-__global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint, RenderParams rp, int rpb,
+__global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint, RenderParams rp,
                                               const uint2* __restrict__ rec_pair, const RecAcc* __restrict__ racc,
                                               const RecGeo* __restrict__ rgeo, const uint32_t* __restrict__ rec_nkey,
                                               const uint32_t* __restrict__ blk_tot, uint32_t* __restrict__ rec_koff,
@@ -318,11 +330,12 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
                                               uint32_t* __restrict__ rec_of_key) {
   __shared__ unsigned long long s_sh[4];
   const uint32_t nrec = ctrl->n_rec_eff;
-  const uint32_t r_begin = blockIdx.x * (uint32_t)rpb;
+  const uint32_t rpb = record_rpb_dev(nrec, gridDim.x);
+  const uint32_t r_begin = blockIdx.x * rpb;
   if (r_begin >= nrec) return;  // uniform
-  const uint32_t nact = (nrec + (uint32_t)rpb - 1) / (uint32_t)rpb;
+  const uint32_t nact = (nrec + rpb - 1) / rpb;
   unsigned long long carry = block_prefix(blk_tot, blockIdx.x, s_sh);
-  const uint32_t r_end = min(r_begin + (uint32_t)rpb, nrec);
+  const uint32_t r_end = min(r_begin + rpb, nrec);
   for (uint32_t r0 = r_begin; r0 < r_end; r0 += 256) {
     const uint32_t r = r0 + threadIdx.x;
     const bool act = r < r_end;
@@ -406,10 +419,22 @@ __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const Pl
       gid = gp.x;
       const uint32_t k0 = rec_koff[r], k1 = rec_koff[r + 1];
       float4 a = make_float4(0.f, 0.f, 0.f, 0.f), c = a;
-      for (uint32_t k = k0; k < k1; ++k) {
-        const float4 x = partial[2 * (size_t)k], y = partial[2 * (size_t)k + 1];
-        a.x += x.x; a.y += x.y; a.z += x.z; a.w += x.w;
-        c.x += y.x; c.y += y.y; c.z += y.z; c.w += y.w;
+      // two keys per step, both loaded before either is added (same order
+      // of additions as one key at a time)
+      for (uint32_t k = k0; k < k1; k += 2) {
+        const float4 x0 = partial[2 * (size_t)k], y0 = partial[2 * (size_t)k + 1];
+        const bool two = k + 1 < k1;
+        float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f), y1 = x1;
+        if (two) {
+          x1 = partial[2 * (size_t)k + 2];
+          y1 = partial[2 * (size_t)k + 3];
+        }
+        a.x += x0.x; a.y += x0.y; a.z += x0.z; a.w += x0.w;
+        c.x += y0.x; c.y += y0.y; c.z += y0.z; c.w += y0.w;
+        if (two) {
+          a.x += x1.x; a.y += x1.y; a.z += x1.z; a.w += x1.w;
+          c.x += y1.x; c.y += y1.y; c.z += y1.z; c.w += y1.w;
+        }
       }
       if (k1 > k0) {
         const float dr[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
@@ -582,14 +607,14 @@ hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const Plan
                          const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* blk_tot,
                          Ctrl* ctrl, hipStream_t s) {
   hipLaunchKernelGGL(k_record, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, g, pc, pint, rp,
-                     record_rpb(rp.rec_cap), rec_pair, racc, rgeo, rec_nkey, blk_tot, ctrl);
+                     rec_pair, racc, rgeo, rec_nkey, blk_tot, ctrl);
   return hipGetLastError();
 }
 
 hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const RecAcc* racc,
                        const RecGeo* rgeo, const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
                        Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, hipStream_t s) {
-  hipLaunchKernelGGL(k_emit, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, pint, rp, record_rpb(rp.rec_cap),
+  hipLaunchKernelGGL(k_emit, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, pint, rp,
                      rec_pair, racc, rgeo, rec_nkey, blk_tot, rec_koff, ctrl, key_tile, rec_of_key);
   return hipGetLastError();
 }
