@@ -73,6 +73,30 @@ def test_one_pixel_planes_and_far_planes(R):
     assert np.all(img[-256:] == 0.0)  # the far plane sees background only
 
 
+def test_in_plane_rotation_gives_rot90(R):
+    """Rotating a plane's in-plane axes by 90 degrees about its normal
+    (e1' = e2, e2' = -e1) on a centred square grid samples the same 3D
+    points, so the image rotates: image'[v, u] = image[u, W-1-v], which is
+    numpy's rot90.  Both renders are also checked against the oracle; the
+    two may differ by more than the tolerance only where a pair sits on the
+    cut-off (rare)."""
+    g = synth.make_gaussians(400, 51, (0.2, 0.2, 0.2), (0.8, 0.8, 0.8), (0.02, 0.1), opacity="random")
+    base = synth.axis_angle((1, 2, 3), 0.7)
+    e1, e2, n = base[:, 0], base[:, 1], base[:, 2]
+    turned = np.stack([e2, -e1, n], axis=1)
+    W = 48
+    pl = synth.pack_planes([base, turned], [(0.5, 0.5, 0.5)] * 2, [(1 / W, 1 / W)] * 2, [(W, W)] * 2)
+    assert np.array_equal(pl.rot[1].reshape(3, 3)[:, 0], pl.rot[0].reshape(3, 3)[:, 1])  # exact in float32
+    for bm in (0, 1, 2):
+        img, plan = _render(R, g, pl, R.Params(box_mode=bm))
+        st = check_image(img, g, pl, plan.params)
+        a, b = img[:W * W].reshape(W, W), img[W * W:].reshape(W, W)
+        diff = np.abs(b.astype(np.float64) - np.rot90(a).astype(np.float64))
+        off = int(np.sum(diff > 2e-4 * st["peak"]))
+        assert off <= max(1, 1e-3 * W * W), f"box {bm}: {off} pixels differ from rot90"
+        print("rot90 box", bm, "max diff / peak", float(diff.max() / st["peak"]), "off", off)
+
+
 def test_tile_shapes_box_modes_batches(R):
     """Within one tile shape, every LDS batch and binning box gives the same
     image bit for bit (each pixel sums its in-support Gaussians in record
