@@ -172,28 +172,51 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
 
 // ---------------------------------------------------------------- backward prep
 // Tile-major padded per-pixel adjoint inputs: gamma = dL/dc_hat / D and
-// gamma * c_hat (zero outside the plane).
+// gamma * c_hat (zero outside the plane).  Four consecutive pixels of a tile
+// row per thread: 16-byte loads where the arrays (vec) and the plane row are
+// aligned and the row holds all four, single loads otherwise.
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_bwd_prep(const PlaneInt* __restrict__ pint,
                                                   const uint32_t* __restrict__ tile_plane,
                                                   const float* __restrict__ image, const float* __restrict__ d_image,
-                                                  const float* __restrict__ dsave, float2* __restrict__ gq,
-                                                  uint32_t num_tiles) {
-  const size_t gidx = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const uint32_t t = (uint32_t)(gidx / (TW * TH));
+                                                  const float* __restrict__ dsave, float4* __restrict__ gq,
+                                                  uint32_t num_tiles, int vec) {
+  static_assert(TW % 4 == 0, "four pixels per thread within a tile row");
+  const size_t gidx = (size_t)blockIdx.x * 256 + threadIdx.x;  // group of four pixels
+  const uint32_t t = (uint32_t)(gidx / (TW * TH / 4));
   if (t >= num_tiles) return;
-  const int j = (int)(gidx % (TW * TH));
+  const int j = (int)(gidx % (TW * TH / 4)) * 4;
   const PlaneInt PI = pint[tile_plane[t]];
   const uint32_t lt = t - PI.tile_off;
   const int u = (int)(lt % (uint32_t)PI.ntx) * TW + j % TW;
   const int v = (int)(lt / (uint32_t)PI.ntx) * TH + j / TW;
-  float2 out = make_float2(0.f, 0.f);
-  if (u < PI.W && v < PI.H) {
+  float gam[4] = {0.f, 0.f, 0.f, 0.f}, gc[4] = {0.f, 0.f, 0.f, 0.f};
+  if (v < PI.H && u < PI.W) {
     const size_t idx = (((size_t)PI.pix_off_hi << 32) | PI.pix_off_lo) + (size_t)v * PI.W + u;
-    const float gam = d_image[idx] / dsave[idx];
-    out = make_float2(gam, gam * image[idx]);
+    if (vec && u + 3 < PI.W && (idx & 3u) == 0) {
+      const float4 dI = *reinterpret_cast<const float4*>(d_image + idx);
+      const float4 Dt = *reinterpret_cast<const float4*>(dsave + idx);
+      const float4 I = *reinterpret_cast<const float4*>(image + idx);
+      gam[0] = dI.x / Dt.x;
+      gam[1] = dI.y / Dt.y;
+      gam[2] = dI.z / Dt.z;
+      gam[3] = dI.w / Dt.w;
+      gc[0] = gam[0] * I.x;
+      gc[1] = gam[1] * I.y;
+      gc[2] = gam[2] * I.z;
+      gc[3] = gam[3] * I.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (u + q < PI.W) {
+          gam[q] = d_image[idx + q] / dsave[idx + q];
+          gc[q] = gam[q] * image[idx + q];
+        }
+      }
+    }
   }
-  gq[gidx] = out;
+  gq[2 * gidx] = make_float4(gam[0], gc[0], gam[1], gc[1]);
+  gq[2 * gidx + 1] = make_float4(gam[2], gc[2], gam[3], gc[3]);
 }
 
 // ---------------------------------------------------------------- backward
@@ -445,13 +468,15 @@ hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneIn
 hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const uint32_t* tile_plane,
                            const float* image, const float* d_image, const float* dsave, float* gq,
                            uint32_t num_tiles, hipStream_t s) {
-  const size_t total = (size_t)num_tiles * tile_w * tile_h;
-  const dim3 grid((unsigned)((total + 255) / 256));
-  float2* g2 = reinterpret_cast<float2*>(gq);
+  const size_t groups = (size_t)num_tiles * tile_w * tile_h / 4;  // four pixels per thread
+  const dim3 grid((unsigned)((groups + 255) / 256));
+  float4* g4 = reinterpret_cast<float4*>(gq);
+  const int vec = (reinterpret_cast<uintptr_t>(image) | reinterpret_cast<uintptr_t>(d_image) |
+                   reinterpret_cast<uintptr_t>(dsave)) % 16 == 0;
 #define UG_PREP(W, H)                                                                                              \
   if (tile_w == W && tile_h == H) {                                                                                \
-    hipLaunchKernelGGL((k_bwd_prep<W, H>), grid, dim3(256), 0, s, pint, tile_plane, image, d_image, dsave, g2,     \
-                       num_tiles);                                                                                 \
+    hipLaunchKernelGGL((k_bwd_prep<W, H>), grid, dim3(256), 0, s, pint, tile_plane, image, d_image, dsave, g4,     \
+                       num_tiles, vec);                                                                            \
     return hipGetLastError();                                                                                      \
   }
   UG_TILE_SHAPES(UG_PREP)
