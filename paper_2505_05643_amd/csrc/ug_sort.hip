@@ -111,7 +111,7 @@ struct SortSet {
 };
 
 template <int kItems, int D>
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __restrict__ ctrl, SortSet in,
+__device__ __forceinline__ void radix_scatter(const Ctrl* __restrict__ ctrl, SortSet in,
                                                                 SortSet out, bool gen_val,
                                                                 const uint32_t* __restrict__ cnt,
                                                                 const uint32_t* __restrict__ coltot, uint32_t G,
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
     // the round's keys split evenly over the waves, in whole loads of 64
     const uint32_t n_round = min((uint32_t)kRound, e - base);
     const uint32_t seg = ((n_round + 255u) / 256u) * 64u;
-    uint32_t kk[kItems], vv[kItems], rr[kItems];
+    uint32_t kk[kItems], rr[kItems];
     // all of the round's loads first: the ranking's wave fences would
     // otherwise keep each load behind the previous key's LDS update
 #pragma unroll
@@ -193,7 +193,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
       wave_lds_sync();
       if (valid && lanemask_lt_popc(peers) == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
       wave_lds_sync();
-      vv[it] = i;
       rr[it] = valid ? before + lanemask_lt_popc(peers) : 0xffffffffu;
     }
     __syncthreads();
@@ -236,33 +235,37 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
         const uint32_t d = (kk[it] >> shift) & dmask;
         const uint32_t slot = loc[d] + wcnt[wave][d] + rr[it];
         s_key[slot] = kk[it];
-        s_src[slot] = vv[it];
+        s_src[slot] = base + (uint32_t)wave * seg + (uint32_t)(it * 64 + lane);  // the key's input position
       }
     }
     __syncthreads();
     // write-out: every slot's payload is gathered before any store (the
     // input and output sets are different arrays, which the compiler cannot
     // know, so interleaved loads would wait for the stores before them)
-    uint32_t opos[kItems], oval[kItems], orec[kItems];
+    constexpr int kHalf = kItems < 8 ? kItems : 8;  // slots gathered per batch
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const uint32_t i = (uint32_t)tid + (uint32_t)(j * kSortThreads);
-      opos[j] = 0xffffffffu;
-      if (i < n_round) {
-        const uint32_t k = s_key[i], src = s_src[i];
-        const uint32_t d = (k >> shift) & dmask;
-        opos[j] = run[d] + (i - loc[d]);
-        kk[j] = k;
-        oval[j] = gen_val ? src : in.val[src];
-        orec[j] = in.rec[src];
+    for (int h = 0; h < kItems; h += kHalf) {
+      uint32_t opos[kHalf], okey[kHalf], oval[kHalf], orec[kHalf];
+#pragma unroll
+      for (int j = 0; j < kHalf; ++j) {
+        const uint32_t i = (uint32_t)tid + (uint32_t)((h + j) * kSortThreads);
+        opos[j] = 0xffffffffu;
+        if (i < n_round) {
+          const uint32_t k = s_key[i], src = s_src[i];
+          const uint32_t d = (k >> shift) & dmask;
+          opos[j] = run[d] + (i - loc[d]);
+          okey[j] = k;
+          oval[j] = gen_val ? src : in.val[src];
+          orec[j] = in.rec[src];
+        }
       }
-    }
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      if (opos[j] != 0xffffffffu) {
-        out.key[opos[j]] = kk[j];
-        out.val[opos[j]] = oval[j];
-        out.rec[opos[j]] = orec[j];
+      for (int j = 0; j < kHalf; ++j) {
+        if (opos[j] != 0xffffffffu) {
+          out.key[opos[j]] = okey[j];
+          out.val[opos[j]] = oval[j];
+          out.rec[opos[j]] = orec[j];
+        }
       }
     }
     __syncthreads();
@@ -270,6 +273,26 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __re
     for (int k = 0; k < kPer; ++k) run[tid * kPer + k] += rcnt[tid * kPer + k];
     __syncthreads();
   }
+}
+
+// Kernels around the scatter body.  The large-input variant (16 keys per
+// thread and round, 256 digits) is held to four workgroups per CU, which its
+// LDS allows; the compiler would otherwise give it more registers and three.
+template <int kItems, int D>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const Ctrl* __restrict__ ctrl, SortSet in,
+                                                                SortSet out, bool gen_val,
+                                                                const uint32_t* __restrict__ cnt,
+                                                                const uint32_t* __restrict__ coltot, uint32_t G,
+                                                                int shift, int dbits, uint32_t* __restrict__ tile_start,
+                                                                uint32_t T) {
+  radix_scatter<kItems, D>(ctrl, in, out, gen_val, cnt, coltot, G, shift, dbits, tile_start, T);
+}
+
+__global__ __launch_bounds__(kSortThreads, 4) void k_radix_scatter_large(
+    const Ctrl* __restrict__ ctrl, SortSet in, SortSet out, bool gen_val, const uint32_t* __restrict__ cnt,
+    const uint32_t* __restrict__ coltot, uint32_t G, int shift, int dbits, uint32_t* __restrict__ tile_start,
+    uint32_t T) {
+  radix_scatter<16, 256>(ctrl, in, out, gen_val, cnt, coltot, G, shift, dbits, tile_start, T);
 }
 
 // tile_start[t] = first sorted key index whose tile id is >= t (t in [0, T]).
@@ -378,7 +401,7 @@ hipError_t launch_radix_scatter(const Ctrl* ctrl, const uint32_t* const in[3], u
     hipLaunchKernelGGL((k_radix_scatter<8, 1024>), dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
                        hist, coltot, G, db * pass, db, tile_start, num_tiles);
   else if (G >= kSortMaxBlocks)
-    hipLaunchKernelGGL((k_radix_scatter<16, 256>), dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
+    hipLaunchKernelGGL(k_radix_scatter_large, dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
                        hist, coltot, G, db * pass, db, tile_start, num_tiles);
   else
     hipLaunchKernelGGL((k_radix_scatter<8, 256>), dim3(G), dim3(kSortThreads), 0, s, ctrl, si, so, pass == 0,
