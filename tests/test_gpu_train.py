@@ -33,6 +33,33 @@ def _adam_ref(p, g_seq, cfg, seg_lr):
     return p
 
 
+@pytest.mark.parametrize("m,offset", [(1, 0), (7, 0), (1023, 0), (12293, 0), (409_600, 0), (409_603, 1),
+                                      (2_000_001, 0)])
+def test_mse_grad_matches_numpy(M, m, offset):
+    """d_image = 2 (image - target) / m and the mean squared error, against
+    float64 numpy; offset 1 makes the arrays 4-byte (not 16-byte) aligned,
+    so the single-pixel path runs.  Called twice on the same scratch
+    buffer: the block counter must be left at zero."""
+    R, _ = M
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(m)
+    img = rng.standard_normal(m + offset).astype(np.float32)
+    tgt = rng.standard_normal(m + offset).astype(np.float32)
+    a = torch.from_numpy(img).to(dev)[offset:]
+    b = torch.from_numpy(tgt).to(dev)[offset:]
+    d = torch.empty(m + offset, dtype=torch.float32, device=dev)[offset:]
+    buf = torch.zeros(R._lib.UG_MSE_SCRATCH_FLOATS, dtype=torch.float32, device=dev)
+    diff = img[offset:].astype(np.float64) - tgt[offset:].astype(np.float64)
+    ref_d = 2.0 * diff / m
+    ref_loss = float(np.mean(diff * diff))
+    for _ in range(2):
+        loss, dimg = R.mse_grad(a, b, d, buf)
+        torch.cuda.synchronize()
+        got = dimg.cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - ref_d)) <= 1e-6 * np.max(np.abs(ref_d))
+        assert abs(float(loss.item()) - ref_loss) <= 1e-5 * ref_loss
+
+
 def test_adam_gaussians_matches_reference(M):
     R, S = M
     dev = torch.device("cuda", 0)
