@@ -5,24 +5,48 @@ namespace ug {
 
 constexpr int kMseBlocks = 1024;
 
-// Each block: d_image over a contiguous chunk and the chunk's squared-error
-// sum (fixed-order tree), written to loss[1 + block]; the last block to
-// finish (a counter in loss[1 + kMseBlocks], left at zero) adds the block
-// sums in block order in double and writes the mean to loss[0].
+// Each block: d_image over a contiguous chunk (a multiple of 1024 pixels)
+// and the chunk's squared-error sum (fixed-order tree), written to
+// loss[1 + block]; the last block to finish (a counter in
+// loss[1 + kMseBlocks], left at zero) adds the block sums in block order in
+// double and writes the mean to loss[0].  With 16-byte aligned arrays (vec)
+// a thread takes four pixels per step.
 __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ image, const float* __restrict__ target,
-                                             int64_t m, float* __restrict__ d_image, float* __restrict__ loss) {
+                                             int64_t m, float* __restrict__ d_image, float* __restrict__ loss,
+                                             int vec) {
   __shared__ float sh[256];
   __shared__ double shd[256];
   __shared__ bool last;
-  const int64_t chunk = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t chunk = ((m + gridDim.x - 1) / gridDim.x + 1023) / 1024 * 1024;
   const int64_t a = (int64_t)blockIdx.x * chunk;
   const int64_t b = a + chunk < m ? a + chunk : m;
   const float scale = 2.0f / (float)m;
   float acc = 0.f;
-  for (int64_t i = a + threadIdx.x; i < b; i += 256) {
-    const float d = image[i] - target[i];
-    d_image[i] = scale * d;
-    acc = fmaf(d, d, acc);
+  if (vec) {
+    const int64_t b4 = a < b ? a + (b - a) / 4 * 4 : a;  // whole groups of four
+#pragma unroll 4
+    for (int64_t i = a + 4 * (int64_t)threadIdx.x; i < b4; i += 1024) {
+      const float4 x = *reinterpret_cast<const float4*>(image + i);
+      const float4 y = *reinterpret_cast<const float4*>(target + i);
+      const float4 d = make_float4(x.x - y.x, x.y - y.y, x.z - y.z, x.w - y.w);
+      *reinterpret_cast<float4*>(d_image + i) = make_float4(scale * d.x, scale * d.y, scale * d.z, scale * d.w);
+      acc = fmaf(d.x, d.x, acc);
+      acc = fmaf(d.y, d.y, acc);
+      acc = fmaf(d.z, d.z, acc);
+      acc = fmaf(d.w, d.w, acc);
+    }
+    const int64_t i = b4 + threadIdx.x;  // fewer than four left at the end
+    if (i < b) {
+      const float d = image[i] - target[i];
+      d_image[i] = scale * d;
+      acc = fmaf(d, d, acc);
+    }
+  } else {
+    for (int64_t i = a + threadIdx.x; i < b; i += 256) {
+      const float d = image[i] - target[i];
+      d_image[i] = scale * d;
+      acc = fmaf(d, d, acc);
+    }
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
@@ -136,9 +160,11 @@ hipError_t launch_adam_gaussians(float* const p[4], const float* const g[4], flo
 
 hipError_t launch_mse(const float* image, const float* target, int64_t m, float* d_image, float* loss,
                       hipStream_t s) {
-  int64_t want = (m + 4095) / 4096;
+  int64_t want = (m + 4095) / 4096;  // few blocks: each one's release fence is costly
   const int blocks = (int)(want < 1 ? 1 : (want > kMseBlocks ? kMseBlocks : want));
-  hipLaunchKernelGGL(k_mse, dim3(blocks), dim3(256), 0, s, image, target, m, d_image, loss);
+  const int vec = (reinterpret_cast<uintptr_t>(image) | reinterpret_cast<uintptr_t>(target) |
+                   reinterpret_cast<uintptr_t>(d_image)) % 16 == 0;
+  hipLaunchKernelGGL(k_mse, dim3(blocks), dim3(256), 0, s, image, target, m, d_image, loss, vec);
   return hipGetLastError();
 }
 
