@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--box", type=int, default=None, help="0 paper, 1 conic, 2 rows")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-plane comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-scatter", action="store_true", help="skip timing the Phase-2 atomic scatter forward")
     ap.add_argument("--cpu-px", type=int, default=640)
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch configuration")
@@ -230,6 +231,25 @@ def main():
             train_ms = None
         del ts, tparams
 
+    # the paper's own accumulation (Phase 2 atomic scatter) on the same
+    # records, for comparison with the gather forward above
+    scatter = None
+    if not args.no_graph and not args.no_scatter:
+        sparams = R.Params(**{**params.__dict__, "flags": R._lib.UG_FLAG_SCATTER})
+        splan = R.Plan(g.n, pl.wh, sparams, device=dev)
+        splan.fit(gd, pd)
+        simg = torch.empty_like(image)
+        s_ms = replay_ms(lambda: splan.render(gd, pd, simg, check_status=False), 1, max(2, args.steps // 10))
+        ok = splan.status() == 0
+        # the two agree to float rounding except where a pair sits on the
+        # cut-off (their exponents round differently): count those pixels
+        peak = max(float(image.abs().max()), 1e-30)
+        off = int(((simg - image).abs() > 1e-4 * peak).sum())
+        scatter = {"forward_ms": s_ms if ok else None, "gather_forward_ms": fwd_ms,
+                   "gather_speedup": (s_ms / fwd_ms) if (ok and fwd_ms) else None,
+                   "pixels_off_gather_by_1e-4_peak": off, "pixels": int(image.numel())}
+        del splan, simg
+
     # in-support pairs of one forward, counted by the kernel itself
     cparams = R.Params(**{**params.__dict__, "flags": 1})
     cplan = R.Plan(g.n, pl.wh, cparams, device=dev)
@@ -343,6 +363,7 @@ def main():
         "graph_ms_per_step": graph_ms_step,
         "forward_only_ms": fwd_ms,
         "train_step_ms": train_ms,
+        "paper_phase2_scatter": scatter,
         "evals_per_s": evals_s,
         "in_support_pairs": n_eval,
         "records": n_rec,

@@ -55,6 +55,13 @@ extern "C" {
 
 /* ---- params.flags bits ------------------------------------------------ */
 #define UG_FLAG_COUNT_EVALS 1 /* forward also counts in-support (Gaussian, pixel) pairs */
+#define UG_FLAG_SCATTER 2     /* forward by the paper's Phase 2 (Sec. 4.4): every record
+                                 adds to per-pixel sums with atomic adds over its box,
+                                 instead of the tile-binned gather; same per-pair test,
+                                 so the same image to float rounding (the order of the
+                                 atomic additions is not fixed).  Forward only: the
+                                 backward of such a plan returns UG_ERR_INVALID_ARG, and
+                                 no keys are emitted (key_capacity may be 0)          */
 
 /* ---- pipeline stages (measurement hooks) ------------------------------- */
 #define UG_STAGE_SETUP 0         /* plane pose set-up                                  */
@@ -71,7 +78,8 @@ extern "C" {
 #define UG_STAGE_ACCUM_BWD 11    /* per-key adjoint of the accumulation                 */
 #define UG_STAGE_RECORD_ADJ 12   /* per-record adjoint of the conic construction        */
 #define UG_STAGE_GAUSS_GRAD 13   /* per-Gaussian sum of its records' adjoints           */
-#define UG_NUM_STAGES 14
+#define UG_STAGE_SCATTER 14      /* UG_FLAG_SCATTER forward: zero, scatter, normalise   */
+#define UG_NUM_STAGES 15
 
 typedef struct ug_plan ug_plan; /* opaque, host-side */
 
@@ -150,7 +158,8 @@ int ug_plan_measure(const ug_plan *plan, const ug_gaussians *g, const ug_planes 
 
 /* Forward render (Section 4.1-4.4).  image: [num_pixels] float32, packed
  * plane after plane, row-major (index v*W + u).  Fills the workspace with the
- * state the backward needs (records, sorted keys, per-pixel denominators). */
+ * state the backward needs (records, sorted keys, per-pixel denominators).
+ * With UG_FLAG_SCATTER the accumulation is the atomic scatter of Phase 2. */
 int ug_render_planes(const ug_plan *plan, const ug_gaussians *g, const ug_planes *planes,
                      float *image, void *workspace, void *stream);
 
@@ -160,6 +169,7 @@ int ug_render_planes(const ug_plan *plan, const ug_gaussians *g, const ug_planes
  * d_means [n][3], d_lraw [n][6], d_intensity [n], d_opacity [n] (logits).
  * accumulate = 0 overwrites them, 1 adds to them.  The cut-off set of Eq. 12
  * is held fixed (the map is piecewise smooth).  Deterministic: no atomics. */
+/* Plans with UG_FLAG_SCATTER have no backward (UG_ERR_INVALID_ARG). */
 int ug_render_planes_backward(const ug_plan *plan, const ug_gaussians *g,
                               const ug_planes *planes, const float *image,
                               const float *d_image, void *workspace, float *d_means,

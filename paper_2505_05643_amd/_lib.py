@@ -25,9 +25,10 @@ UG_BOX_ROWS = 2
 
 UG_MSE_SCRATCH_FLOATS = 1026
 UG_FLAG_COUNT_EVALS = 1
+UG_FLAG_SCATTER = 2
 
 STAGES = ("setup", "cull_count", "cull_write", "record", "emit", "sort_hist", "sort_scan", "sort_scatter", "ranges",
-          "accum", "bwd_prep", "accum_bwd", "record_adj", "gauss_grad")
+          "accum", "bwd_prep", "accum_bwd", "record_adj", "gauss_grad", "scatter")
 UG_NUM_STAGES = len(STAGES)
 
 c_i32, c_i64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p

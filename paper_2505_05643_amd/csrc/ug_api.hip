@@ -105,7 +105,7 @@ bool valid_params(const ug_params& p) {
   if (!(p.bg_alpha > 0.f) || !std::isfinite(p.bg_alpha)) return false;
   if (!std::isfinite(p.bg_color)) return false;
   if (p.box_mode != UG_BOX_PAPER && p.box_mode != UG_BOX_CONIC && p.box_mode != UG_BOX_ROWS) return false;
-  if ((p.flags & ~UG_FLAG_COUNT_EVALS) != 0) return false;
+  if ((p.flags & ~(UG_FLAG_COUNT_EVALS | UG_FLAG_SCATTER)) != 0) return false;
   const int ppl = p.px_per_lane ? p.px_per_lane : accum_default_ppl(p.tile_w, p.tile_h);
   return accum_config_supported(p.tile_w, p.tile_h, ppl, p.lds_batch);
 }
@@ -171,7 +171,7 @@ int check_inputs(const ug_plan* plan, const ug_gaussians* g, const ug_planes* pl
 
 // Culling and record passes shared by measure and render.
 hipError_t enqueue_preprocess(const ug_plan* plan, const ug_gaussians& g, const ug_planes& pl, void* ws,
-                              const RenderParams& rp, hipStream_t s) {
+                              const RenderParams& rp, hipStream_t s, bool emit = true) {
   const Layout& L = plan->lay;
   Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
   hipError_t e;
@@ -199,7 +199,7 @@ hipError_t enqueue_preprocess(const ug_plan* plan, const ug_gaussians& g, const 
                       at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<uint32_t>(ws, L.rec_nkey),
                       at<uint32_t>(ws, L.blk_r), ctrl, s);
   }
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !emit) return e;
   StageScope sc(plan, UG_STAGE_EMIT, s);
   return launch_emit(plan->d_pint, rp, at<uint2>(ws, L.rec_pair), at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo),
                      at<uint32_t>(ws, L.rec_nkey), at<uint32_t>(ws, L.blk_r), at<uint32_t>(ws, L.rec_koff), ctrl,
@@ -390,6 +390,26 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
   void* ws = workspace;
   const RenderParams rp = make_rp(plan);
   Ctrl* ctrl = at<Ctrl>(ws, L.ctrl);
+  if (plan->prm.flags & UG_FLAG_SCATTER) {
+    // Phase 2: records only, then the atomic scatter into image (numerator)
+    // and the saved denominators
+    hipError_t e = enqueue_preprocess(plan, *g, *planes, ws, rp, s, false);
+    if (e != hipSuccess) return UG_ERR_HIP;
+    float* den = at<float>(ws, L.dsave);
+    {
+      StageScope sc(plan, UG_STAGE_SCATTER, s);
+      e = launch_scatter_zero(image, den, plan->num_pixels, s);
+    }
+    if (e != hipSuccess) return UG_ERR_HIP;
+    {
+      StageScope sc(plan, UG_STAGE_SCATTER, s);
+      e = launch_scatter(ctrl, at<uint2>(ws, L.rec_pair), plan->d_pint, at<RecAcc>(ws, L.racc),
+                         at<RecGeo>(ws, L.rgeo), plan->prm.tile_w, plan->prm.tile_h, plan->rec_cap, image, den, s);
+    }
+    if (e != hipSuccess) return UG_ERR_HIP;
+    StageScope sc(plan, UG_STAGE_SCATTER, s);
+    return hip_status(launch_scatter_norm(image, den, plan->num_pixels, plan->prm.bg_alpha, plan->prm.bg_color, s));
+  }
   hipError_t e = enqueue_preprocess(plan, *g, *planes, ws, rp, s);
   if (e != hipSuccess) return UG_ERR_HIP;
   e = enqueue_sort(plan, ws, s);
@@ -418,6 +438,7 @@ int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const 
   if (!image || !d_image) return UG_ERR_INVALID_ARG;
   if (plan->n > 0 && (!d_means || !d_lraw || !d_intensity || !d_opacity)) return UG_ERR_INVALID_ARG;
   if (accumulate != 0 && accumulate != 1) return UG_ERR_INVALID_ARG;
+  if (plan->prm.flags & UG_FLAG_SCATTER) return UG_ERR_INVALID_ARG;  // no keys to walk
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Layout& L = plan->lay;
   void* ws = workspace;

@@ -69,6 +69,15 @@ hipError_t launch_tile_ranges(const Ctrl* ctrl, const uint32_t* skeys, uint32_t 
                               int mask_shift, uint32_t* tile_start, hipStream_t s);
 uint32_t sort_blocks_for(uint32_t key_cap);
 
+// ---- Phase-2 atomic scatter forward (ug_scatter.hip): zero the sums, one
+// wave per record adds w c and w over its box, normalise in place.
+hipError_t launch_scatter_zero(float* num, float* den, uint64_t m, hipStream_t s);
+hipError_t launch_scatter(const Ctrl* ctrl, const uint2* rec_pair, const PlaneInt* pint, const RecAcc* racc,
+                          const RecGeo* rgeo, int tile_w, int tile_h, uint32_t rec_cap, float* num, float* den,
+                          hipStream_t s);
+hipError_t launch_scatter_norm(float* image, float* dsave, uint64_t m, float bg_alpha, float bg_color,
+                               hipStream_t s);
+
 // ---- accumulate (ug_raster.hip)
 int accum_default_ppl(int tile_w, int tile_h);
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);

@@ -97,6 +97,35 @@ def test_in_plane_rotation_gives_rot90(R):
         print("rot90 box", bm, "max diff / peak", float(diff.max() / st["peak"]), "off", off)
 
 
+def test_paper_phase2_atomic_scatter(R):
+    """UG_FLAG_SCATTER, the paper's Phase 2: each record adds to per-pixel
+    sums with atomic adds over its box.  Same per-pair test as the gather,
+    so the oracle's image within the parity tolerance and the gather's to
+    float rounding (pairs on the cut-off aside); such plans refuse the
+    backward."""
+    from paper_2505_05643_amd._lib import UG_FLAG_SCATTER, UgError
+    cases = [synth.make_config(0)[:2]]
+    g1 = synth.make_gaussians(300, 41, (0, 0, 0), (1, 1, 1), (0.02, 0.12), opacity="random")
+    p1 = synth.random_planes(3, 42, (8, 8), 1 / 40, 0.3, 0.7)
+    p1.wh[:] = [[37, 23], [8, 8], [50, 41]]
+    cases.append((g1, p1))
+    for g, pl in cases:
+        for bm in (0, 1, 2):
+            img_s, plan_s = _render(R, g, pl, R.Params(box_mode=bm, flags=UG_FLAG_SCATTER))
+            st = check_image(img_s, g, pl, plan_s.params)
+            img_g, _ = _render(R, g, pl, R.Params(box_mode=bm))
+            diff = np.abs(img_s.astype(np.float64) - img_g.astype(np.float64))
+            off = int(np.sum(diff > 2e-5 * st["peak"]))
+            assert off <= max(1, 1e-3 * img_s.size), f"box {bm}: {off} pixels differ from the gather"
+    g, pl = cases[1]
+    img, plan = _render(R, g, pl, R.Params(chi2=math.inf, flags=UG_FLAG_SCATTER))
+    check_image(img, g, pl, plan.params)
+    dev = torch.device("cuda", 0)
+    gd, pd = R.to_device(g, dev), R.to_device(pl, dev)
+    with pytest.raises(UgError):
+        plan.backward(gd, pd, torch.from_numpy(img).to(dev), torch.zeros(plan.num_pixels, device=dev))
+
+
 def test_tile_shapes_box_modes_batches(R):
     """Within one tile shape, every LDS batch and binning box gives the same
     image bit for bit (each pixel sums its in-support Gaussians in record
@@ -136,3 +165,17 @@ def test_configs_sampled_pixels(R, k, count):
     flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
     st = check_image(img[flat], g, pl, plan.params, pix=pix)
     print(f"c{k}", st, "records/keys", plan.status(counts=True))
+
+
+@pytest.mark.parametrize("k,count", [(1, 1500), (4, 300)])
+def test_configs_sampled_pixels_phase2_scatter(R, k, count):
+    """The Phase-2 atomic scatter on full-size workloads: a seeded sample of
+    pixels against the oracle."""
+    from paper_2505_05643_amd._lib import UG_FLAG_SCATTER
+    g, pl, _ = synth.make_config(k)
+    img, plan = _render(R, g, pl, R.Params(flags=UG_FLAG_SCATTER))
+    pix = synth.sample_pixels(pl, count, 700 + k)
+    offs = pl.pixel_offsets()
+    flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
+    st = check_image(img[flat], g, pl, plan.params, pix=pix)
+    print(f"scatter c{k}", st)
