@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-plane comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scatter", action="store_true", help="skip timing the Phase-2 atomic scatter forward")
+    ap.add_argument("--no-densify", action="store_true", help="skip timing the densify / prune pass")
     ap.add_argument("--cpu-px", type=int, default=640)
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch configuration")
@@ -364,6 +365,7 @@ def main():
         "forward_only_ms": fwd_ms,
         "train_step_ms": train_ms,
         "paper_phase2_scatter": scatter,
+        "densify": densify_ms(R, gd, dev, args.warmup, args.steps) if not args.no_densify else None,
         "evals_per_s": evals_s,
         "in_support_pairs": n_eval,
         "records": n_rec,
@@ -398,6 +400,53 @@ def main():
         for _ in range(5):
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
+
+
+def densify_ms(R, gd, dev, warmup, steps):
+    """The densify / prune pass over the workload's Gaussians with seeded
+    gradient statistics (about a tenth cloned or split, a few pruned):
+    average ms per call and its rate against HBM.  Algorithmic bytes: the
+    decision pass reads lraw, opacity and the statistics (36 B per
+    Gaussian), the write pass reads them again with means and intensity
+    (52 B) and writes 44 B per output (the 24 B of z a split reads are not
+    counted, so the rate is a lower bound)."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2505_05643_amd import _lib
+    n = gd.means.shape[0]
+    rng = np.random.default_rng(77)
+    cnt = torch.from_numpy(rng.integers(1, 20, n).astype(np.int32)).to(dev)
+    acc = torch.from_numpy((rng.uniform(0.0, 2.2e-4, n) * cnt.cpu().numpy()).astype(np.float32)).to(dev)
+    z = torch.from_numpy(rng.standard_normal((n, 2, 3)).astype(np.float32)).to(dev)
+    cap = 2 * n
+    out = [torch.empty((cap,) + sh, device=dev) for sh in ((3,), (6,), (), ())]
+    ws = torch.empty((_lib.lib.ug_densify_workspace_bytes(n) + 3) // 4 + 1, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    cg = R._c_gauss(gd)
+    co = _lib.UgGaussiansMut(*(t.data_ptr() for t in out), cap)
+    dp = _lib.UgDensifyParams()
+    _lib.lib.ug_densify_params_default(ctypes.byref(dp))
+
+    def call():
+        R.check(_lib.lib.ug_densify(ctypes.byref(cg), acc.data_ptr(), cnt.data_ptr(), z.data_ptr(), ctypes.byref(dp),
+                                    ctypes.byref(co), cap, count.data_ptr(), ws.data_ptr(), R._stream()), "ug_densify")
+
+    for _ in range(max(1, warmup)):
+        call()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, steps)
+    t0.record()
+    for _ in range(reps):
+        call()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    m = int(count.item())
+    nbytes = 36 * n + 52 * n + 44 * m
+    return {"ms": ms, "gaussians_in": n, "gaussians_out": m, "algorithmic_bytes": nbytes,
+            "achieved_gbs": nbytes / (ms / 1e3) / 1e9, "frac_hbm": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
 def replay_ms(fn, warmup, steps):

@@ -248,6 +248,61 @@ int ug_adam_gaussians(const ug_plan *plan, const void *workspace, const ug_gauss
                       const ug_gaussians_mut *m2, const ug_adam_params *hp, int32_t *step_dev,
                       void *stream);
 
+/* ---- Densification and pruning between training steps.  Section 4.2
+ * draws new means from a Gaussian through its triangular factor,
+ * y = mu + L^-T z (back substitution with L^T, no general inverse); the
+ * clone / split / prune rule is only referenced by the paper (to 3D
+ * Gaussian splatting), so the one below is a stated choice.  Random numbers
+ * are inputs (z), so results are reproducible. */
+
+/* out[j] = means[idx[j]] + L^-T z[j], j < k, with L from lraw[idx[j]] by
+ * Eq. 11 (shift beta).  idx [k] int32, z [k][3] (standard normals for a
+ * draw from the Gaussian), out [k][3]: device, float32.  An idx entry
+ * outside [0, g->n) yields NaN for that sample.  No synchronisation. */
+int ug_sample_gaussians(const ug_gaussians *g, float beta, const int32_t *idx, const float *z, int64_t k,
+                        float *out, void *stream);
+
+/* acc[i] += |d_means[i]| (Euclidean norm) and cnt[i] += 1 for i < n: the
+ * per-Gaussian statistic ug_densify reads (device arrays; start at zero). */
+int ug_accumulate_grad_norm(const float *d_means, int32_t n, float *acc, int32_t *cnt, void *stream);
+
+typedef struct {
+  float beta;         /* Eq. 11 shift, as in the render (default 1e-4)                  */
+  float min_opacity;  /* prune when sigmoid(a) < this (default 0.005)                   */
+  float grad_thresh;  /* clone or split when acc >= grad_thresh * cnt, cnt > 0
+                         (default 2e-4, in loss units per world unit)                  */
+  float split_size;   /* split (else clone) when size > this, world units (default 1)  */
+  float max_size;     /* prune when size > this; 0 = no limit (default 0)              */
+  float split_factor; /* a split child has every std divided by this, > 1 (default 1.6) */
+} ug_densify_params;
+
+/* Fills *out with the defaults listed above. */
+void ug_densify_params_default(ug_densify_params *out);
+
+/* Bytes of device workspace ug_densify needs for n Gaussians. */
+size_t ug_densify_workspace_bytes(int32_t n);
+
+/* The rule, per Gaussian i, decided in float32 with the operations in a fixed
+ * order (size^2 = trace of the covariance = sum of squares of the entries of
+ * L^-1, written out; the opacity floor compared in logit space):
+ *   prune if sigmoid(a) < min_opacity, or max_size > 0 and size > max_size;
+ *   else if cnt[i] > 0 and acc[i] >= grad_thresh * cnt[i]:
+ *     split if size > split_size: two children, means mu + L^-T z[i][c]
+ *       (c = 0, 1) and factor split_factor * L (every std divided by
+ *       split_factor), intensity and opacity copied;
+ *     else clone: two copies;
+ *   else keep one copy.
+ * out (device, capacity out_capacity Gaussians; its n is ignored) receives
+ * the outputs in Gaussian order (i ascending, a Gaussian's outputs
+ * together): deterministic.  z [n][2][3] standard normals, read for split
+ * Gaussians only.  The number of outputs goes to *count_dev (device int64);
+ * when it exceeds out_capacity nothing past the capacity is written.
+ * workspace: ug_densify_workspace_bytes(n) bytes of device memory, 256-byte
+ * aligned, caller-owned.  Arrays must not overlap g's.  No synchronisation. */
+int ug_densify(const ug_gaussians *g, const float *acc, const int32_t *cnt, const float *z,
+               const ug_densify_params *dp, const ug_gaussians_mut *out, int64_t out_capacity,
+               int64_t *count_dev, void *workspace, void *stream);
+
 /* Human-readable text for a status code (static storage). */
 const char *ug_status_string(int status);
 

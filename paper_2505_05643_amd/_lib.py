@@ -57,6 +57,11 @@ class UgAdamParams(ctypes.Structure):
                 ("beta1", c_f32), ("beta2", c_f32), ("eps", c_f32)]
 
 
+class UgDensifyParams(ctypes.Structure):
+    _fields_ = [("beta", c_f32), ("min_opacity", c_f32), ("grad_thresh", c_f32), ("split_size", c_f32),
+                ("max_size", c_f32), ("split_factor", c_f32)]
+
+
 # name -> (restype, argtypes); mirrors include/ug.h
 SIGNATURES = {
     "ug_params_default": (None, [ctypes.POINTER(UgParams)]),
@@ -79,6 +84,12 @@ SIGNATURES = {
     "ug_adam_gaussians": (c_i32, [c_vp, c_vp, ctypes.POINTER(UgGaussiansMut), ctypes.POINTER(UgGaussiansMut),
                                   ctypes.POINTER(UgGaussiansMut), ctypes.POINTER(UgGaussiansMut),
                                   ctypes.POINTER(UgAdamParams), c_vp, c_vp]),
+    "ug_sample_gaussians": (c_i32, [ctypes.POINTER(UgGaussians), c_f32, c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "ug_accumulate_grad_norm": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "ug_densify_params_default": (None, [ctypes.POINTER(UgDensifyParams)]),
+    "ug_densify_workspace_bytes": (ctypes.c_size_t, [c_i32]),
+    "ug_densify": (c_i32, [ctypes.POINTER(UgGaussians), c_vp, c_vp, c_vp, ctypes.POINTER(UgDensifyParams),
+                           ctypes.POINTER(UgGaussiansMut), c_i64, c_vp, c_vp, c_vp]),
     "ug_status_string": (ctypes.c_char_p, [c_i32]),
     "ug_plan_destroy": (None, [c_vp]),
 }

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libug.so")
 
-SOURCES = ["ug_api.hip", "ug_preprocess.hip", "ug_sort.hip", "ug_raster.hip", "ug_scatter.hip", "ug_train.hip"]
+SOURCES = ["ug_api.hip", "ug_preprocess.hip", "ug_sort.hip", "ug_raster.hip", "ug_scatter.hip", "ug_densify.hip",
+           "ug_train.hip"]
 
 ARCH = "gfx950"
 HIPCC_FLAGS = [

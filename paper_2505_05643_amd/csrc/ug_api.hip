@@ -532,6 +532,52 @@ int ug_adam_gaussians(const ug_plan* plan, const void* workspace, const ug_gauss
   return hip_status(launch_adam_gaussians(p, g, m, v, n, *hp, step_dev, ctrl, static_cast<hipStream_t>(stream)));
 }
 
+int ug_sample_gaussians(const ug_gaussians* g, float beta, const int32_t* idx, const float* z, int64_t k,
+                        float* out, void* stream) {
+  if (!g || k < 0 || g->n < 0 || !(beta > 0.f) || !std::isfinite(beta)) return UG_ERR_INVALID_ARG;
+  if (k == 0) return UG_OK;
+  if (!idx || !z || !out || !g->means || !g->lraw) return UG_ERR_INVALID_ARG;
+  return hip_status(launch_sample(*g, beta, idx, z, k, out, static_cast<hipStream_t>(stream)));
+}
+
+int ug_accumulate_grad_norm(const float* d_means, int32_t n, float* acc, int32_t* cnt, void* stream) {
+  if (n < 0) return UG_ERR_INVALID_ARG;
+  if (n == 0) return UG_OK;
+  if (!d_means || !acc || !cnt) return UG_ERR_INVALID_ARG;
+  return hip_status(launch_grad_norm(d_means, n, acc, cnt, static_cast<hipStream_t>(stream)));
+}
+
+void ug_densify_params_default(ug_densify_params* out) {
+  if (!out) return;
+  out->beta = 1e-4f;
+  out->min_opacity = 0.005f;
+  out->grad_thresh = 2e-4f;
+  out->split_size = 1.0f;
+  out->max_size = 0.0f;
+  out->split_factor = 1.6f;
+}
+
+size_t ug_densify_workspace_bytes(int32_t n) {
+  return n < 0 ? 0 : align_up((size_t)densify_blocks(n) * 4 + 4);
+}
+
+int ug_densify(const ug_gaussians* g, const float* acc, const int32_t* cnt, const float* z,
+               const ug_densify_params* dp, const ug_gaussians_mut* out, int64_t out_capacity, int64_t* count_dev,
+               void* workspace, void* stream) {
+  if (!g || !dp || !out || !count_dev || !workspace || g->n < 0 || out_capacity < 0) return UG_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return UG_ERR_INVALID_ARG;
+  if (!(dp->beta > 0.f) || !std::isfinite(dp->beta) || !(dp->min_opacity >= 0.f && dp->min_opacity <= 1.f) ||
+      !std::isfinite(dp->grad_thresh) || !(dp->split_size >= 0.f) || !std::isfinite(dp->split_size) ||
+      !(dp->max_size >= 0.f) || !std::isfinite(dp->max_size) || !(dp->split_factor > 1.f) ||
+      !std::isfinite(dp->split_factor))
+    return UG_ERR_INVALID_ARG;
+  if (g->n > 0 && (!g->means || !g->lraw || !g->intensity || !g->opacity || !acc || !cnt || !z))
+    return UG_ERR_INVALID_ARG;
+  if (out_capacity > 0 && (!out->means || !out->lraw || !out->intensity || !out->opacity)) return UG_ERR_INVALID_ARG;
+  return hip_status(launch_densify(*g, acc, cnt, z, *dp, *out, out_capacity, count_dev,
+                                   static_cast<uint32_t*>(workspace), static_cast<hipStream_t>(stream)));
+}
+
 const char* ug_status_string(int status) {
   switch (status) {
     case UG_OK: return "ok";

@@ -78,6 +78,15 @@ hipError_t launch_scatter(const Ctrl* ctrl, const uint2* rec_pair, const PlaneIn
 hipError_t launch_scatter_norm(float* image, float* dsave, uint64_t m, float bg_alpha, float bg_color,
                                hipStream_t s);
 
+// ---- densification (ug_densify.hip)
+uint32_t densify_blocks(int32_t n);
+hipError_t launch_densify(const ug_gaussians& g, const float* acc, const int32_t* cnt, const float* z,
+                          const ug_densify_params& dp, const ug_gaussians_mut& out, int64_t cap, int64_t* count,
+                          uint32_t* blk, hipStream_t s);
+hipError_t launch_sample(const ug_gaussians& g, float beta, const int32_t* idx, const float* z, int64_t k, float* out,
+                         hipStream_t s);
+hipError_t launch_grad_norm(const float* d_means, int32_t n, float* acc, int32_t* cnt, hipStream_t s);
+
 // ---- accumulate (ug_raster.hip)
 int accum_default_ppl(int tile_w, int tile_h);
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);

@@ -1,0 +1,116 @@
+"""Densify / prune and the Section 4.2 draw on the GPU against the
+reference (oracle/densify.py): the same decisions (exactly: both sides take
+them in float32 in the same order), copies bit for bit, split children and
+draws to float rounding."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import densify as D
+from paper_2505_05643_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BETA = 1e-4
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_05643_amd import densify, raster
+    return raster, densify
+
+
+def _population(n, seed):
+    """Mixed population: opacities around the floor, gradient statistics
+    around the threshold, sizes on both sides of the split size."""
+    rng = np.random.default_rng(seed)
+    g = synth.make_gaussians(n, seed, (0, 0, 0), (4, 4, 4), (0.05, 1.5), aniso_max=8.0, opacity="random")
+    g.opacity[:] = rng.uniform(-7.0, 3.0, n).astype(np.float32)
+    cnt = rng.integers(0, 20, n).astype(np.int32)
+    acc = (rng.uniform(0.0, 4e-4, n) * cnt).astype(np.float32)
+    z = rng.standard_normal((n, 2, 3)).astype(np.float32)
+    return g, acc, cnt, z
+
+
+def test_sample_matches_reference(M):
+    R, Dn = M
+    dev = torch.device("cuda", 0)
+    g = synth.make_gaussians(300, 11, (0, 0, 0), (1, 1, 1), (0.01, 0.3), aniso_max=30.0)
+    rng = np.random.default_rng(1)
+    idx = rng.integers(0, 300, 2000).astype(np.int32)
+    idx[:3] = [-1, 300, 299]
+    z = rng.standard_normal((2000, 3)).astype(np.float32)
+    out = Dn.sample_gaussians(R.to_device(g, dev), torch.from_numpy(idx).to(dev), torch.from_numpy(z).to(dev),
+                              BETA).cpu().numpy()
+    assert np.all(np.isnan(out[:2]))
+    ref = oracle.sample_gaussian(g.means[idx[2:]], g.lraw[idx[2:]], z[2:], BETA)
+    scale = np.abs(ref - g.means[idx[2:]]).max()
+    assert np.abs(out[2:] - ref).max() <= 1e-5 * max(scale, 1.0)
+
+
+def test_accumulate_grad_norm(M):
+    R, Dn = M
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(2)
+    dm = rng.standard_normal((1000, 3)).astype(np.float32)
+    acc = torch.full((1000,), 0.5, device=dev)
+    cnt = torch.full((1000,), 3, dtype=torch.int32, device=dev)
+    for _ in range(2):
+        Dn.accumulate_grad_norm(torch.from_numpy(dm).to(dev), acc, cnt)
+    ref = 0.5 + 2 * np.linalg.norm(dm.astype(np.float64), axis=1)
+    np.testing.assert_allclose(acc.cpu().numpy(), ref, rtol=1e-6)
+    assert np.all(cnt.cpu().numpy() == 5)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 5), (257, 6), (20_000, 7)])
+def test_densify_matches_reference(M, n, seed):
+    R, Dn = M
+    dev = torch.device("cuda", 0)
+    g, acc, cnt, z = _population(n, seed)
+    prm = Dn.DensifyParams(beta=BETA, min_opacity=0.005, grad_thresh=2e-4, split_size=1.0, max_size=3.0,
+                           split_factor=1.6)
+    out = Dn.densify(R.to_device(g, dev), torch.from_numpy(acc).to(dev), torch.from_numpy(cnt).to(dev),
+                     torch.from_numpy(z).to(dev), prm)
+    means, lraw, inten, opac, src, d = D.densify(g, acc, cnt, z, BETA, 0.005, 2e-4, 1.0, 3.0, 1.6)
+    if n > 100:
+        assert all(np.any(d == k) for k in (D.PRUNE, D.KEEP, D.CLONE, D.SPLIT)), np.bincount(d)
+    gm, gl = out.means.cpu().numpy(), out.lraw.cpu().numpy()
+    assert gm.shape[0] == src.shape[0]
+    np.testing.assert_array_equal(out.intensity.cpu().numpy(), g.intensity[src])
+    np.testing.assert_array_equal(out.opacity.cpu().numpy(), g.opacity[src])
+    split = d[src] == D.SPLIT
+    np.testing.assert_array_equal(gm[~split], g.means[src[~split]])  # copies are exact
+    np.testing.assert_array_equal(gl[~split], g.lraw[src[~split]])
+    if split.any():
+        assert np.abs(gm[split] - means[split]).max() <= 1e-5 * max(1.0, np.abs(means[split]).max())
+        np.testing.assert_allclose(gl[split], lraw[split], rtol=2e-6, atol=1e-6 * np.abs(lraw[split]).max())
+
+
+def test_densify_capacity_overflow_reports_the_total(M):
+    R, Dn = M
+    from paper_2505_05643_amd import _lib
+    dev = torch.device("cuda", 0)
+    g, acc, cnt, z = _population(3000, 9)
+    _, _, _, _, src, _ = D.densify(g, acc, cnt, z, BETA, 0.005, 2e-4, 1.0, 0.0, 1.6)
+    total = src.shape[0]
+    cap = total - 7
+    gd = R.to_device(g, dev)
+    out = [torch.full((cap + 16,) + s, -1.0, device=dev) for s in ((3,), (6,), (), ())]
+    ws = torch.empty((_lib.lib.ug_densify_workspace_bytes(3000) + 3) // 4, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    cg = R._c_gauss(gd)
+    co = _lib.UgGaussiansMut(*(t.data_ptr() for t in out), cap)
+    dp = _lib.UgDensifyParams()
+    _lib.lib.ug_densify_params_default(ctypes.byref(dp))
+    da, dc, dz = (torch.from_numpy(x).to(dev) for x in (acc, cnt, z))
+    code = _lib.lib.ug_densify(ctypes.byref(cg), da.data_ptr(), dc.data_ptr(), dz.data_ptr(), ctypes.byref(dp),
+                               ctypes.byref(co), cap, count.data_ptr(), ws.data_ptr(), R._stream())
+    assert code == 0
+    assert int(count.item()) == total
+    assert torch.all(out[2][cap:] == -1.0)  # nothing past the capacity
+    np.testing.assert_array_equal(out[2][:cap].cpu().numpy(), g.intensity[src[:cap]])
