@@ -263,8 +263,12 @@ int ug_sample_gaussians(const ug_gaussians *g, float beta, const int32_t *idx, c
                         float *out, void *stream);
 
 /* acc[i] += |d_means[i]| (Euclidean norm) and cnt[i] += 1 for i < n: the
- * per-Gaussian statistic ug_densify reads (device arrays; start at zero). */
-int ug_accumulate_grad_norm(const float *d_means, int32_t n, float *acc, int32_t *cnt, void *stream);
+ * per-Gaussian statistic ug_densify reads (device arrays; start at zero).
+ * If plan and workspace are given and the render that filled the workspace
+ * overflowed its capacity, the update is skipped on the device (as in
+ * ug_adam_gaussians: the gradients were not computed). */
+int ug_accumulate_grad_norm(const ug_plan *plan, const void *workspace, const float *d_means, int32_t n,
+                            float *acc, int32_t *cnt, void *stream);
 
 typedef struct {
   float beta;         /* Eq. 11 shift, as in the render (default 1e-4)                  */

@@ -85,7 +85,7 @@ SIGNATURES = {
                                   ctypes.POINTER(UgGaussiansMut), ctypes.POINTER(UgGaussiansMut),
                                   ctypes.POINTER(UgAdamParams), c_vp, c_vp]),
     "ug_sample_gaussians": (c_i32, [ctypes.POINTER(UgGaussians), c_f32, c_vp, c_vp, c_i64, c_vp, c_vp]),
-    "ug_accumulate_grad_norm": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "ug_accumulate_grad_norm": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp]),
     "ug_densify_params_default": (None, [ctypes.POINTER(UgDensifyParams)]),
     "ug_densify_workspace_bytes": (ctypes.c_size_t, [c_i32]),
     "ug_densify": (c_i32, [ctypes.POINTER(UgGaussians), c_vp, c_vp, c_vp, ctypes.POINTER(UgDensifyParams),

@@ -540,11 +540,15 @@ int ug_sample_gaussians(const ug_gaussians* g, float beta, const int32_t* idx, c
   return hip_status(launch_sample(*g, beta, idx, z, k, out, static_cast<hipStream_t>(stream)));
 }
 
-int ug_accumulate_grad_norm(const float* d_means, int32_t n, float* acc, int32_t* cnt, void* stream) {
-  if (n < 0) return UG_ERR_INVALID_ARG;
+int ug_accumulate_grad_norm(const ug_plan* plan, const void* workspace, const float* d_means, int32_t n, float* acc,
+                            int32_t* cnt, void* stream) {
+  if (n < 0 || (plan == nullptr) != (workspace == nullptr)) return UG_ERR_INVALID_ARG;
+  if (plan && plan->n != n) return UG_ERR_INVALID_ARG;
   if (n == 0) return UG_OK;
   if (!d_means || !acc || !cnt) return UG_ERR_INVALID_ARG;
-  return hip_status(launch_grad_norm(d_means, n, acc, cnt, static_cast<hipStream_t>(stream)));
+  const Ctrl* ctrl = plan ? reinterpret_cast<const Ctrl*>(static_cast<const char*>(workspace) + plan->lay.ctrl)
+                          : nullptr;
+  return hip_status(launch_grad_norm(ctrl, d_means, n, acc, cnt, static_cast<hipStream_t>(stream)));
 }
 
 void ug_densify_params_default(ug_densify_params* out) {

@@ -168,8 +168,10 @@ __global__ __launch_bounds__(256) void k_sample(ug_gaussians g, float beta, cons
   }
 }
 
-__global__ __launch_bounds__(256) void k_grad_norm(const float* __restrict__ d_means, int32_t n,
-                                                   float* __restrict__ acc, int32_t* __restrict__ cnt) {
+// Skipped when the render that produced the gradients overflowed (ctrl).
+__global__ __launch_bounds__(256) void k_grad_norm(const Ctrl* __restrict__ ctrl, const float* __restrict__ d_means,
+                                                   int32_t n, float* __restrict__ acc, int32_t* __restrict__ cnt) {
+  if (ctrl && (ctrl->flags & (kFlagRecCap | kFlagKeyCap))) return;
   for (int i = (int)(blockIdx.x * 256 + threadIdx.x); i < n; i += (int)(gridDim.x * 256)) {
     const float x = d_means[3 * i], y = d_means[3 * i + 1], w = d_means[3 * i + 2];
     acc[i] += sqrtf(x * x + y * y + w * w);
@@ -208,10 +210,11 @@ hipError_t launch_sample(const ug_gaussians& g, float beta, const int32_t* idx, 
   return hipGetLastError();
 }
 
-hipError_t launch_grad_norm(const float* d_means, int32_t n, float* acc, int32_t* cnt, hipStream_t s) {
+hipError_t launch_grad_norm(const Ctrl* ctrl, const float* d_means, int32_t n, float* acc, int32_t* cnt,
+                            hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int want = (n + 255) / 256;
-  hipLaunchKernelGGL(k_grad_norm, dim3(want > 8192 ? 8192 : want), dim3(256), 0, s, d_means, n, acc, cnt);
+  hipLaunchKernelGGL(k_grad_norm, dim3(want > 8192 ? 8192 : want), dim3(256), 0, s, ctrl, d_means, n, acc, cnt);
   return hipGetLastError();
 }
 

@@ -85,7 +85,8 @@ hipError_t launch_densify(const ug_gaussians& g, const float* acc, const int32_t
                           uint32_t* blk, hipStream_t s);
 hipError_t launch_sample(const ug_gaussians& g, float beta, const int32_t* idx, const float* z, int64_t k, float* out,
                          hipStream_t s);
-hipError_t launch_grad_norm(const float* d_means, int32_t n, float* acc, int32_t* cnt, hipStream_t s);
+hipError_t launch_grad_norm(const Ctrl* ctrl, const float* d_means, int32_t n, float* acc, int32_t* cnt,
+                            hipStream_t s);
 
 // ---- accumulate (ug_raster.hip)
 int accum_default_ppl(int tile_w, int tile_h);

@@ -43,12 +43,16 @@ def sample_gaussians(g: R.GaussianTensors, idx: torch.Tensor, z: torch.Tensor, b
     return out
 
 
-def accumulate_grad_norm(d_means: torch.Tensor, acc: torch.Tensor, cnt: torch.Tensor) -> None:
-    """acc += |d_means| per Gaussian, cnt += 1 (float32 / int32 device tensors)."""
+def accumulate_grad_norm(d_means: torch.Tensor, acc: torch.Tensor, cnt: torch.Tensor,
+                         plan: R.Plan | None = None) -> None:
+    """acc += |d_means| per Gaussian, cnt += 1 (float32 / int32 device
+    tensors); skipped on the device if ``plan``'s last render overflowed."""
     n = d_means.shape[0]
     if acc.shape != (n,) or cnt.shape != (n,) or acc.dtype != torch.float32 or cnt.dtype != torch.int32:
         raise ValueError("acc float32 [n], cnt int32 [n]")
-    check(lib.ug_accumulate_grad_norm(d_means.contiguous().data_ptr(), n, acc.data_ptr(), cnt.data_ptr(),
+    check(lib.ug_accumulate_grad_norm(plan._h if plan is not None else None,
+                                      plan._ws_ptr if plan is not None else None,
+                                      d_means.contiguous().data_ptr(), n, acc.data_ptr(), cnt.data_ptr(),
                                       R._stream()), "ug_accumulate_grad_norm")
 
 

@@ -6,6 +6,10 @@ replayed.  The Adam step counter lives in device memory and the Adam kernel
 skips itself when the render overflowed its capacity; ``run`` checks the
 status every ``check_every`` steps and, on an overflow, re-sizes the plan,
 captures again and redoes the step.
+
+Each step also adds |dL/dmu| to a per-Gaussian statistic; ``densify``
+(between steps) clones, splits and prunes by it (include/ug.h, ug_densify),
+then re-plans for the new number of Gaussians and captures again.
 """
 from __future__ import annotations
 
@@ -16,6 +20,7 @@ import torch
 
 from . import _lib
 from ._lib import lib, check
+from . import densify as D
 from . import raster as R
 
 
@@ -76,7 +81,14 @@ class TrainStep:
         self.image = torch.empty(self.plan.num_pixels, device=dev)
         self.d_image = torch.empty_like(self.image)
         self.loss_buf = torch.zeros(_lib.UG_MSE_SCRATCH_FLOATS, device=dev)
+        self._reset_stats()
         self.graph = None
+
+    def _reset_stats(self):
+        n = self.params.means.shape[0]
+        dev = self.params.means.device
+        self.grad_acc = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.grad_cnt = torch.zeros(n, dtype=torch.int32, device=dev)
 
     # ---------------------------------------------------------------- eager
     def enqueue(self):
@@ -84,6 +96,7 @@ class TrainStep:
         self.plan.render(self.params, self.planes, self.image, check_status=False)
         R.mse_grad(self.image, self.target, self.d_image, self.loss_buf)
         self.plan.backward(self.params, self.planes, self.image, self.d_image, self.grads)
+        D.accumulate_grad_norm(self.grads.means, self.grad_acc, self.grad_cnt, self.plan)
         adam_gaussians(self.params, self.grads, self.m1, self.m2, self.adam, self.step_dev, self.plan)
 
     # ---------------------------------------------------------------- graph
@@ -129,3 +142,27 @@ class TrainStep:
     @property
     def step_count(self) -> int:
         return int(self.step_dev.item())
+
+    # ---------------------------------------------------------------- densify
+    def densify(self, params: "D.DensifyParams | None" = None, seed: int = 0) -> int:
+        """Clone / split / prune by the accumulated statistic; returns the new
+        number of Gaussians.  ``self.params`` then holds new tensors (the old
+        ones are not updated any more); the Adam moments of the new set start
+        at zero and the statistic restarts.  Synchronises."""
+        torch.cuda.synchronize()
+        n = self.params.means.shape[0]
+        dev = self.params.means.device
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed)
+        z = torch.randn(n, 2, 3, generator=gen, device=dev)
+        new = D.densify(self.params, self.grad_acc, self.grad_cnt, z, params)
+        self.params = R.GaussianTensors(*(t.contiguous() for t in new))
+        z0 = lambda t: torch.zeros_like(t)  # noqa: E731
+        self.grads = R.GaussianTensors(*(z0(t) for t in self.params))
+        self.m1 = R.GaussianTensors(*(z0(t) for t in self.params))
+        self.m2 = R.GaussianTensors(*(z0(t) for t in self.params))
+        self.plan = R.Plan(self.params.means.shape[0], self.plan.wh, self.plan.params, device=dev)
+        self.plan.fit(self.params, self.planes, self.headroom)
+        self._reset_stats()
+        self.graph = None
+        return self.params.means.shape[0]

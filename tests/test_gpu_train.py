@@ -141,3 +141,34 @@ def test_overflow_skips_update_and_run_recovers(M):
         assert torch.equal(x, y)
     st.run(3, use_graph=True)      # re-sizes, re-captures, redoes the step
     assert st.step_count == 5
+
+
+def test_training_with_densify(M):
+    """The gradient statistic accumulates inside the captured step (and not
+    for a step whose render overflowed); densify clones, splits and prunes by
+    it, re-plans for the new number of Gaussians and training continues."""
+    R, S = M
+    from paper_2505_05643_amd import densify as Dn
+    gt, pt, wh, target = _problem(R, seed=97)
+    st = S.TrainStep(gt, pt, wh, target, adam=S.AdamConfig(lr_means=2e-3, lr_means_final=2e-4, decay_steps=60,
+                                                            lr=0.02))
+    l0 = st.run(20, use_graph=True, check_every=10)
+    torch.cuda.synchronize()
+    assert int(st.grad_cnt.min().item()) == 20 and float(st.grad_acc.max().item()) > 0.0
+    # an overflowed render leaves the statistic alone
+    acc0, cnt0 = st.grad_acc.clone(), st.grad_cnt.clone()
+    st.plan.reserve(4, 8)
+    st.graph = None
+    st.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(st.grad_acc, acc0) and torch.equal(st.grad_cnt, cnt0)
+    st.plan.fit(st.params, st.planes, st.headroom)
+    st.graph = None
+    n0 = st.params.means.shape[0]
+    med = float(st.grad_acc.median().item()) / 20.0
+    prm = Dn.DensifyParams(grad_thresh=med, split_size=0.05, min_opacity=0.3)
+    n1 = st.densify(prm, seed=3)
+    assert n1 != n0 and st.plan.n == n1
+    assert int(st.grad_cnt.sum().item()) == 0
+    l1 = st.run(20, use_graph=True, check_every=10)
+    assert all(np.isfinite(l1)) and l1[-1] < l0[0], (l0, l1)
