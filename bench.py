@@ -249,7 +249,18 @@ def main():
         scatter = {"forward_ms": s_ms if ok else None, "gather_forward_ms": fwd_ms,
                    "gather_speedup": (s_ms / fwd_ms) if (ok and fwd_ms) else None,
                    "pixels_off_gather_by_1e-4_peak": off, "pixels": int(image.numel())}
-        del splan, simg
+        del splan
+        # the paper-literal support: every pixel of the Eq. 13 box counts
+        bparams = R.Params(**{**params.__dict__,
+                              "flags": R._lib.UG_FLAG_SCATTER | R._lib.UG_FLAG_BOX_SUPPORT})
+        bplan = R.Plan(g.n, pl.wh, bparams, device=dev)
+        bplan.fit(gd, pd)
+        b_ms = replay_ms(lambda: bplan.render(gd, pd, simg, check_status=False), 1, max(2, args.steps // 10))
+        bok = bplan.status() == 0
+        scatter["box_support_forward_ms"] = b_ms if bok else None
+        # how far the box support moves the image from the ellipsoid support
+        scatter["box_support_max_change_by_peak"] = float((simg - image).abs().max()) / peak
+        del bplan, simg
 
     # in-support pairs of one forward, counted by the kernel itself
     cparams = R.Params(**{**params.__dict__, "flags": 1})

@@ -62,6 +62,15 @@ extern "C" {
                                  atomic additions is not fixed).  Forward only: the
                                  backward of such a plan returns UG_ERR_INVALID_ARG, and
                                  no keys are emitted (key_capacity may be 0)          */
+#define UG_FLAG_BOX_SUPPORT 4 /* with UG_FLAG_SCATTER only: the paper-literal support of
+                                 Phase 2 (Sec. 4.4).  A (Gaussian, plane) pair is kept
+                                 iff the plane meets the Eq. 13 box (decided in FP64,
+                                 with no slack), and then every pixel whose centre lies
+                                 in the in-plane part of that box, edges included, takes
+                                 the Eq. 8 weight: there is no per-pair Eq. 12 test, so
+                                 box corners outside the chi^2 ellipse count and the
+                                 image differs from the ellipsoid support.  box_mode is
+                                 ignored.  Without UG_FLAG_SCATTER: UG_ERR_INVALID_ARG */
 
 /* ---- pipeline stages (measurement hooks) ------------------------------- */
 #define UG_STAGE_SETUP 0         /* plane pose set-up                                  */

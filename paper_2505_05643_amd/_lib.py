@@ -26,6 +26,7 @@ UG_BOX_ROWS = 2
 UG_MSE_SCRATCH_FLOATS = 1026
 UG_FLAG_COUNT_EVALS = 1
 UG_FLAG_SCATTER = 2
+UG_FLAG_BOX_SUPPORT = 4
 
 STAGES = ("setup", "cull_count", "cull_write", "record", "emit", "sort_hist", "sort_scan", "sort_scatter", "ranges",
           "accum", "bwd_prep", "accum_bwd", "record_adj", "gauss_grad", "scatter")

@@ -105,7 +105,8 @@ bool valid_params(const ug_params& p) {
   if (!(p.bg_alpha > 0.f) || !std::isfinite(p.bg_alpha)) return false;
   if (!std::isfinite(p.bg_color)) return false;
   if (p.box_mode != UG_BOX_PAPER && p.box_mode != UG_BOX_CONIC && p.box_mode != UG_BOX_ROWS) return false;
-  if ((p.flags & ~(UG_FLAG_COUNT_EVALS | UG_FLAG_SCATTER)) != 0) return false;
+  if ((p.flags & ~(UG_FLAG_COUNT_EVALS | UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT)) != 0) return false;
+  if ((p.flags & UG_FLAG_BOX_SUPPORT) && !(p.flags & UG_FLAG_SCATTER)) return false;
   const int ppl = p.px_per_lane ? p.px_per_lane : accum_default_ppl(p.tile_w, p.tile_h);
   return accum_config_supported(p.tile_w, p.tile_h, ppl, p.lds_batch);
 }
@@ -152,6 +153,7 @@ RenderParams make_rp(const ug_plan* pl) {
   rp.tile_w = pl->prm.tile_w;
   rp.tile_h = pl->prm.tile_h;
   rp.box_mode = pl->prm.box_mode;
+  rp.box_support = (pl->prm.flags & UG_FLAG_BOX_SUPPORT) ? 1 : 0;
   rp.n = pl->n;
   rp.p = pl->p;
   rp.num_tiles = pl->num_tiles;
@@ -402,9 +404,12 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
     }
     if (e != hipSuccess) return UG_ERR_HIP;
     {
+      // box-support records carry their rectangle in pixels, others in tiles
+      const bool px = rp.box_support != 0;
       StageScope sc(plan, UG_STAGE_SCATTER, s);
       e = launch_scatter(ctrl, at<uint2>(ws, L.rec_pair), plan->d_pint, at<RecAcc>(ws, L.racc),
-                         at<RecGeo>(ws, L.rgeo), plan->prm.tile_w, plan->prm.tile_h, plan->rec_cap, image, den, s);
+                         at<RecGeo>(ws, L.rgeo), px ? 1 : plan->prm.tile_w, px ? 1 : plan->prm.tile_h,
+                         plan->rec_cap, image, den, s);
     }
     if (e != hipSuccess) return UG_ERR_HIP;
     StageScope sc(plan, UG_STAGE_SCATTER, s);

@@ -322,12 +322,67 @@ __device__ __forceinline__ uint32_t rows_count(const RecAcc& ra, const RecGeo& g
   return keys;
 }
 
+// The float record of an accepted pair: the in-plane factor scaled to pixel
+// units, the conic centre (u0, v0) split into an integer base pixel and a
+// fraction, the exponent offset and cut-off, the intensity.
+__device__ __forceinline__ void record_conic(const GaussIn& G, const PlaneConst& P, const Conic& k, double chi2,
+                                             double u0, double v0, Footprint& f) {
+  const double ks = sqrt(kHalfLog2e);
+  double ubd = floor(u0 + 0.5), vbd = floor(v0 + 0.5);
+  ubd = ubd < -1.0e9 ? -1.0e9 : (ubd > 1.0e9 ? 1.0e9 : ubd);
+  vbd = vbd < -1.0e9 ? -1.0e9 : (vbd > 1.0e9 ? 1.0e9 : vbd);
+  f.acc.t11 = (float)(ks * k.T11 * P.sx);
+  f.acc.t12 = (float)(ks * k.T12 * P.sy);
+  f.acc.t22 = (float)(ks * k.T22 * P.sy);
+  f.acc.fu = (float)(u0 - ubd);
+  f.acc.fv = (float)(v0 - vbd);
+  f.acc.e0 = (float)(G.log2a - kHalfLog2e * k.r2);
+  f.acc.emin = (float)(G.log2a - kHalfLog2e * chi2);
+  f.acc.c = (float)G.c;
+  f.geo.ub = (int32_t)ubd;
+  f.geo.vb = (int32_t)vbd;
+}
+
+// Pixels [lo, hi] (clipped to the image) whose index lies in
+// [centre - half, centre + half], edges included, with no padding; false if
+// none.
+__device__ __forceinline__ bool box_pixels(double centre, double half, int32_t size, int& lo, int& hi) {
+  double a = centre - half, b = centre + half;
+  if (!(a <= b)) return false;  // NaN
+  if (b < 0.0 || a > (double)(size - 1)) return false;
+  a = a > 0.0 ? ceil(a) : 0.0;
+  b = b < (double)(size - 1) ? floor(b) : (double)(size - 1);
+  lo = (int)a;
+  hi = (int)b;
+  return lo <= hi;
+}
+
+// Record of a pair under the paper-literal Phase-2 support (the plane meets
+// the Eq. 13 box, decided by the caller): the rectangle fields hold the
+// pixels whose centres lie in the in-plane part of the box, b_{1:2} = m_{1:2}
+// -/+ sqrt(chi^2 Sigma'_kk), and the cut-off is -inf, so every pixel of the
+// rectangle takes its Eq. 8 weight.  Pixel u's centre is at
+// (u - cu) sx in the plane, hence the index interval below.  No keys.
+__device__ __forceinline__ bool make_box_record(const GaussIn& G, const PlaneConst& P, const PlaneInt& PI,
+                                                const Conic& k, double chi2, Footprint& f) {
+  int ulo, uhi, vlo, vhi;
+  if (!box_pixels(k.m1 / P.sx + P.cu, sqrt(chi2 * k.S11) / P.sx, PI.W, ulo, uhi)) return false;
+  if (!box_pixels(k.m2 / P.sy + P.cv, sqrt(chi2 * k.S22) / P.sy, PI.H, vlo, vhi)) return false;
+  record_conic(G, P, k, chi2, k.c1 / P.sx + P.cu, k.c2 / P.sy + P.cv, f);
+  f.acc.emin = -INFINITY;
+  f.geo.tx0 = (uint16_t)ulo;
+  f.geo.tx1 = (uint16_t)uhi;
+  f.geo.ty0 = (uint16_t)vlo;
+  f.geo.ty1 = (uint16_t)vhi;
+  f.keys = 0;
+  return true;
+}
+
 // Record, tile rectangle and key count of an accepted pair (conic_full done).
 // Returns false if the footprint misses the image.
 __device__ __forceinline__ bool make_footprint(const GaussIn& G, const PlaneConst& P, const PlaneInt& PI,
                                                const Conic& k, double chi2, int box_mode, int TW, int TH,
                                                Footprint& f) {
-  const double ks = sqrt(kHalfLog2e);
   const double u0 = k.c1 / P.sx + P.cu;
   const double v0 = k.c2 / P.sy + P.cv;
   int ulo, uhi, vlo, vhi;
@@ -343,19 +398,7 @@ __device__ __forceinline__ bool make_footprint(const GaussIn& G, const PlaneCons
     if (!pixel_range(u0, sqrt(q * cross_norm2(k.g1, k.g3) * k.iS) / P.sx, PI.W, ulo, uhi)) return false;
     if (!pixel_range(v0, sqrt(q * cross_norm2(k.g2, k.g3) * k.iS) / P.sy, PI.H, vlo, vhi)) return false;
   }
-  double ubd = floor(u0 + 0.5), vbd = floor(v0 + 0.5);
-  ubd = ubd < -1.0e9 ? -1.0e9 : (ubd > 1.0e9 ? 1.0e9 : ubd);
-  vbd = vbd < -1.0e9 ? -1.0e9 : (vbd > 1.0e9 ? 1.0e9 : vbd);
-  f.acc.t11 = (float)(ks * k.T11 * P.sx);
-  f.acc.t12 = (float)(ks * k.T12 * P.sy);
-  f.acc.t22 = (float)(ks * k.T22 * P.sy);
-  f.acc.fu = (float)(u0 - ubd);
-  f.acc.fv = (float)(v0 - vbd);
-  f.acc.e0 = (float)(G.log2a - kHalfLog2e * k.r2);
-  f.acc.emin = (float)(G.log2a - kHalfLog2e * chi2);
-  f.acc.c = (float)G.c;
-  f.geo.ub = (int32_t)ubd;
-  f.geo.vb = (int32_t)vbd;
+  record_conic(G, P, k, chi2, u0, v0, f);
   f.geo.tx0 = (uint16_t)(ulo / TW);
   f.geo.tx1 = (uint16_t)(uhi / TW);
   f.geo.ty0 = (uint16_t)(vlo / TH);

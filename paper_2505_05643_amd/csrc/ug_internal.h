@@ -116,6 +116,7 @@ struct Partial {
 struct RenderParams {
   float beta, chi2, bg_alpha, bg_color;
   int32_t tile_w, tile_h, box_mode;
+  int32_t box_support;  // paper-literal Phase-2 support (records carry pixel boxes)
   int32_t n, p;
   uint32_t num_tiles;
   uint32_t rec_cap, key_cap;

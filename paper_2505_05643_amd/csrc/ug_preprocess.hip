@@ -301,11 +301,15 @@ __global__ __launch_bounds__(256) void k_record(ug_gaussians g, const PlaneConst
     const PlaneConst& P = pc[gp.y];
     const PlaneT<double> Pd = plane_as<double>(P);
     Conic k;
-    conic_cull(G, Pd, chi2, k);
+    const bool meets = conic_cull(G, Pd, chi2, k);
     conic_full(G, Pd, k);
     Footprint f;
-    if (!make_footprint(G, P, pint[gp.y], k, chi2, rp.box_mode, rp.tile_w, rp.tile_h, f)) {
-      // the plane cuts the ellipsoid outside the image: a record with no keys
+    // Box support: the FP64 Phase-1 decision is final (a pair the
+    // conservative float cull let through would otherwise fill its box).
+    const bool ok = rp.box_support ? (meets && make_box_record(G, P, pint[gp.y], k, chi2, f))
+                                   : make_footprint(G, P, pint[gp.y], k, chi2, rp.box_mode, rp.tile_w, rp.tile_h, f);
+    if (!ok) {
+      // the plane cuts the ellipsoid (or box) outside the image: a record with no keys
       f.keys = 0;
       f.acc = RecAcc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       f.geo = RecGeo{0, 0, 1, 0, 1, 0};

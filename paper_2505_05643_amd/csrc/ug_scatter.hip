@@ -11,6 +11,11 @@
 // walk the record's pixel box 64 at a time.  The box is the record's tile
 // rectangle (from the chosen binning) cut to the ellipse's bounding box,
 // padded so float rounding never drops a pixel the per-pair test keeps.
+//
+// With the paper-literal box support the records hold the exact pixel
+// rectangle of their Eq. 13 box and a cut-off of -inf: the same kernel,
+// launched with a 1 x 1 "tile", adds every pixel of the rectangle (the
+// ellipse cut is skipped because the cut-off is unbounded).
 #include "ug_kernels.h"
 
 namespace ug {

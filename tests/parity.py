@@ -45,6 +45,27 @@ def check_image(gpu: np.ndarray, g, planes, params, pix=None, tol_rel=IMAGE_TOL,
             "max_rel_peak": float(diff.max() / max(pk, 1e-30))}
 
 
+def check_image_box_support(gpu: np.ndarray, g, planes, params, pix=None, tol_rel=IMAGE_TOL):
+    """Element-wise parity against the paper-literal box-support reference;
+    pixels off by more than tol must lie within tol of the interval spanned
+    by its borderline decisions.  Returns a stats dict."""
+    from oracle.box_support import render_box_support
+    ref, _, lo, hi, k = render_box_support(g, planes, oracle_params(params), pix=pix)
+    gpu = np.asarray(gpu, dtype=np.float64).reshape(-1)
+    assert gpu.shape == ref.shape
+    assert np.all(np.isfinite(gpu)), "non-finite GPU output"
+    pk = float(np.abs(ref).max())
+    tol = tol_rel * max(pk, 1e-30)
+    diff = np.abs(gpu - ref)
+    bad = diff > tol
+    dist = np.maximum(lo - gpu, gpu - hi)
+    assert np.all(dist[bad] <= tol), f"{int(np.sum(dist[bad] > tol))} pixels outside tolerance"
+    n_amb = int(np.sum(k > 0))
+    assert n_amb <= max(1, AMBIG_FRAC * gpu.size), f"{n_amb} ambiguous pixels"
+    return {"max_abs": float(diff.max()), "tol": tol, "peak": pk, "ambiguous": n_amb,
+            "max_rel_peak": float(diff.max() / max(pk, 1e-30))}
+
+
 def check_grads(gpu: dict, ref: dict, tol_rel=GRAD_TOL):
     errs = {}
     for name in ("means", "lraw", "intensity", "opacity"):

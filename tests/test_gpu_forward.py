@@ -179,3 +179,51 @@ def test_configs_sampled_pixels_phase2_scatter(R, k, count):
     flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
     st = check_image(img[flat], g, pl, plan.params, pix=pix)
     print(f"scatter c{k}", st)
+
+
+def test_paper_phase2_box_support(R):
+    """UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT, the paper-literal Phase 2:
+    every pixel whose centre lies in a kept pair's Eq. 13 box takes the Eq. 8
+    weight.  Parity with the box-support reference; the image departs from
+    the ellipsoid support (box corners count); with chi^2 = inf both supports
+    are the plain sum; the flag needs the scatter; no backward."""
+    from paper_2505_05643_amd._lib import UG_FLAG_BOX_SUPPORT, UG_FLAG_SCATTER, UgError
+    from tests.parity import check_image_box_support
+    fl = UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT
+    cases = [synth.make_config(0)[:2]]
+    g1 = synth.make_gaussians(300, 41, (0, 0, 0), (1, 1, 1), (0.02, 0.12), aniso_max=8.0, opacity="random")
+    p1 = synth.random_planes(3, 42, (8, 8), 1 / 40, 0.3, 0.7)
+    p1.wh[:] = [[37, 23], [8, 8], [50, 41]]
+    cases.append((g1, p1))
+    for g, pl in cases:
+        for bm in (0, 2):  # the binning box is ignored under the box support
+            img, plan = _render(R, g, pl, R.Params(box_mode=bm, flags=fl))
+            st = check_image_box_support(img, g, pl, plan.params)
+            ell, _ = _render(R, g, pl, R.Params(box_mode=bm, flags=UG_FLAG_SCATTER))
+            change = float(np.abs(img.astype(np.float64) - ell).max()) / st["peak"]
+            assert change > 100 * 1e-4, f"box support changed the image by only {change:.3g} of peak"
+            print("box support", st, "change vs ellipsoid", change)
+    g, pl = cases[1]
+    img, plan = _render(R, g, pl, R.Params(chi2=math.inf, flags=fl))
+    check_image_box_support(img, g, pl, plan.params)
+    check_image(img, g, pl, plan.params)  # the ellipsoid reference at chi^2 = inf
+    with pytest.raises(UgError):
+        R.Plan(g.n, pl.wh, R.Params(flags=UG_FLAG_BOX_SUPPORT), device=torch.device("cuda", 0))
+    dev = torch.device("cuda", 0)
+    gd, pd = R.to_device(g, dev), R.to_device(pl, dev)
+    with pytest.raises(UgError):
+        plan.backward(gd, pd, torch.from_numpy(img).to(dev), torch.zeros(plan.num_pixels, device=dev))
+
+
+def test_configs_sampled_pixels_box_support(R):
+    """The box-support Phase 2 on the full c1 workload (50k Gaussians, 16
+    planes of 160^2): a seeded sample of pixels against the reference."""
+    from paper_2505_05643_amd._lib import UG_FLAG_BOX_SUPPORT, UG_FLAG_SCATTER
+    from tests.parity import check_image_box_support
+    g, pl, _ = synth.make_config(1)
+    img, plan = _render(R, g, pl, R.Params(flags=UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT))
+    pix = synth.sample_pixels(pl, 1500, 801)
+    offs = pl.pixel_offsets()
+    flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
+    st = check_image_box_support(img[flat], g, pl, plan.params, pix=pix)
+    print("box support c1", st)
