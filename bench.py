@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scatter", action="store_true", help="skip timing the Phase-2 atomic scatter forward")
     ap.add_argument("--no-densify", action="store_true", help="skip timing the densify / prune pass")
+    ap.add_argument("--no-recon", action="store_true",
+                    help="skip the synthetic reconstruction-quality workload (run with the default workload)")
+    ap.add_argument("--recon-steps", type=int, default=300, help="training steps per reconstruction case")
     ap.add_argument("--cpu-px", type=int, default=640)
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch configuration")
@@ -389,6 +392,8 @@ def main():
         "kernels": kernels,
         "roofline": roof,
     }
+    if k == 1 and not args.no_recon and not args.no_graph:
+        out["reconstruction"] = reconstruction(dev, args.recon_steps)
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(k, args.cpu_px)
@@ -411,6 +416,32 @@ def main():
         for _ in range(5):
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
+
+
+def reconstruction(dev, steps):
+    """The synthetic reconstruction-quality workload: each case (full axial
+    coverage, half, half with +-5 degree tilts) trained from the Section 4.5
+    initialisation for ``steps`` graph-replayed steps over all its slices,
+    then scored by SSIM / PSNR on 160 axial, coronal and sagittal slices."""
+    from paper_2505_05643_amd import raster as R
+    from paper_2505_05643_amd import recon, synth
+    setup = recon.ReconSetup(steps=steps)
+    truth = R.to_device(recon.truth_gaussians(setup), dev)
+    scorer = recon.Scorer(setup, truth, R.Params(), dev)
+    cases = [recon.run_case(setup, c, dev, scorer=scorer) for c in recon.CASES]
+    # the scoring kernel alone over all evaluation slices: it reads two
+    # float32 images (8 B per pixel); its FP64 window sums bound it (row
+    # pass 10 flop per tap x 11 taps x 18/8 rows per pixel, column pass
+    # 5 x 2 flop x 11 taps, the score about 20: about 380 flop per pixel)
+    img = scorer.images(R.to_device(synth.paper_init(setup.n_model, 6000), dev))
+    q_ms = scorer.quality_ms(img)
+    npx = img.numel()
+    return {"setup": {"volume": f"phantom in the unit cube, {setup.n_truth} seeded ground-truth Gaussians",
+                      "slices": f"{setup.size}^2", "gaussians": setup.n_model, "steps": steps},
+            "cases": cases,
+            "quality_kernel": {"ms": q_ms, "pixels": npx, "gpix_per_s": npx / (q_ms * 1e6),
+                               "hbm_gbs": 8 * npx / (q_ms * 1e6),
+                               "fp64_tflops": 380 * npx / (q_ms * 1e9)}}
 
 
 def densify_ms(R, gd, dev, warmup, steps):

@@ -316,6 +316,29 @@ int ug_densify(const ug_gaussians *g, const float *acc, const int32_t *cnt, cons
                const ug_densify_params *dp, const ug_gaussians_mut *out, int64_t out_capacity,
                int64_t *count_dev, void *workspace, void *stream);
 
+/* ---- scoring reconstructions ------------------------------------------ */
+
+/* Bytes of device workspace ug_image_quality needs for this plan's planes. */
+size_t ug_quality_workspace_bytes(const ug_plan *plan);
+
+/* Image-quality scores of packed planes against references, for the SSIM
+ * and PSNR evaluation of Section 5.2.  image, ref: device float32 [M_px],
+ * packed like ug_render_planes images (the plan's planes and sizes).  Per
+ * plane p: ssim[p] = the mean SSIM (Wang et al. 2004: 11 x 11 Gaussian
+ * window, standard deviation 1.5, weights summing to one, weighted
+ * population moments, C1 = (0.01 L)^2, C2 = (0.03 L)^2, L = data_range)
+ * over the window positions that lie wholly inside the image (NaN for a
+ * plane under 11 pixels in either direction); mse[p] = the mean squared
+ * difference over all its pixels, so PSNR = 10 log10(L^2 / mse[p]).
+ * ssim, mse: device float64 [P].  Moments are summed in FP64 and every sum
+ * is taken in a fixed order, so the scores are deterministic.  workspace:
+ * ug_quality_workspace_bytes(plan) bytes of device memory, 256-byte aligned,
+ * caller-owned (independent of the render workspace).  Errors:
+ * UG_ERR_INVALID_ARG for a NULL pointer, misaligned workspace or a
+ * data_range that is not positive and finite.  No synchronisation. */
+int ug_image_quality(const ug_plan *plan, const float *image, const float *ref, float data_range,
+                     double *ssim, double *mse, void *workspace, void *stream);
+
 /* Human-readable text for a status code (static storage). */
 const char *ug_status_string(int status);
 

@@ -91,6 +91,8 @@ SIGNATURES = {
     "ug_densify_workspace_bytes": (ctypes.c_size_t, [c_i32]),
     "ug_densify": (c_i32, [ctypes.POINTER(UgGaussians), c_vp, c_vp, c_vp, ctypes.POINTER(UgDensifyParams),
                            ctypes.POINTER(UgGaussiansMut), c_i64, c_vp, c_vp, c_vp]),
+    "ug_quality_workspace_bytes": (ctypes.c_size_t, [c_vp]),
+    "ug_image_quality": (c_i32, [c_vp, c_vp, c_vp, c_f32, c_vp, c_vp, c_vp, c_vp]),
     "ug_status_string": (ctypes.c_char_p, [c_i32]),
     "ug_plan_destroy": (None, [c_vp]),
 }

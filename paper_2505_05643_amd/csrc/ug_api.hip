@@ -587,6 +587,33 @@ int ug_densify(const ug_gaussians* g, const float* acc, const int32_t* cnt, cons
                                    static_cast<uint32_t*>(workspace), static_cast<hipStream_t>(stream)));
 }
 
+size_t ug_quality_workspace_bytes(const ug_plan* plan) {
+  return plan ? align_up((size_t)plan->num_tiles * quality_subs(plan->prm.tile_w, plan->prm.tile_h) *
+                         sizeof(double2))
+              : 0;
+}
+
+int ug_image_quality(const ug_plan* plan, const float* image, const float* ref, float data_range, double* ssim,
+                     double* mse, void* workspace, void* stream) {
+  if (!plan || !image || !ref || !ssim || !mse || !workspace) return UG_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return UG_ERR_INVALID_ARG;
+  if (!(data_range > 0.f) || !std::isfinite(data_range)) return UG_ERR_INVALID_ARG;
+  QualityConst q;
+  double sum = 0.0;
+  for (int k = 0; k < 11; ++k) {
+    const double d = (double)(k - 5);
+    q.taps[k] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+    sum += q.taps[k];
+  }
+  for (int k = 0; k < 11; ++k) q.taps[k] /= sum;
+  const double L = (double)data_range;
+  q.c1 = (0.01 * L) * (0.01 * L);
+  q.c2 = (0.03 * L) * (0.03 * L);
+  return hip_status(launch_quality(plan->d_pint, plan->d_tile_plane, plan->d_tile_org, plan->num_tiles, plan->p,
+                                   plan->prm.tile_w, plan->prm.tile_h, image, ref, q,
+                                   static_cast<double2*>(workspace), ssim, mse, static_cast<hipStream_t>(stream)));
+}
+
 const char* ug_status_string(int status) {
   switch (status) {
     case UG_OK: return "ok";

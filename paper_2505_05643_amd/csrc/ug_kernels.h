@@ -88,6 +88,16 @@ hipError_t launch_sample(const ug_gaussians& g, float beta, const int32_t* idx, 
 hipError_t launch_grad_norm(const Ctrl* ctrl, const float* d_means, int32_t n, float* acc, int32_t* cnt,
                             hipStream_t s);
 
+// ---- image-quality scores (ug_quality.hip)
+struct QualityConst {
+  double taps[11];  // normalised 1D Gaussian window
+  double c1, c2;
+};
+uint32_t quality_subs(int tile_w, int tile_h);  // 8 x 8 sub-blocks per tile
+hipError_t launch_quality(const PlaneInt* pint, const uint32_t* tile_plane, const uint32_t* tile_org,
+                          uint32_t num_tiles, int32_t p, int tile_w, int tile_h, const float* img, const float* ref,
+                          const QualityConst& q, double2* part, double* ssim, double* mse, hipStream_t s);
+
 // ---- accumulate (ug_raster.hip)
 int accum_default_ppl(int tile_w, int tile_h);
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);

@@ -195,6 +195,22 @@ class Plan:
               "ug_render_planes_backward")
         return grads
 
+    def quality(self, image: torch.Tensor, ref: torch.Tensor, data_range: float = 1.0):
+        """Per-plane (ssim, mse) float64 device tensors of ``image`` against
+        ``ref`` (both packed like this plan's renders): mean SSIM over the
+        11 x 11 Gaussian windows inside each plane and MSE over its pixels."""
+        for t in (image, ref):
+            if t.numel() != self.num_pixels or not t.is_contiguous() or t.dtype != torch.float32:
+                raise ValueError("images must be contiguous float32 tensors of num_pixels elements")
+        nbytes = int(lib.ug_quality_workspace_bytes(self._h))
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (ws.data_ptr() + 255) // 256 * 256
+        ssim = torch.empty(self.p, dtype=torch.float64, device=self.device)
+        mse = torch.empty(self.p, dtype=torch.float64, device=self.device)
+        check(lib.ug_image_quality(self._h, image.data_ptr(), ref.data_ptr(), float(data_range), ssim.data_ptr(),
+                                   mse.data_ptr(), ptr, _stream()), "ug_image_quality")
+        return ssim, mse
+
     def status(self, counts: bool = False):
         """Device status of the last render (synchronises); with counts=True
         (code, records, keys, in-support pairs, evaluated pairs), the last two
