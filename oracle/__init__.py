@@ -17,13 +17,13 @@ function here.  The one part that is not pinned to a unique value is which
 of several correct outputs a pixel takes when a pair sits on the cut-off
 d^2 = chi^2 to within rounding: ``ambiguity`` reports the interval instead.
 """
-from . import box_support, densify, quality
+from . import box_support, densify, params, quality
 from .render import (CHI2_PAPER, Params, activate_l, covariance, sigmoid,
                      plane_points, render, render_points, grad, grad_points,
                      ambiguity_points, box_eq13, inplane_conic, d2_points,
                      sample_gaussian)
 
-__all__ = ["box_support", "densify", "quality", "CHI2_PAPER", "Params", "activate_l", "covariance", "sigmoid",
+__all__ = ["box_support", "densify", "params", "quality", "CHI2_PAPER", "Params", "activate_l", "covariance", "sigmoid",
            "plane_points", "render", "render_points", "grad", "grad_points",
            "ambiguity_points", "box_eq13", "inplane_conic", "d2_points",
            "sample_gaussian"]

@@ -57,28 +57,34 @@ __global__ __launch_bounds__(kDensifyThreads) void k_densify_count(ug_gaussians 
 }
 
 // One block: exclusive scan of the block counts in place, the total to
-// *count.
+// *count.  Thread t owns a contiguous run of the block counts; the run sums
+// are scanned across the block (wave prefix by shuffles, then the 16 wave
+// totals), and each thread rewrites its run from its exclusive prefix.
 __global__ __launch_bounds__(1024) void k_densify_scan(uint32_t* __restrict__ blk, uint32_t nblk,
                                                        int64_t* __restrict__ count) {
-  __shared__ unsigned long long s_part[1024];
+  __shared__ unsigned long long s_wave[16];
   const uint32_t t = threadIdx.x;
+  const int lane = (int)(t & 63u), wave = (int)(t >> 6);
   const uint32_t per = (nblk + 1023u) / 1024u;
-  const uint32_t b0 = t * per, b1 = min(b0 + per, nblk);
+  const uint32_t b0 = min(t * per, nblk), b1 = min(b0 + per, nblk);
   unsigned long long s = 0;
   for (uint32_t b = b0; b < b1; ++b) s += blk[b];
-  s_part[t] = s;
-  __syncthreads();
-  if (t == 0) {  // 1024 partial sums in order
-    unsigned long long run = 0;
-    for (int j = 0; j < 1024; ++j) {
-      const unsigned long long v = s_part[j];
-      s_part[j] = run;
-      run += v;
-    }
-    *count = (int64_t)run;
+  unsigned long long x = s;  // inclusive prefix within the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
+  if (lane == 63) s_wave[wave] = x;
   __syncthreads();
-  unsigned long long run = s_part[t];
+  unsigned long long before = 0, total = 0;
+  for (int w = 0; w < 16; ++w) {
+    const unsigned long long v = s_wave[w];
+    if (w < wave) before += v;
+    total += v;
+  }
+  if (t == 0) *count = (int64_t)total;
+  unsigned long long run = before + x - s;
   for (uint32_t b = b0; b < b1; ++b) {
     const uint32_t v = blk[b];
     blk[b] = (uint32_t)run;

@@ -399,6 +399,38 @@ def paper_init(n: int, seed: int, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Gau
     return Gaussians(means.astype(f), lraw.astype(f), np.full(n, 0.5, dtype=f), np.ones(n, dtype=f))
 
 
+# ---------------------------------------------------------------- parameterisation study
+def param_study_inputs(n: int, seed: int, aniso: float, beta: float = DEFAULT_BETA):
+    """Seeded covariances with anisotropy ``aniso`` (scales 1/aniso,
+    aniso^-u with u ~ U(0, 1), and 1; random rotations) in the three raw
+    layouts (8 float32 each): triangular factor of the precision (Eq. 11),
+    symmetric M = R diag(sqrt(s^-2 - beta)) R^T (Eq. 10) and unit quaternion
+    with scales; standard normals z [n, 3]; offsets delta [n, 3] at
+    Mahalanobis distance U(0.5, 2.8); and the FP64 scales and rotations."""
+    rng = np.random.default_rng(seed)
+    u = rng.random(n)
+    scales = np.stack([np.full(n, 1.0 / aniso), aniso ** -u, np.ones(n)], axis=1)
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    rots = quat_to_rot(q)
+    tri = np.zeros((n, 8))
+    tri[:, :6] = scales_rots_to_lraw(scales, rots, beta)
+    ev = np.sqrt(scales ** -2 - beta)
+    M = rots @ (np.transpose(rots, (0, 2, 1)) * ev[:, :, None])
+    sym = np.zeros((n, 8))
+    sym[:, :6] = np.stack([M[:, 0, 0], M[:, 0, 1], M[:, 0, 2], M[:, 1, 1], M[:, 1, 2], M[:, 2, 2]], axis=1)
+    quat = np.zeros((n, 8))
+    quat[:, :4] = q
+    quat[:, 4:7] = scales
+    z = rng.standard_normal((n, 3))
+    w = rng.standard_normal((n, 3))
+    w *= (rng.uniform(0.5, 2.8, n) / np.linalg.norm(w, axis=1))[:, None]
+    delta = (rots @ (scales * w)[:, :, None])[:, :, 0]
+    f = np.float32
+    return {"tri": tri.astype(f), "sym": sym.astype(f), "quat": quat.astype(f), "z": z.astype(f),
+            "delta": delta.astype(f), "scales": scales, "rots": rots}
+
+
 def sample_pixels(planes: Planes, count: int, seed: int) -> np.ndarray:
     """Seeded (plane, u, v) triples, uniform over all pixels of the launch."""
     rng = np.random.default_rng(seed)

@@ -67,7 +67,7 @@ def test_accumulate_grad_norm(M):
     assert np.all(cnt.cpu().numpy() == 5)
 
 
-@pytest.mark.parametrize("n,seed", [(1, 5), (257, 6), (20_000, 7)])
+@pytest.mark.parametrize("n,seed", [(1, 5), (257, 6), (20_000, 7), (600_000, 8)])
 def test_densify_matches_reference(M, n, seed):
     R, Dn = M
     dev = torch.device("cuda", 0)
