@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--no-recon", action="store_true",
                     help="skip the synthetic reconstruction-quality workload (run with the default workload)")
     ap.add_argument("--recon-steps", type=int, default=300, help="training steps per reconstruction case")
+    ap.add_argument("--no-param-study", action="store_true",
+                    help="skip the covariance parameterisation study (run with the default workload)")
     ap.add_argument("--cpu-px", type=int, default=640)
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch configuration")
@@ -394,6 +396,10 @@ def main():
     }
     if k == 1 and not args.no_recon and not args.no_graph:
         out["reconstruction"] = reconstruction(dev, args.recon_steps)
+    if k == 1 and not args.no_param_study:
+        from paper_2505_05643_amd import paramstudy
+        out["parameterization"] = {"float32_error": paramstudy.study(device=dev),
+                                   "throughput": paramstudy.throughput(device=dev)}
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(k, args.cpu_px)

@@ -339,6 +339,35 @@ size_t ug_quality_workspace_bytes(const ug_plan *plan);
 int ug_image_quality(const ug_plan *plan, const float *image, const float *ref, float data_range,
                      double *ssim, double *mse, void *workspace, void *stream);
 
+/* ---- covariance parameterisation study -------------------------------- */
+
+#define UG_PARAM_TRI 0  /* Eq. 11: (l11, l21, l31, l22, l32, l33), Sigma^-1 = L L^T,
+                           diagonal l^2 + beta                                    */
+#define UG_PARAM_SYM 1  /* Eq. 10: (M11, M12, M13, M22, M23, M33), M symmetric,
+                           Sigma^-1 = M M^T + beta I                               */
+#define UG_PARAM_QUAT 2 /* (qw, qx, qy, qz, s1, s2, s3): Sigma = R diag(s^2) R^T,
+                           R of the normalised quaternion                          */
+
+/* Sec. 4.2's comparison of covariance parameterisations: per Gaussian, one
+ * route's covariance, a draw and a distance, in float32 (fp64 = 0) or
+ * float64 (fp64 = 1; the reference for the float32 rounding, which for SYM
+ * inverts the precision through its Cholesky factor instead of the
+ * adjugate, whose error grows with the squared condition number).
+ *   raw   [n][8] float32, the kind's layout (unused entries ignored);
+ *   z     [n][3] float32 standard normals; delta [n][3] float32 offsets;
+ *   sigma [n][6] out: Sigma (11, 12, 13, 22, 23, 33) -- from L^-1 written out
+ *         (TRI), the adjugate inverse of the precision (SYM), the product
+ *         (QUAT);
+ *   draw  [n][3] out: F z with F F^T = Sigma -- back substitution with L^T
+ *         (TRI), the lower Cholesky factor of that Sigma (SYM; NaN when a
+ *         pivot is not positive), R diag(s) (QUAT);
+ *   d2    [n] out: delta^T Sigma^-1 delta.
+ * Outputs are float32 or float64 as fp64 says; all pointers are device
+ * memory owned by the caller.  Errors: UG_ERR_INVALID_ARG for an unknown
+ * kind, n < 0 or a NULL pointer with n > 0.  No synchronisation. */
+int ug_param_eval(int32_t kind, int32_t fp64, const float *raw, const float *z, const float *delta, int64_t n,
+                  float beta, void *sigma, void *draw, void *d2, void *stream);
+
 /* Human-readable text for a status code (static storage). */
 const char *ug_status_string(int status);
 

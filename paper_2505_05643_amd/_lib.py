@@ -27,6 +27,7 @@ UG_MSE_SCRATCH_FLOATS = 1026
 UG_FLAG_COUNT_EVALS = 1
 UG_FLAG_SCATTER = 2
 UG_FLAG_BOX_SUPPORT = 4
+UG_PARAM_TRI, UG_PARAM_SYM, UG_PARAM_QUAT = 0, 1, 2
 
 STAGES = ("setup", "cull_count", "cull_write", "record", "emit", "sort_hist", "sort_scan", "sort_scatter", "ranges",
           "accum", "bwd_prep", "accum_bwd", "record_adj", "gauss_grad", "scatter")
@@ -93,6 +94,7 @@ SIGNATURES = {
                            ctypes.POINTER(UgGaussiansMut), c_i64, c_vp, c_vp, c_vp]),
     "ug_quality_workspace_bytes": (ctypes.c_size_t, [c_vp]),
     "ug_image_quality": (c_i32, [c_vp, c_vp, c_vp, c_f32, c_vp, c_vp, c_vp, c_vp]),
+    "ug_param_eval": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_i64, c_f32, c_vp, c_vp, c_vp, c_vp]),
     "ug_status_string": (ctypes.c_char_p, [c_i32]),
     "ug_plan_destroy": (None, [c_vp]),
 }

@@ -614,6 +614,16 @@ int ug_image_quality(const ug_plan* plan, const float* image, const float* ref, 
                                    static_cast<double2*>(workspace), ssim, mse, static_cast<hipStream_t>(stream)));
 }
 
+int ug_param_eval(int32_t kind, int32_t fp64, const float* raw, const float* z, const float* delta, int64_t n,
+                  float beta, void* sigma, void* draw, void* d2, void* stream) {
+  if (kind != UG_PARAM_TRI && kind != UG_PARAM_SYM && kind != UG_PARAM_QUAT) return UG_ERR_INVALID_ARG;
+  if (n < 0 || (fp64 != 0 && fp64 != 1)) return UG_ERR_INVALID_ARG;
+  if (n > 0 && (!raw || !z || !delta || !sigma || !draw || !d2)) return UG_ERR_INVALID_ARG;
+  if (n > (int64_t)0x7fffffff * 256) return UG_ERR_INVALID_ARG;  // grid limit
+  return hip_status(launch_param_eval(kind, fp64 != 0, raw, z, delta, n, beta, sigma, draw, d2,
+                                      static_cast<hipStream_t>(stream)));
+}
+
 const char* ug_status_string(int status) {
   switch (status) {
     case UG_OK: return "ok";

@@ -98,6 +98,10 @@ hipError_t launch_quality(const PlaneInt* pint, const uint32_t* tile_plane, cons
                           uint32_t num_tiles, int32_t p, int tile_w, int tile_h, const float* img, const float* ref,
                           const QualityConst& q, double2* part, double* ssim, double* mse, hipStream_t s);
 
+// ---- covariance parameterisation study (ug_params.hip)
+hipError_t launch_param_eval(int32_t kind, bool fp64, const float* raw, const float* z, const float* delta,
+                             int64_t n, float beta, void* sigma, void* draw, void* d2, hipStream_t s);
+
 // ---- accumulate (ug_raster.hip)
 int accum_default_ppl(int tile_w, int tile_h);
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);
