@@ -158,10 +158,9 @@ def main():
     grads = R.GaussianTensors(torch.empty_like(gd.means), torch.empty_like(gd.lraw),
                               torch.empty_like(gd.intensity), torch.empty_like(gd.opacity))
 
-    def step(p=plan, gg=gd, pp=pd, img=image, dimg=d_image, gr=grads, tgt=target):
+    def step(p=plan, gg=gd, pp=pd, img=image, gr=grads, tgt=target):
         p.render(gg, pp, img, check_status=False)
-        R.mse_grad(img, tgt, dimg, loss_buf)
-        p.backward(gg, pp, img, dimg, gr)
+        p.backward_mse(gg, pp, img, tgt, gr, loss_buf=loss_buf)
 
     for _ in range(args.warmup):
         step()
@@ -373,7 +372,7 @@ def main():
         "config": {"workload": synth.CONFIG_NAMES[k], "gaussians": g.n, "planes": pl.p,
                    "pixels": int(pl.npix), "tile": f"{params.tile_w}x{params.tile_h}",
                    "px_per_lane": plan_ppl(params), "lds_batch": params.lds_batch, "box_mode": params.box_mode,
-                   "step": "render + mse grad + backward",
+                   "step": "render + MSE adjoint (gradient of the loss formed in the first adjoint kernel)",
                    "launch": "hipGraph replay" if graph_ms_step is not None else "eager"},
         "autotune": tuned,
         "eager_ms_per_step": eager_ms_step,

@@ -185,6 +185,21 @@ int ug_render_planes_backward(const ug_plan *plan, const ug_gaussians *g,
                               float *d_lraw, float *d_intensity, float *d_opacity,
                               int32_t accumulate, void *stream);
 
+/* The same adjoint for the training loss of Sec. 4.5, the mean squared
+ * error against target ([num_pixels] float32, the image's layout), fused:
+ * dL/dc_hat = 2 (image - target) / num_pixels is formed inside the first
+ * adjoint kernel with the float operations ug_mse_grad uses, so the
+ * gradients equal ug_mse_grad followed by ug_render_planes_backward bit for
+ * bit, with one launch and one pixel array less.  loss_dev (device float32,
+ * may be NULL) receives the mean squared error, written by the last adjoint
+ * kernel from per-block sums added in a fixed order (FP64).  Other
+ * arguments, errors and determinism as ug_render_planes_backward. */
+int ug_render_planes_backward_mse(const ug_plan *plan, const ug_gaussians *g,
+                                  const ug_planes *planes, const float *image,
+                                  const float *target, void *workspace, float *d_means,
+                                  float *d_lraw, float *d_intensity, float *d_opacity,
+                                  int32_t accumulate, float *loss_dev, void *stream);
+
 /* Reads the device-side status the last render left in the workspace
  * (synchronises the stream): UG_OK, UG_ERR_CAPACITY, UG_ERR_NONFINITE or
  * UG_ERR_INTERNAL.  counts_host (may be NULL) receives [records, keys,

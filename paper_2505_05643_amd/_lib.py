@@ -78,6 +78,8 @@ SIGNATURES = {
     "ug_render_planes": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp, c_vp, c_vp]),
     "ug_render_planes_backward": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp,
                                           c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "ug_render_planes_backward_mse": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp,
+                                              c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp]),
     "ug_plan_status": (c_i32, [c_vp, c_vp, ctypes.POINTER(c_i64), c_vp]),
     "ug_mse_grad": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "ug_adam_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_f32, c_f32, c_f32, c_f32, c_i32, c_vp]),

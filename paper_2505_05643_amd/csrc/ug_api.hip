@@ -19,6 +19,7 @@ struct Layout {
   size_t rec_pair, racc, rgeo, rec_nkey, rec_koff, side;
   size_t tile_start, dsave, gq, hist;
   size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, partial;
+  size_t loss_part;
   size_t total;
 };
 
@@ -91,6 +92,7 @@ void compute_layout(ug_plan* pl) {
   L.rec_of_key = take(K * 4);
   L.srec = take(K * 4);
   L.partial = take(K * 32);
+  L.loss_part = take((size_t)bwd_prep_blocks(pl->prm.tile_w, pl->prm.tile_h, pl->num_tiles) * 4);
   L.total = o;
 }
 
@@ -434,13 +436,16 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
   return hip_status(e);
 }
 
-int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes,
-                              const float* image, const float* d_image, void* workspace, float* d_means,
-                              float* d_lraw, float* d_intensity, float* d_opacity, int32_t accumulate,
-                              void* stream) {
+namespace {
+
+// The backward passes; with target (mse), dL/dc_hat is formed from it in the
+// first kernel and the loss goes to loss_dev (if not null).
+int backward_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes, const float* image,
+                  const float* second, bool mse, float* loss_dev, void* workspace, float* d_means, float* d_lraw,
+                  float* d_intensity, float* d_opacity, int32_t accumulate, void* stream) {
   const int st = check_inputs(plan, g, planes, workspace);
   if (st != UG_OK) return st;
-  if (!image || !d_image) return UG_ERR_INVALID_ARG;
+  if (!image || !second) return UG_ERR_INVALID_ARG;
   if (plan->n > 0 && (!d_means || !d_lraw || !d_intensity || !d_opacity)) return UG_ERR_INVALID_ARG;
   if (accumulate != 0 && accumulate != 1) return UG_ERR_INVALID_ARG;
   if (plan->prm.flags & UG_FLAG_SCATTER) return UG_ERR_INVALID_ARG;  // no keys to walk
@@ -453,8 +458,10 @@ int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const 
   hipError_t e;
   {
     StageScope sc(plan, UG_STAGE_BWD_PREP, s);
-    e = launch_bwd_prep(plan->prm.tile_w, plan->prm.tile_h, plan->d_pint, plan->d_tile_plane, image, d_image,
-                        at<float>(ws, L.dsave), at<float>(ws, L.gq), plan->num_tiles, s);
+    const float scale = 2.0f / (float)(plan->num_pixels > 0 ? plan->num_pixels : 1);
+    e = launch_bwd_prep(plan->prm.tile_w, plan->prm.tile_h, plan->d_pint, plan->d_tile_plane, image, second, mse,
+                        scale, at<float>(ws, L.loss_part), at<float>(ws, L.dsave), at<float>(ws, L.gq),
+                        plan->num_tiles, s);
   }
   if (e != hipSuccess) return UG_ERR_HIP;
   {
@@ -473,9 +480,30 @@ int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const 
   }
   if (e != hipSuccess) return UG_ERR_HIP;
   StageScope sc(plan, UG_STAGE_GAUSS_GRAD, s);
+  const uint32_t nparts = bwd_prep_blocks(plan->prm.tile_w, plan->prm.tile_h, plan->num_tiles);
   e = launch_gauss_grad(*g, rp, ctrl, at<uint32_t>(ws, L.cnt_rec), at<unsigned long long>(ws, L.off_rec),
-                        at<float>(ws, L.side), d_means, d_lraw, d_intensity, d_opacity, accumulate, s);
+                        at<float>(ws, L.side), d_means, d_lraw, d_intensity, d_opacity, accumulate,
+                        at<float>(ws, L.loss_part), nparts,
+                        1.0 / (double)(plan->num_pixels > 0 ? plan->num_pixels : 1), mse ? loss_dev : nullptr, s);
   return hip_status(e);
+}
+
+}  // namespace
+
+int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes,
+                              const float* image, const float* d_image, void* workspace, float* d_means,
+                              float* d_lraw, float* d_intensity, float* d_opacity, int32_t accumulate,
+                              void* stream) {
+  return backward_impl(plan, g, planes, image, d_image, false, nullptr, workspace, d_means, d_lraw, d_intensity,
+                       d_opacity, accumulate, stream);
+}
+
+int ug_render_planes_backward_mse(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes,
+                                  const float* image, const float* target, void* workspace, float* d_means,
+                                  float* d_lraw, float* d_intensity, float* d_opacity, int32_t accumulate,
+                                  float* loss_dev, void* stream) {
+  return backward_impl(plan, g, planes, image, target, true, loss_dev, workspace, d_means, d_lraw, d_intensity,
+                       d_opacity, accumulate, stream);
 }
 
 int ug_plan_status(const ug_plan* plan, const void* workspace, int64_t* counts_host, void* stream) {

@@ -37,9 +37,12 @@ hipError_t launch_record_adjoint(const ug_gaussians& g, const PlaneConst* pc, co
                                  const float* partial, const uint32_t* cnt_rec, const unsigned long long* off_rec,
                                  float* side, float* d_means, float* d_lraw, float* d_int, float* d_op,
                                  int accumulate, hipStream_t s);
+// loss_out (may be null): the mean squared error, inv_m times the sum of the
+// nparts per-block sums in loss_part.
 hipError_t launch_gauss_grad(const ug_gaussians& g, const RenderParams& rp, const Ctrl* ctrl, const uint32_t* cnt_rec,
                              const unsigned long long* off_rec, const float* side, float* d_means, float* d_lraw,
-                             float* d_int, float* d_op, int accumulate, hipStream_t s);
+                             float* d_int, float* d_op, int accumulate, const float* loss_part, uint32_t nparts,
+                             double inv_m, float* loss_out, hipStream_t s);
 
 // ---- tile binning sort (ug_sort.hip)
 // Stable LSD radix sort of the key words on their low `bits` bits (the tile
@@ -109,9 +112,13 @@ hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneIn
                             const uint32_t* tile_start, const uint32_t* skey, const uint32_t* srec,
                             const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave, float bg_alpha,
                             float bg_color, uint32_t num_tiles, unsigned long long* n_eval, hipStream_t s);
+// second = dL/dc_hat, or (mse) the target with dL/dc_hat = scale (image -
+// target) formed inside and per-block squared-difference sums in loss_part
+// (bwd_prep_blocks floats).
+uint32_t bwd_prep_blocks(int tile_w, int tile_h, uint32_t num_tiles);
 hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const uint32_t* tile_plane,
-                           const float* image, const float* d_image, const float* dsave, float* gq,
-                           uint32_t num_tiles, hipStream_t s);
+                           const float* image, const float* second, bool mse, float scale, float* loss_part,
+                           const float* dsave, float* gq, uint32_t num_tiles, hipStream_t s);
 // tile_org[t] = pixel origin of tile t, x0 | y0 << 16.
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint32_t* tile_org,
                             const uint32_t* skey, const uint32_t* sval,

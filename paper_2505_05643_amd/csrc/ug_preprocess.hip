@@ -492,12 +492,28 @@ __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const Pl
 // and the sum of the wave pieces for one whose records span waves (the
 // first wave's last segment, whole middle waves, the last wave's first
 // segment); the others were written by k_record_adjoint.
+// With loss_out, block 0 also adds the backward prep's per-block squared
+// differences (nparts floats, in order, in FP64) into the mean squared error.
 __global__ __launch_bounds__(256) void k_gauss_grad(ug_gaussians g, RenderParams rp, const Ctrl* __restrict__ ctrl,
                                                     const uint32_t* __restrict__ cnt_rec,
                                                     const unsigned long long* __restrict__ off_rec,
                                                     const float* __restrict__ side, float* __restrict__ d_means,
                                                     float* __restrict__ d_lraw, float* __restrict__ d_int,
-                                                    float* __restrict__ d_op, int accumulate) {
+                                                    float* __restrict__ d_op, int accumulate,
+                                                    const float* __restrict__ loss_part, uint32_t nparts,
+                                                    double inv_m, float* __restrict__ loss_out) {
+  if (loss_out && blockIdx.x == 0) {  // uniform
+    __shared__ double s_l[256];
+    double a = 0.0;
+    for (uint32_t k = threadIdx.x; k < nparts; k += 256) a += (double)loss_part[k];
+    s_l[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) s_l[threadIdx.x] += s_l[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_out[0] = (float)(s_l[0] * inv_m);
+  }
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rp.n) return;
   const bool ok = (ctrl->flags & (kFlagRecCap | kFlagKeyCap)) == 0;
@@ -640,11 +656,13 @@ hipError_t launch_record_adjoint(const ug_gaussians& g, const PlaneConst* pc, co
 
 hipError_t launch_gauss_grad(const ug_gaussians& g, const RenderParams& rp, const Ctrl* ctrl, const uint32_t* cnt_rec,
                              const unsigned long long* off_rec, const float* side, float* d_means, float* d_lraw,
-                             float* d_int, float* d_op, int accumulate, hipStream_t s) {
-  const int blocks = (rp.n + 255) / 256;
+                             float* d_int, float* d_op, int accumulate, const float* loss_part, uint32_t nparts,
+                             double inv_m, float* loss_out, hipStream_t s) {
+  int blocks = (rp.n + 255) / 256;
+  if (loss_out && blocks < 1) blocks = 1;  // the loss is written even with no Gaussians
   if (blocks > 0)
     hipLaunchKernelGGL(k_gauss_grad, dim3(blocks), dim3(256), 0, s, g, rp, ctrl, cnt_rec, off_rec, side, d_means,
-                       d_lraw, d_int, d_op, accumulate);
+                       d_lraw, d_int, d_op, accumulate, loss_part, nparts, inv_m, loss_out);
   return hipGetLastError();
 }
 

@@ -175,48 +175,76 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
 // gamma * c_hat (zero outside the plane).  Four consecutive pixels of a tile
 // row per thread: 16-byte loads where the arrays (vec) and the plane row are
 // aligned and the row holds all four, single loads otherwise.
-template <int TW, int TH>
+//
+// MSE: the second array is the target and dL/dc_hat = scale (c_hat - target)
+// is formed here, with the same float operations as the separate gradient
+// kernel (so the same gamma bit for bit); each block also writes the sum of
+// its squared differences to loss_part[block] (a fixed-order reduction).
+template <int TW, int TH, bool MSE>
 __global__ __launch_bounds__(256) void k_bwd_prep(const PlaneInt* __restrict__ pint,
                                                   const uint32_t* __restrict__ tile_plane,
-                                                  const float* __restrict__ image, const float* __restrict__ d_image,
+                                                  const float* __restrict__ image, const float* __restrict__ second,
                                                   const float* __restrict__ dsave, float4* __restrict__ gq,
-                                                  uint32_t num_tiles, int vec) {
+                                                  uint32_t num_tiles, int vec, float scale,
+                                                  float* __restrict__ loss_part) {
   static_assert(TW % 4 == 0, "four pixels per thread within a tile row");
   const size_t gidx = (size_t)blockIdx.x * 256 + threadIdx.x;  // group of four pixels
   const uint32_t t = (uint32_t)(gidx / (TW * TH / 4));
-  if (t >= num_tiles) return;
-  const int j = (int)(gidx % (TW * TH / 4)) * 4;
-  const PlaneInt PI = pint[tile_plane[t]];
-  const uint32_t lt = t - PI.tile_off;
-  const int u = (int)(lt % (uint32_t)PI.ntx) * TW + j % TW;
-  const int v = (int)(lt / (uint32_t)PI.ntx) * TH + j / TW;
-  float gam[4] = {0.f, 0.f, 0.f, 0.f}, gc[4] = {0.f, 0.f, 0.f, 0.f};
-  if (v < PI.H && u < PI.W) {
-    const size_t idx = (((size_t)PI.pix_off_hi << 32) | PI.pix_off_lo) + (size_t)v * PI.W + u;
-    if (vec && u + 3 < PI.W && (idx & 3u) == 0) {
-      const float4 dI = *reinterpret_cast<const float4*>(d_image + idx);
-      const float4 Dt = *reinterpret_cast<const float4*>(dsave + idx);
-      const float4 I = *reinterpret_cast<const float4*>(image + idx);
-      gam[0] = dI.x / Dt.x;
-      gam[1] = dI.y / Dt.y;
-      gam[2] = dI.z / Dt.z;
-      gam[3] = dI.w / Dt.w;
-      gc[0] = gam[0] * I.x;
-      gc[1] = gam[1] * I.y;
-      gc[2] = gam[2] * I.z;
-      gc[3] = gam[3] * I.w;
-    } else {
+  float sq = 0.f;  // MSE: this thread's squared differences
+  if (t < num_tiles) {
+    const int j = (int)(gidx % (TW * TH / 4)) * 4;
+    const PlaneInt PI = pint[tile_plane[t]];
+    const uint32_t lt = t - PI.tile_off;
+    const int u = (int)(lt % (uint32_t)PI.ntx) * TW + j % TW;
+    const int v = (int)(lt / (uint32_t)PI.ntx) * TH + j / TW;
+    float gam[4] = {0.f, 0.f, 0.f, 0.f}, gc[4] = {0.f, 0.f, 0.f, 0.f};
+    if (v < PI.H && u < PI.W) {
+      const size_t idx = (((size_t)PI.pix_off_hi << 32) | PI.pix_off_lo) + (size_t)v * PI.W + u;
+      if (vec && u + 3 < PI.W && (idx & 3u) == 0) {
+        const float4 S2 = *reinterpret_cast<const float4*>(second + idx);
+        const float4 Dt = *reinterpret_cast<const float4*>(dsave + idx);
+        const float4 I = *reinterpret_cast<const float4*>(image + idx);
+        const float s2[4] = {S2.x, S2.y, S2.z, S2.w}, dt[4] = {Dt.x, Dt.y, Dt.z, Dt.w};
+        const float im[4] = {I.x, I.y, I.z, I.w};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (u + q < PI.W) {
-          gam[q] = d_image[idx + q] / dsave[idx + q];
-          gc[q] = gam[q] * image[idx + q];
+        for (int q = 0; q < 4; ++q) {
+          float dI = s2[q];
+          if constexpr (MSE) {
+            const float d = im[q] - s2[q];
+            dI = scale * d;
+            sq = fmaf(d, d, sq);
+          }
+          gam[q] = dI / dt[q];
+          gc[q] = gam[q] * im[q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (u + q < PI.W) {
+            const float im = image[idx + q];
+            float dI = second[idx + q];
+            if constexpr (MSE) {
+              const float d = im - dI;
+              dI = scale * d;
+              sq = fmaf(d, d, sq);
+            }
+            gam[q] = dI / dsave[idx + q];
+            gc[q] = gam[q] * im;
+          }
         }
       }
     }
+    gq[2 * gidx] = make_float4(gam[0], gc[0], gam[1], gc[1]);
+    gq[2 * gidx + 1] = make_float4(gam[2], gc[2], gam[3], gc[3]);
   }
-  gq[2 * gidx] = make_float4(gam[0], gc[0], gam[1], gc[1]);
-  gq[2 * gidx + 1] = make_float4(gam[2], gc[2], gam[3], gc[3]);
+  if constexpr (MSE) {
+    __shared__ float s_w[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+  }
 }
 
 // ---------------------------------------------------------------- backward
@@ -465,18 +493,26 @@ hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneIn
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const uint32_t* tile_plane,
-                           const float* image, const float* d_image, const float* dsave, float* gq,
-                           uint32_t num_tiles, hipStream_t s) {
+uint32_t bwd_prep_blocks(int tile_w, int tile_h, uint32_t num_tiles) {
   const size_t groups = (size_t)num_tiles * tile_w * tile_h / 4;  // four pixels per thread
-  const dim3 grid((unsigned)((groups + 255) / 256));
+  return (uint32_t)((groups + 255) / 256);
+}
+
+hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const uint32_t* tile_plane,
+                           const float* image, const float* second, bool mse, float scale, float* loss_part,
+                           const float* dsave, float* gq, uint32_t num_tiles, hipStream_t s) {
+  const dim3 grid(bwd_prep_blocks(tile_w, tile_h, num_tiles));
   float4* g4 = reinterpret_cast<float4*>(gq);
-  const int vec = (reinterpret_cast<uintptr_t>(image) | reinterpret_cast<uintptr_t>(d_image) |
+  const int vec = (reinterpret_cast<uintptr_t>(image) | reinterpret_cast<uintptr_t>(second) |
                    reinterpret_cast<uintptr_t>(dsave)) % 16 == 0;
 #define UG_PREP(W, H)                                                                                              \
   if (tile_w == W && tile_h == H) {                                                                                \
-    hipLaunchKernelGGL((k_bwd_prep<W, H>), grid, dim3(256), 0, s, pint, tile_plane, image, d_image, dsave, g4,     \
-                       num_tiles, vec);                                                                            \
+    if (mse)                                                                                                       \
+      hipLaunchKernelGGL((k_bwd_prep<W, H, true>), grid, dim3(256), 0, s, pint, tile_plane, image, second, dsave,  \
+                         g4, num_tiles, vec, scale, loss_part);                                                    \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_bwd_prep<W, H, false>), grid, dim3(256), 0, s, pint, tile_plane, image, second, dsave, \
+                         g4, num_tiles, vec, scale, loss_part);                                                    \
     return hipGetLastError();                                                                                      \
   }
   UG_TILE_SHAPES(UG_PREP)

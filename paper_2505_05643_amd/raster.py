@@ -195,6 +195,31 @@ class Plan:
               "ug_render_planes_backward")
         return grads
 
+    def backward_mse(self, g: GaussianTensors, planes: PlaneTensors, image: torch.Tensor, target: torch.Tensor,
+                     grads: GaussianTensors | None = None, accumulate: bool = False,
+                     loss_buf: torch.Tensor | None = None) -> GaussianTensors:
+        """Adjoint of the mean squared error against ``target`` (the gradient
+        of the MSE formed inside the first adjoint kernel); the loss goes to
+        loss_buf[0] if given (float32 device tensor)."""
+        cg, cp = _c_gauss(g), _c_planes(planes)
+        n = g.means.shape[0]
+        if grads is None:
+            dev = self.device
+            grads = GaussianTensors(torch.empty(n, 3, device=dev), torch.empty(n, 6, device=dev),
+                                    torch.empty(n, device=dev), torch.empty(n, device=dev))
+        target = target.contiguous()
+        if target.numel() != self.num_pixels or target.dtype != torch.float32:
+            raise ValueError("target must be float32 with num_pixels elements")
+        if loss_buf is not None and (loss_buf.dtype != torch.float32 or not loss_buf.is_cuda):
+            raise ValueError("loss_buf must be a float32 device tensor")
+        check(lib.ug_render_planes_backward_mse(self._h, ctypes.byref(cg), ctypes.byref(cp), image.data_ptr(),
+                                                target.data_ptr(), self._ws_ptr, grads.means.data_ptr(),
+                                                grads.lraw.data_ptr(), grads.intensity.data_ptr(),
+                                                grads.opacity.data_ptr(), 1 if accumulate else 0,
+                                                loss_buf.data_ptr() if loss_buf is not None else None, _stream()),
+              "ug_render_planes_backward_mse")
+        return grads
+
     def quality(self, image: torch.Tensor, ref: torch.Tensor, data_range: float = 1.0):
         """Per-plane (ssim, mse) float64 device tensors of ``image`` against
         ``ref`` (both packed like this plan's renders): mean SSIM over the

@@ -79,7 +79,6 @@ class TrainStep:
         self.m2 = R.GaussianTensors(*(z(t) for t in params))
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
         self.image = torch.empty(self.plan.num_pixels, device=dev)
-        self.d_image = torch.empty_like(self.image)
         self.loss_buf = torch.zeros(_lib.UG_MSE_SCRATCH_FLOATS, device=dev)
         self._reset_stats()
         self.graph = None
@@ -94,8 +93,7 @@ class TrainStep:
     def enqueue(self):
         """Enqueue one step on the current stream (no synchronisation)."""
         self.plan.render(self.params, self.planes, self.image, check_status=False)
-        R.mse_grad(self.image, self.target, self.d_image, self.loss_buf)
-        self.plan.backward(self.params, self.planes, self.image, self.d_image, self.grads)
+        self.plan.backward_mse(self.params, self.planes, self.image, self.target, self.grads, loss_buf=self.loss_buf)
         D.accumulate_grad_norm(self.grads.means, self.grad_acc, self.grad_cnt, self.plan)
         adam_gaussians(self.params, self.grads, self.m1, self.m2, self.adam, self.step_dev, self.plan)
 

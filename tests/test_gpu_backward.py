@@ -131,3 +131,55 @@ def test_accumulate_flag_and_autograd(R):
     plan.backward(gd, pd, img2, w, grads=g1, accumulate=True)
     for a, b in zip(leaves, g1):
         torch.testing.assert_close(b, 2 * a.grad, rtol=1e-6, atol=0)
+
+
+def test_fused_mse_backward_equals_separate(R):
+    """ug_render_planes_backward_mse: the gradients equal ug_mse_grad then
+    ug_render_planes_backward bit for bit (tile shapes, aligned and unaligned
+    arrays, ragged planes); the loss is the float64 mean squared error; with
+    no Gaussians the loss is still written."""
+    dev = torch.device("cuda", 0)
+    g = synth.make_gaussians(400, 61, (0, 0, 0), (1, 1, 1), (0.03, 0.15), aniso_max=6.0, opacity="random")
+    t = synth.make_gaussians(400, 62, (0, 0, 0), (1, 1, 1), (0.03, 0.15))
+    pl = synth.random_planes(3, 63, (40, 33), 1 / 36, 0.35, 0.65)
+    pl.wh[:] = [[41, 33], [8, 8], [57, 21]]
+    gd, td, pd = R.to_device(g, dev), R.to_device(t, dev), R.to_device(pl, dev)
+    for tile, off in (((16, 16), 0), ((16, 8), 1), ((32, 32), 0), ((8, 8), 3)):
+        params = R.Params(tile_w=tile[0], tile_h=tile[1])
+        tplan = R.Plan(t.n, pl.wh, params, device=dev)
+        tplan.fit(td, pd)
+        tgt_buf = torch.empty(tplan.num_pixels + off, device=dev)
+        target = tgt_buf[off:]
+        tplan.render(td, pd, target)
+        plan = R.Plan(g.n, pl.wh, params, device=dev)
+        plan.fit(gd, pd)
+        img_buf = torch.empty(plan.num_pixels + off, device=dev)
+        img = img_buf[off:]
+        plan.render(gd, pd, img)
+        d_image = torch.empty_like(img)
+        loss_a = torch.zeros(1026, device=dev)
+        R.mse_grad(img, target, d_image, loss_a)
+        ga = plan.backward(gd, pd, img, d_image)
+        loss_b = torch.full((4,), -1.0, device=dev)
+        gb = plan.backward_mse(gd, pd, img, target, loss_buf=loss_b)
+        torch.cuda.synchronize()
+        for a, b in zip(ga, gb):
+            assert torch.equal(a, b), (tile, off)
+        ref = float(np.mean((img.cpu().numpy().astype(np.float64) - target.cpu().numpy()) ** 2))
+        assert abs(float(loss_b[0]) - ref) <= 1e-6 * ref, (tile, off, float(loss_b[0]), ref)
+        assert abs(float(loss_a[0]) - ref) <= 1e-6 * ref
+        assert float(loss_b[1]) == -1.0  # only the first element is written
+        # accumulate = 1 adds the same gradients again
+        gc = plan.backward_mse(gd, pd, img, target, grads=R.GaussianTensors(*(x.clone() for x in gb)),
+                               accumulate=True)
+        for a, c in zip(gb, gc):
+            assert torch.allclose(c, 2 * a, rtol=1e-6, atol=0)
+    g0 = synth.make_gaussians(0, 1)
+    g0d = R.to_device(g0, dev)
+    plan = R.Plan(0, pl.wh, R.Params(), device=dev)
+    img = plan.render(g0d, pd)
+    target = torch.full_like(img, 0.25)
+    loss = torch.full((1,), -1.0, device=dev)
+    plan.backward_mse(g0d, pd, img, target, loss_buf=loss)
+    ref = float(np.mean((img.cpu().numpy().astype(np.float64) - 0.25) ** 2))
+    assert abs(float(loss[0]) - ref) <= 1e-6 * ref
