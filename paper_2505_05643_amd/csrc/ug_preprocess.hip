@@ -201,12 +201,18 @@ __global__ __launch_bounds__(256) void k_cull_write(RenderParams rp, int gpb, ui
                                                     unsigned long long* __restrict__ off_rec,
                                                     uint2* __restrict__ rec_pair, Ctrl* __restrict__ ctrl) {
   __shared__ unsigned long long s_sh[4];
-  unsigned long long carry = block_prefix(blk_tot, blockIdx.x * m, s_sh);
   const int nch = (rp.p + 63) / 64;
+  // the first round's counts and first acceptance word do not depend on the
+  // block prefix: load them before it so the two round trips overlap
+  const int gi0 = blockIdx.x * gpb + threadIdx.x;
+  const bool has0 = (int)threadIdx.x < gpb && gi0 < rp.n;
+  const unsigned long long cnt0 = has0 ? cnt_rec[gi0] : 0ull;
+  const unsigned long long bits0 = has0 ? accbits[(size_t)gi0 * nch] : 0ull;
+  unsigned long long carry = block_prefix(blk_tot, blockIdx.x * m, s_sh);
   for (int r0 = 0; r0 < gpb; r0 += 256) {
     const int gi = blockIdx.x * gpb + r0 + threadIdx.x;
     const bool has = r0 + (int)threadIdx.x < gpb && gi < rp.n;
-    const unsigned long long cnt = has ? cnt_rec[gi] : 0ull;
+    const unsigned long long cnt = r0 == 0 ? cnt0 : (has ? cnt_rec[gi] : 0ull);
     unsigned long long tot;
     const unsigned long long base = carry + block_exscan_256<unsigned long long>(cnt, s_sh, tot);
     carry += tot;
@@ -214,7 +220,7 @@ __global__ __launch_bounds__(256) void k_cull_write(RenderParams rp, int gpb, ui
     off_rec[gi] = base;
     unsigned long long r = base;
     for (int c = 0; c < nch; ++c) {
-      unsigned long long bits = accbits[(size_t)gi * nch + c];
+      unsigned long long bits = (r0 == 0 && c == 0) ? bits0 : accbits[(size_t)gi * nch + c];
       while (bits) {
         const int j = __builtin_ctzll(bits);
         bits &= bits - 1ull;
@@ -338,20 +344,42 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
   const uint32_t r_begin = blockIdx.x * rpb;
   if (r_begin >= nrec) return;  // uniform
   const uint32_t nact = (nrec + rpb - 1) / rpb;
-  unsigned long long carry = block_prefix(blk_tot, blockIdx.x, s_sh);
   const uint32_t r_end = min(r_begin + rpb, nrec);
+  // the first round's record data does not depend on the block prefix:
+  // issue its loads before the prefix so the two round trips overlap
+  uint32_t r = r_begin + threadIdx.x;
+  bool act = r < r_end;
+  uint32_t nk = 0u;
+  RecAcc ra{};
+  RecGeo ge{};
+  PlaneInt PI{};
+  if (act) {
+    nk = rec_nkey[r];
+    ra = racc[r];
+    ge = rgeo[r];
+    PI = pint[rec_pair[r].y];
+  }
+  unsigned long long carry = block_prefix(blk_tot, blockIdx.x, s_sh);
   for (uint32_t r0 = r_begin; r0 < r_end; r0 += 256) {
-    const uint32_t r = r0 + threadIdx.x;
-    const bool act = r < r_end;
-    const uint32_t nk = act ? rec_nkey[r] : 0u;
+    if (r0 != r_begin) {
+      r = r0 + threadIdx.x;
+      act = r < r_end;
+      nk = 0u;
+      if (act) {
+        nk = rec_nkey[r];
+        ra = racc[r];
+        ge = rgeo[r];
+        PI = pint[rec_pair[r].y];
+      }
+    }
     unsigned long long tot;
     const unsigned long long koff = carry + block_exscan_256<unsigned long long>(nk, s_sh, tot);
     carry += tot;
     if (act) {
       rec_koff[r] = (uint32_t)(koff < rp.key_cap ? koff : rp.key_cap);
       if (nk > 0 && koff + nk <= rp.key_cap)
-        emit_keys(racc[r], rgeo[r], pint[rec_pair[r].y], rp.box_mode, rp.tile_w, rp.tile_h, r, (uint32_t)koff,
-                  (uint32_t)(koff + nk), key_tile, rec_of_key);
+        emit_keys(ra, ge, PI, rp.box_mode, rp.tile_w, rp.tile_h, r, (uint32_t)koff, (uint32_t)(koff + nk), key_tile,
+                  rec_of_key);
     }
   }
   if (blockIdx.x == nact - 1 && threadIdx.x == 0) {
