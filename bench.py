@@ -39,7 +39,8 @@ METRIC = "fwd+bwd planes/s and Gaussian-pixel evals/s vs plain per-plane, at 1e-
 #            dT22 (3), du0 (1), dv0 (4)                                = 32
 FLOPS_PER_PAIR = {"accum": 16, "accum_bwd": 32}
 # Peak of the scalar (non-packed) FP32 vector ALU: 256 CUs x 4 SIMDs x 16
-# lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32 is not used by this build.
+# lanes x 2 flops (FMA) x 2.4 GHz.  The kernels are compiled without packed
+# FP32, so the packed 157.3 TFLOP/s figure does not apply.
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
@@ -102,7 +103,7 @@ def main():
                     help="finish with 5 elementwise copies (dst = -src) of MIB MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU (plane-sharded) path is a design, "
+        print("bench.py: runs on one GPU only; the multi-GPU (plane-sharded) path is a design, "
               "not an implementation. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
