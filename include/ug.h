@@ -272,6 +272,56 @@ int ug_adam_gaussians(const ug_plan *plan, const void *workspace, const ug_gauss
                       const ug_gaussians_mut *m2, const ug_adam_params *hp, int32_t *step_dev,
                       void *stream);
 
+/* ---- the training step as one HIP graph -------------------------------- */
+
+/* Captures one training step of Sec. 4.5 into a HIP graph held by the plan:
+ * ug_render_planes into image, ug_render_planes_backward_mse against target
+ * into grads (overwritten) and *loss_dev (may be NULL), optionally
+ * ug_accumulate_grad_norm into grad_acc / grad_cnt (both NULL or both
+ * given), and ug_adam_gaussians on params with m1, m2, adam and step_dev.
+ * Nothing runs at capture: the library captures on a stream of its own
+ * (default priority) and instantiates the graph; every pointer passed is
+ * baked into it, so the buffers must stay allocated and in place, and new
+ * contents (poses, targets) may be copied into them between replays.  The
+ * graph holds no memset or copy nodes (only kernels) and nothing in it
+ * allocates or synchronises.  A new capture replaces the previous one;
+ * ug_plan_reserve and ug_plan_destroy drop it.  Errors: UG_ERR_INVALID_ARG
+ * for NULL or inconsistent arguments, a plan with UG_FLAG_SCATTER (no
+ * backward) or stage profiling active (its events would be captured);
+ * UG_ERR_HIP if capture or instantiation fails. */
+int ug_step_capture(ug_plan *plan, const ug_gaussians_mut *params, const ug_planes *planes,
+                    const float *target, float *image, void *workspace, const ug_gaussians_mut *grads,
+                    const ug_gaussians_mut *m1, const ug_gaussians_mut *m2, const ug_adam_params *adam,
+                    int32_t *step_dev, float *loss_dev, float *grad_acc, int32_t *grad_cnt);
+
+/* Launches the captured step on stream (asynchronous; the device-side step
+ * counter advances the learning-rate schedule on every replay).
+ * UG_ERR_INVALID_ARG if nothing is captured. */
+int ug_step_replay(ug_plan *plan, void *stream);
+
+/* ---- test hook: the records of the last render -------------------------- */
+
+/* One accepted (Gaussian, plane) pair as the accumulate kernels see it: in
+ * pixel units, with du = u - ub - fu and dv = v - vb - fv,
+ *   t1 = t11 du + t12 dv,  t2 = t22 dv,  e = e0 - t1^2 - t2^2,
+ * and the pair adds weight 2^e (intensity c) to pixel (u, v) iff e >= emin
+ * (Eq. 8 restricted to the plane, base 2: e0 = log2 alpha - r^2 log2(e) / 2,
+ * emin = log2 alpha - chi^2 log2(e) / 2).  [tx0, tx1] x [ty0, ty1] is its
+ * tile rectangle (pixel rectangle under UG_FLAG_BOX_SUPPORT). */
+typedef struct {
+  int32_t gaussian, plane;
+  float t11, t12, t22, fu, fv, e0, emin, c;
+  int32_t ub, vb;
+  uint16_t tx0, tx1, ty0, ty1;
+} ug_record;
+
+/* Copies up to cap records of the last render (Gaussian-major, planes
+ * ascending) to host_out and returns their number (which may exceed cap),
+ * or a negative status.  Synchronises the stream.  For tests; not for use
+ * under graph capture. */
+int64_t ug_debug_records(const ug_plan *plan, const void *workspace, ug_record *host_out, int64_t cap,
+                         void *stream);
+
 /* ---- Densification and pruning between training steps.  Section 4.2
  * draws new means from a Gaussian through its triangular factor,
  * y = mu + L^-T z (back substitution with L^T, no general inverse); the

@@ -59,6 +59,13 @@ class UgAdamParams(ctypes.Structure):
                 ("beta1", c_f32), ("beta2", c_f32), ("eps", c_f32)]
 
 
+class UgRecord(ctypes.Structure):
+    _fields_ = [("gaussian", c_i32), ("plane", c_i32), ("t11", c_f32), ("t12", c_f32), ("t22", c_f32),
+                ("fu", c_f32), ("fv", c_f32), ("e0", c_f32), ("emin", c_f32), ("c", c_f32),
+                ("ub", c_i32), ("vb", c_i32), ("tx0", ctypes.c_uint16), ("tx1", ctypes.c_uint16),
+                ("ty0", ctypes.c_uint16), ("ty1", ctypes.c_uint16)]
+
+
 class UgDensifyParams(ctypes.Structure):
     _fields_ = [("beta", c_f32), ("min_opacity", c_f32), ("grad_thresh", c_f32), ("split_size", c_f32),
                 ("max_size", c_f32), ("split_factor", c_f32)]
@@ -97,6 +104,12 @@ SIGNATURES = {
     "ug_quality_workspace_bytes": (ctypes.c_size_t, [c_vp]),
     "ug_image_quality": (c_i32, [c_vp, c_vp, c_vp, c_f32, c_vp, c_vp, c_vp, c_vp]),
     "ug_param_eval": (c_i32, [c_i32, c_i32, c_vp, c_vp, c_vp, c_i64, c_f32, c_vp, c_vp, c_vp, c_vp]),
+    "ug_step_capture": (c_i32, [c_vp, ctypes.POINTER(UgGaussiansMut), ctypes.POINTER(UgPlanes), c_vp, c_vp, c_vp,
+                                ctypes.POINTER(UgGaussiansMut), ctypes.POINTER(UgGaussiansMut),
+                                ctypes.POINTER(UgGaussiansMut), ctypes.POINTER(UgAdamParams), c_vp, c_vp, c_vp,
+                                c_vp]),
+    "ug_step_replay": (c_i32, [c_vp, c_vp]),
+    "ug_debug_records": (c_i64, [c_vp, c_vp, ctypes.POINTER(UgRecord), c_i64, c_vp]),
     "ug_status_string": (ctypes.c_char_p, [c_i32]),
     "ug_plan_destroy": (None, [c_vp]),
 }

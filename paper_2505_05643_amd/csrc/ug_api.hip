@@ -49,6 +49,7 @@ struct ug_plan {
     std::vector<int> stage;      // cap
   };
   mutable Prof prof;
+  hipGraphExec_t step_exec = nullptr;  // the captured training step, if any
 };
 
 namespace {
@@ -354,6 +355,10 @@ int ug_plan_reserve(ug_plan* plan, int64_t record_capacity, int64_t key_capacity
   plan->key_cap = (uint32_t)key_capacity;
   plan->sort_blocks = sort_blocks_for(plan->key_cap);
   compute_layout(plan);
+  if (plan->step_exec) {  // its kernels were captured with the old layout
+    (void)hipGraphExecDestroy(plan->step_exec);
+    plan->step_exec = nullptr;
+  }
   return UG_OK;
 }
 
@@ -714,9 +719,113 @@ int ug_profile_read(ug_plan* plan, float* ms_host, int32_t* launches_host) {
   return st;
 }
 
+static_assert(sizeof(ug_record) == 56, "ug_record layout");
+
+int64_t ug_debug_records(const ug_plan* plan, const void* workspace, ug_record* host_out, int64_t cap,
+                         void* stream) {
+  if (!plan || !workspace || cap < 0 || (cap > 0 && !host_out)) return UG_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = plan->lay;
+  const char* ws = static_cast<const char*>(workspace);
+  Ctrl c;
+  if (hipMemcpyAsync(&c, ws + L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return UG_ERR_HIP;
+  const int64_t n = (int64_t)c.n_rec_eff;
+  const int64_t m = n < cap ? n : cap;
+  if (m > 0) {
+    std::vector<uint2> pair((size_t)m);
+    std::vector<RecAcc> acc((size_t)m);
+    std::vector<RecGeo> geo((size_t)m);
+    if (hipMemcpyAsync(pair.data(), ws + L.rec_pair, (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(acc.data(), ws + L.racc, (size_t)m * sizeof(RecAcc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(geo.data(), ws + L.rgeo, (size_t)m * sizeof(RecGeo), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return UG_ERR_HIP;
+    for (int64_t i = 0; i < m; ++i) {
+      ug_record& r = host_out[i];
+      r.gaussian = (int32_t)pair[(size_t)i].x;
+      r.plane = (int32_t)pair[(size_t)i].y;
+      const RecAcc& a = acc[(size_t)i];
+      r.t11 = a.t11;
+      r.t12 = a.t12;
+      r.t22 = a.t22;
+      r.fu = a.fu;
+      r.fv = a.fv;
+      r.e0 = a.e0;
+      r.emin = a.emin;
+      r.c = a.c;
+      const RecGeo& gg = geo[(size_t)i];
+      r.ub = gg.ub;
+      r.vb = gg.vb;
+      r.tx0 = gg.tx0;
+      r.tx1 = gg.tx1;
+      r.ty0 = gg.ty0;
+      r.ty1 = gg.ty1;
+    }
+  }
+  return n;
+}
+
+int ug_step_capture(ug_plan* plan, const ug_gaussians_mut* params, const ug_planes* planes, const float* target,
+                    float* image, void* workspace, const ug_gaussians_mut* grads, const ug_gaussians_mut* m1,
+                    const ug_gaussians_mut* m2, const ug_adam_params* adam, int32_t* step_dev, float* loss_dev,
+                    float* grad_acc, int32_t* grad_cnt) {
+  if (!plan || !params || !planes || !target || !image || !workspace || !grads || !m1 || !m2 || !adam ||
+      !step_dev)
+    return UG_ERR_INVALID_ARG;
+  if ((grad_acc == nullptr) != (grad_cnt == nullptr)) return UG_ERR_INVALID_ARG;
+  if (plan->prof.on) return UG_ERR_INVALID_ARG;  // the hooks' events would be captured
+  if (plan->prm.flags & UG_FLAG_SCATTER) return UG_ERR_INVALID_ARG;
+  const ug_gaussians g{params->means, params->lraw, params->intensity, params->opacity, params->n};
+  int st = check_inputs(plan, &g, planes, workspace);
+  if (st != UG_OK) return st;
+  int prev = 0;
+  if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(plan->device) != hipSuccess) return UG_ERR_HIP;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipSetDevice(prev);
+    return UG_ERR_HIP;
+  }
+  st = UG_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = UG_ERR_HIP;
+  if (st == UG_OK) {
+    st = ug_render_planes(plan, &g, planes, image, workspace, cs);
+    if (st == UG_OK)
+      st = ug_render_planes_backward_mse(plan, &g, planes, image, target, workspace, grads->means, grads->lraw,
+                                         grads->intensity, grads->opacity, 0, loss_dev, cs);
+    if (st == UG_OK && grad_acc)
+      st = ug_accumulate_grad_norm(plan, workspace, grads->means, g.n, grad_acc, grad_cnt, cs);
+    if (st == UG_OK) st = ug_adam_gaussians(plan, workspace, params, grads, m1, m2, adam, step_dev, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);  // always ends the capture
+    hipGraphExec_t exec = nullptr;
+    if (st == UG_OK && (ee != hipSuccess || !graph || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) !=
+                                                           hipSuccess))
+      st = UG_ERR_HIP;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st == UG_OK) {
+      if (plan->step_exec) (void)hipGraphExecDestroy(plan->step_exec);
+      plan->step_exec = exec;
+    } else if (exec) {
+      (void)hipGraphExecDestroy(exec);
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  (void)hipSetDevice(prev);
+  return st;
+}
+
+int ug_step_replay(ug_plan* plan, void* stream) {
+  if (!plan || !plan->step_exec) return UG_ERR_INVALID_ARG;
+  return hip_status(hipGraphLaunch(plan->step_exec, static_cast<hipStream_t>(stream)));
+}
+
 void ug_plan_destroy(ug_plan* plan) {
   if (!plan) return;
   prof_release(plan);
+  if (plan->step_exec) (void)hipGraphExecDestroy(plan->step_exec);
   if (plan->d_pint) (void)hipFree(plan->d_pint);
   if (plan->d_tile_plane) (void)hipFree(plan->d_tile_plane);
   if (plan->d_tile_org) (void)hipFree(plan->d_tile_org);

@@ -220,6 +220,18 @@ class Plan:
               "ug_render_planes_backward_mse")
         return grads
 
+    def debug_records(self) -> np.ndarray:
+        """The records of the last render as a numpy structured array (fields
+        of ug_record; synchronises).  A test hook."""
+        n = int(lib.ug_debug_records(self._h, self._ws_ptr, None, 0, _stream()))
+        if n < 0:
+            check(n, "ug_debug_records")
+        arr = (_lib.UgRecord * max(n, 1))()
+        got = int(lib.ug_debug_records(self._h, self._ws_ptr, arr, n, _stream()))
+        if got < 0:
+            check(got, "ug_debug_records")
+        return np.ctypeslib.as_array(arr)[:n].copy()
+
     def quality(self, image: torch.Tensor, ref: torch.Tensor, data_range: float = 1.0):
         """Per-plane (ssim, mse) float64 device tensors of ``image`` against
         ``ref`` (both packed like this plan's renders): mean SSIM over the

@@ -64,7 +64,9 @@ class TrainStep:
     poses or targets can be copied into them between steps)."""
 
     def __init__(self, params: R.GaussianTensors, planes: R.PlaneTensors, wh, target: torch.Tensor,
-                 render_params: R.Params | None = None, adam: AdamConfig | None = None, headroom: float = 1.5):
+                 render_params: R.Params | None = None, adam: AdamConfig | None = None, headroom: float = 1.5,
+                 native_graph: bool = False):
+        self.native = native_graph  # capture with ug_step_capture instead of torch's graph capture
         self.params = params
         self.planes = planes
         self.target = target
@@ -102,6 +104,17 @@ class TrainStep:
         """Capture one step as a hipGraph (the capture itself runs no step)."""
         self.graph = None
         torch.cuda.synchronize()
+        if self.native:
+            cp = R._c_planes(self.planes)
+            hp = self.adam.to_c()
+            p, gr, a, b = _mut(self.params), _mut(self.grads), _mut(self.m1), _mut(self.m2)
+            check(lib.ug_step_capture(self.plan._h, ctypes.byref(p), ctypes.byref(cp), self.target.data_ptr(),
+                                      self.image.data_ptr(), self.plan._ws_ptr, ctypes.byref(gr), ctypes.byref(a),
+                                      ctypes.byref(b), ctypes.byref(hp), self.step_dev.data_ptr(),
+                                      self.loss_buf.data_ptr(), self.grad_acc.data_ptr(), self.grad_cnt.data_ptr()),
+                  "ug_step_capture")
+            self.graph = "native"
+            return self.graph
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             self.enqueue()
@@ -111,7 +124,10 @@ class TrainStep:
     def replay(self):
         if self.graph is None:
             self.capture()
-        self.graph.replay()
+        if self.native:
+            check(lib.ug_step_replay(self.plan._h, R._stream()), "ug_step_replay")
+        else:
+            self.graph.replay()
 
     # ---------------------------------------------------------------- driver
     def run(self, steps: int, use_graph: bool = True, check_every: int = 1):

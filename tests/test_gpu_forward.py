@@ -227,3 +227,52 @@ def test_configs_sampled_pixels_box_support(R):
     flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
     st = check_image_box_support(img[flat], g, pl, plan.params, pix=pix)
     print("box support c1", st)
+
+
+def test_records_are_the_inplane_conic(R):
+    """ug_debug_records: every record's float conic against the float64
+    restriction of Eq. 8 to the plane (centre, 2x2 precision, offset r^2):
+    T^T T = log2(e)/2 diag(s) A diag(s) in pixel units, the centre at the
+    pixel coordinates of c, e0 and emin from r^2 and chi^2 (relative 1e-5)."""
+    import math
+
+    import oracle
+    from tests.parity import oracle_params
+    g = synth.make_gaussians(300, 71, (0, 0, 0), (1, 1, 1), (0.02, 0.12), aniso_max=8.0, opacity="random")
+    pl = synth.random_planes(3, 72, (8, 8), 1 / 40, 0.3, 0.7)
+    pl.wh[:] = [[37, 23], [48, 48], [50, 41]]
+    img, plan = _render(R, g, pl)
+    allrec = plan.debug_records()
+    n_rec = plan.status(counts=True)[1]
+    assert allrec.shape[0] == n_rec > 50
+    # a pair whose footprint misses the image keeps a zeroed record with an
+    # empty rectangle; the conic is compared on the others
+    on = (allrec["tx0"] <= allrec["tx1"]) & (allrec["ty0"] <= allrec["ty1"])
+    assert np.all(allrec["t11"][~on] == 0) and on.sum() > 50
+    rec = allrec[on]
+    op = oracle_params(plan.params)
+    cen, A, r2 = oracle.inplane_conic(g, pl, op)
+    k = 0.5 * math.log2(math.e)
+    alpha = oracle.sigmoid(g.opacity)
+    gi, pi = rec["gaussian"].astype(int), rec["plane"].astype(int)
+    assert np.all(np.diff(gi) >= 0)  # Gaussian-major
+    sx, sy = pl.spacing[pi, 0].astype(np.float64), pl.spacing[pi, 1].astype(np.float64)
+    W, H = pl.wh[pi, 0].astype(np.float64), pl.wh[pi, 1].astype(np.float64)
+    t11, t12, t22 = (rec[f].astype(np.float64) for f in ("t11", "t12", "t22"))
+    Ap = A[gi, pi]
+    want = np.stack([k * Ap[:, 0, 0] * sx * sx, k * Ap[:, 0, 1] * sx * sy, k * Ap[:, 1, 1] * sy * sy], axis=1)
+    got = np.stack([t11 * t11, t11 * t12, t12 * t12 + t22 * t22], axis=1)
+    scale = np.abs(want).max(axis=1, keepdims=True)
+    assert np.max(np.abs(got - want) / scale) <= 1e-5
+    cu = rec["ub"] + rec["fu"].astype(np.float64)
+    cv = rec["vb"] + rec["fv"].astype(np.float64)
+    np.testing.assert_allclose(cu, cen[gi, pi, 0] / sx + W / 2 - 0.5, rtol=0, atol=1e-4)
+    np.testing.assert_allclose(cv, cen[gi, pi, 1] / sy + H / 2 - 0.5, rtol=0, atol=1e-4)
+    la = np.log2(alpha[gi])
+    np.testing.assert_allclose(rec["e0"], la - k * r2[gi, pi], rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(rec["emin"], la - k * op.chi2, rtol=1e-5, atol=1e-5)
+    np.testing.assert_array_equal(rec["c"], g.intensity[gi])
+    # every pair whose plane meets the ellipsoid has a record (the float cull
+    # may add a few that narrowly miss, whose support is empty)
+    meets = set(zip(*np.nonzero(r2 <= op.chi2)))
+    assert meets <= set(zip(allrec["gaussian"].tolist(), allrec["plane"].tolist()))

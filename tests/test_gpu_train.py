@@ -116,6 +116,37 @@ def test_graph_replay_equals_eager_steps(M):
     assert la == lb
 
 
+def test_native_step_graph_equals_torch_graph_and_eager(M):
+    """ug_step_capture / ug_step_replay: each replay (with eager work between
+    them) leaves the same parameters, statistic and loss as the torch-captured
+    graph and the eager steps, bit for bit; a reserve drops the capture."""
+    R, S = M
+    gt, pt, wh, target = _problem(R, seed=97)
+    sets = [R.GaussianTensors(*(x.clone() for x in gt)) for _ in range(3)]
+    native = S.TrainStep(sets[0], pt, wh, target, native_graph=True)
+    graph = S.TrainStep(sets[1], pt, wh, target)
+    eager = S.TrainStep(sets[2], pt, wh, target)
+    for k in range(5):
+        native.replay()
+        graph.replay()
+        eager.enqueue()
+        junk = torch.randn(1000, device=pt.rot.device).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for x, y, z in zip(native.params, graph.params, eager.params):
+            assert torch.equal(x, y) and torch.equal(x, z), k
+        assert torch.equal(native.grad_acc, eager.grad_acc) and torch.equal(native.grad_cnt, eager.grad_cnt)
+        assert float(native.loss_buf[0]) == float(eager.loss_buf[0]) == float(graph.loss_buf[0])
+    assert native.step_count == 5 and native.plan.status() == 0
+    from paper_2505_05643_amd._lib import UgError
+    native.plan.reserve(native.plan.record_capacity + 64, native.plan.key_capacity)
+    with pytest.raises(UgError):
+        S.check(S.lib.ug_step_replay(native.plan._h, R._stream()), "ug_step_replay")
+    native.graph = None  # re-captured on the next replay, against the new layout
+    losses = native.run(3, check_every=1)
+    assert native.step_count == 8 and len(losses) == 3
+
+
 def test_training_reduces_loss(M):
     R, S = M
     gt, pt, wh, target = _problem(R, seed=91)
