@@ -1,4 +1,6 @@
 """Seeded workload generators: shapes, ranges and determinism (no method arithmetic)."""
+import math
+
 import numpy as np
 
 from paper_2505_05643_amd import synth
@@ -35,3 +37,58 @@ def test_sample_pixels_in_range():
     pix = synth.sample_pixels(pl, 1000, 7)
     assert pix.shape == (1000, 3)
     assert np.all(pix[:, 1] < pl.wh[pix[:, 0], 0]) and np.all(pix[:, 2] < pl.wh[pix[:, 0], 1])
+
+
+# ---------------------------------------------------------------- reconstruction and study inputs
+def test_volume_sweeps_frames_positions_and_jitter():
+    for view, normal in (("axial", (0, 0, 1)), ("coronal", (0, -1, 0)), ("sagittal", (1, 0, 0))):
+        pl = synth.volume_sweep(view, 8, 32)
+        R = pl.rot.astype(np.float64).reshape(-1, 3, 3)
+        assert np.allclose(np.einsum("pji,pjk->pik", R, R), np.eye(3), atol=1e-6)
+        assert np.allclose(np.linalg.det(R), 1.0, atol=1e-6)
+        assert np.allclose(R[:, :, 2], normal, atol=1e-7)
+        along = pl.origin.astype(np.float64) @ np.abs(np.asarray(normal, dtype=np.float64))
+        np.testing.assert_allclose(along, (np.arange(8) + 0.5) / 8, atol=1e-7)
+        off = pl.origin.astype(np.float64) - np.outer(along, np.abs(normal))
+        other = off + 0.5 * np.abs(np.asarray(normal, dtype=np.float64))
+        np.testing.assert_allclose(other, 0.5, atol=1e-7)  # centred in the other directions
+        assert np.all(pl.spacing == np.float32(1 / 32)) and np.all(pl.wh == 32)
+    a = synth.volume_sweep("axial", 50, 16, 5.0, 3)
+    b = synth.volume_sweep("axial", 50, 16, 5.0, 3)
+    assert np.array_equal(a.rot, b.rot)
+    n = a.rot.astype(np.float64).reshape(-1, 3, 3)[:, :, 2]
+    tilt = np.degrees(np.arccos(np.clip(n[:, 2], -1, 1)))
+    assert tilt.max() <= math.hypot(5.0, 5.0) + 1e-3 and tilt.max() > 2.0
+
+
+def test_phantom_structure():
+    g = synth.phantom_gaussians(2000, 9)
+    assert g.n == 2000 and np.all(np.isfinite(g.lraw))
+    r = np.array([0.38, 0.32, 0.42])
+    rad = np.linalg.norm((g.means.astype(np.float64) - 0.5) / r, axis=1)
+    shell, inner = rad[:1000], rad[1000:]
+    np.testing.assert_allclose(shell, 1.0, atol=1e-6)
+    assert inner.max() <= 0.85 + 1e-6
+    assert g.intensity[:1000].min() >= 0.7 and g.intensity[1000:].max() <= 0.6
+    assert np.array_equal(synth.phantom_gaussians(2000, 9).means, g.means)
+
+
+def test_paper_init_section_4_5():
+    g = synth.paper_init(5000, 4)
+    assert g.means.min() >= 0 and g.means.max() < 1
+    assert g.lraw.min() >= 4 and g.lraw.max() < 5
+    assert np.all(g.intensity == np.float32(0.5)) and np.all(g.opacity == np.float32(1.0))
+
+
+def test_param_study_inputs_shapes_and_distances():
+    d = synth.param_study_inputs(256, 5, 100.0)
+    for k in ("tri", "sym", "quat"):
+        assert d[k].shape == (256, 8) and d[k].dtype == np.float32 and np.all(d[k][:, 7] == 0)
+    assert np.all(d["tri"][:, 6:] == 0) and np.all(d["sym"][:, 6:] == 0)
+    np.testing.assert_allclose(np.linalg.norm(d["quat"][:, :4], axis=1), 1.0, atol=1e-6)
+    s = d["scales"]
+    np.testing.assert_allclose(s.max(axis=1) / s.min(axis=1), 100.0, rtol=1e-12)
+    # delta = R (s * w) with |w| in [0.5, 2.8]: its Mahalanobis length is |w|
+    w = np.einsum("nji,nj->ni", d["rots"], d["delta"].astype(np.float64)) / s
+    length = np.linalg.norm(w, axis=1)
+    assert length.min() >= 0.5 - 1e-3 and length.max() <= 2.8 + 1e-3
