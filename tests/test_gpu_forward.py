@@ -276,3 +276,33 @@ def test_records_are_the_inplane_conic(R):
     # may add a few that narrowly miss, whose support is empty)
     meets = set(zip(*np.nonzero(r2 <= op.chi2)))
     assert meets <= set(zip(allrec["gaussian"].tolist(), allrec["plane"].tolist()))
+
+
+def test_widest_planes_gather_and_box_support(R):
+    """Planes at the widest size the plan accepts (32,767 pixels): the
+    16-bit tile and pixel rectangles and the pixel offsets near their
+    limits, for the gather (every binning) and the box-support scatter."""
+    from paper_2505_05643_amd._lib import UG_FLAG_BOX_SUPPORT, UG_FLAG_SCATTER
+    from tests.parity import check_image_box_support
+    W = 32767
+    frames = [np.eye(3), synth.axis_angle((1, 0, 0), 0.3)]
+    pl = synth.pack_planes(frames, [(0.5, 0.5, 0.5), (0.5, 0.5, 0.52)], [(1.0 / 8192, 1.0 / 256)] * 2,
+                           [(W, 3), (W, 5)])
+    rng = np.random.default_rng(81)
+    g = synth.make_gaussians(120, 82, (0.0, 0.49, 0.45), (1.0, 0.51, 0.55), (0.001, 0.01), opacity="random")
+    # a few Gaussians right at the far end of the planes
+    # (pixel u sits at x = 0.5 + (u + 1/2 - W/2) / 8192: x in [-1.5, 2.5])
+    g.means[:6, 0] = (2.47 + 0.02 * rng.random(6)).astype(np.float32)
+    g.means[:6, 1] = (0.5 + 0.002 * rng.standard_normal(6)).astype(np.float32)   # on the tilted plane
+    g.means[:6, 2] = (0.52 + 0.002 * rng.standard_normal(6)).astype(np.float32)
+    pix = np.concatenate([np.stack([np.zeros(300, int), rng.integers(12000, 20600, 300), rng.integers(0, 3, 300)], 1),
+                          np.stack([np.zeros(100, int), rng.integers(0, W, 100), rng.integers(0, 3, 100)], 1),
+                          np.stack([np.ones(400, int), rng.integers(W - 400, W, 400), rng.integers(0, 5, 400)], 1)])
+    offs = pl.pixel_offsets()
+    flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
+    for bm in (0, 1, 2):
+        img, plan = _render(R, g, pl, R.Params(box_mode=bm))
+        check_image(img[flat], g, pl, plan.params, pix=pix)
+    img, plan = _render(R, g, pl, R.Params(flags=UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT))
+    check_image_box_support(img[flat], g, pl, plan.params, pix=pix)
+    assert img.shape[0] == W * 8
