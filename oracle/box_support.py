@@ -48,7 +48,6 @@ def render_box_support(g, planes, params: Params | None = None, pix=None, tol: f
     number per pixel (k > max_k gives an unbounded interval)."""
     params = params or Params()
     mu, L, c, alpha = _unpack(g, params)
-    bmin, bmax = box_eq13(g, planes, params)
     if pix is None:
         sel = []
         for p in range(planes.p):
@@ -61,14 +60,16 @@ def render_box_support(g, planes, params: Params | None = None, pix=None, tol: f
     out, den = np.empty(M), np.empty(M)
     lo, hi = np.empty(M), np.empty(M)
     kk = np.zeros(M, dtype=np.int64)
-    for p in np.unique(pix[:, 0]):
-        p = int(p)
+    # boxes only for the planes sampled (the same arithmetic per plane)
+    used = [int(p) for p in np.unique(pix[:, 0])]
+    bmin_u, bmax_u = box_eq13(g, planes.subset(used), params)
+    for ui, p in enumerate(used):
         rows = np.nonzero(pix[:, 0] == p)[0]
         R = np.asarray(planes.rot[p], dtype=np.float64).reshape(3, 3)
         o = np.asarray(planes.origin[p], dtype=np.float64)
         W, H = float(planes.wh[p, 0]), float(planes.wh[p, 1])
         sx, sy = (float(s) for s in planes.spacing[p])
-        b0, b1 = bmin[:, p], bmax[:, p]
+        b0, b1 = bmin_u[:, ui], bmax_u[:, ui]
         # Phase 1 (step 2), with its borderline band (chi^2 = inf: unbounded
         # boxes, never borderline)
         acc = (b0[:, 2] <= 0.0) & (b1[:, 2] >= 0.0)

@@ -215,18 +215,27 @@ def test_paper_phase2_box_support(R):
         plan.backward(gd, pd, torch.from_numpy(img).to(dev), torch.zeros(plan.num_pixels, device=dev))
 
 
-def test_configs_sampled_pixels_box_support(R):
-    """The box-support Phase 2 on the full c1 workload (50k Gaussians, 16
-    planes of 160^2): a seeded sample of pixels against the reference."""
+@pytest.mark.parametrize("k", [1, 4])
+def test_configs_sampled_pixels_box_support(R, k):
+    """The box-support Phase 2 on full workloads (c1: 50k Gaussians, 16
+    planes of 160^2, 1500 pixels over all planes; c4: 1M Gaussians, 256
+    planes of 256^2, 300 pixels over three planes, which keeps the
+    reference's boxes to those planes): seeded pixels against the
+    reference."""
     from paper_2505_05643_amd._lib import UG_FLAG_BOX_SUPPORT, UG_FLAG_SCATTER
     from tests.parity import check_image_box_support
-    g, pl, _ = synth.make_config(1)
+    g, pl, _ = synth.make_config(k)
     img, plan = _render(R, g, pl, R.Params(flags=UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT))
-    pix = synth.sample_pixels(pl, 1500, 801)
+    if k == 1:
+        pix = synth.sample_pixels(pl, 1500, 801)
+    else:
+        planes = np.random.default_rng(5).choice(pl.p, 3, replace=False)
+        pix = synth.sample_pixels(pl.subset(planes), 300, 804)
+        pix[:, 0] = planes[pix[:, 0]]
     offs = pl.pixel_offsets()
     flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
     st = check_image_box_support(img[flat], g, pl, plan.params, pix=pix)
-    print("box support c1", st)
+    print(f"box support c{k}", st)
 
 
 def test_records_are_the_inplane_conic(R):
