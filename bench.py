@@ -437,8 +437,8 @@ def reconstruction(dev, steps):
     cases = [recon.run_case(setup, c, dev, scorer=scorer) for c in recon.CASES]
     # the scoring kernel alone over all evaluation slices: it reads two
     # float32 images (8 B per pixel); its FP64 window sums bound it (row
-    # pass 10 flop per tap x 11 taps x 18/8 rows per pixel, column pass
-    # 5 x 2 flop x 11 taps, the score about 20: about 380 flop per pixel)
+    # pass 10 flop per tap x 11 taps, once per row; column pass 5 x 2 flop
+    # x 11 taps; the score about 20: about 240 flop per pixel)
     img = scorer.images(R.to_device(synth.paper_init(setup.n_model, 6000), dev))
     q_ms = scorer.quality_ms(img)
     npx = img.numel()
@@ -447,7 +447,7 @@ def reconstruction(dev, steps):
             "cases": cases,
             "quality_kernel": {"ms": q_ms, "pixels": npx, "gpix_per_s": npx / (q_ms * 1e6),
                                "hbm_gbs": 8 * npx / (q_ms * 1e6),
-                               "fp64_tflops": 380 * npx / (q_ms * 1e9)}}
+                               "fp64_tflops": 240 * npx / (q_ms * 1e9)}}
 
 
 def densify_ms(R, gd, dev, warmup, steps):

@@ -50,6 +50,7 @@ struct ug_plan {
   };
   mutable Prof prof;
   hipGraphExec_t step_exec = nullptr;  // the captured training step, if any
+  int32_t max_w = 0;                   // widest plane (pixels)
 };
 
 namespace {
@@ -282,10 +283,12 @@ int ug_plan_create(int32_t n, int32_t p, const int32_t* wh_host, const ug_params
   const int TW = params->tile_w, TH = params->tile_h;
   std::vector<PlaneInt> pint((size_t)p);
   uint64_t tiles = 0, pix = 0;
+  int32_t max_w = 0;
   for (int32_t i = 0; i < p; ++i) {
     const int32_t W = wh_host[2 * i], H = wh_host[2 * i + 1];
     if (W < 1 || H < 1 || W > 32767 || H > 32767) return UG_ERR_INVALID_ARG;
     PlaneInt& q = pint[(size_t)i];
+    max_w = W > max_w ? W : max_w;
     q.W = W;
     q.H = H;
     q.ntx = (W + TW - 1) / TW;
@@ -311,6 +314,7 @@ int ug_plan_create(int32_t n, int32_t p, const int32_t* wh_host, const ug_params
   if (!pl) return UG_ERR_HIP;
   pl->n = n;
   pl->p = p;
+  pl->max_w = max_w;
   pl->prm = *params;
   pl->ppl = params->px_per_lane ? params->px_per_lane : accum_default_ppl(TW, TH);
   pl->num_tiles = (uint32_t)tiles;
@@ -621,9 +625,7 @@ int ug_densify(const ug_gaussians* g, const float* acc, const int32_t* cnt, cons
 }
 
 size_t ug_quality_workspace_bytes(const ug_plan* plan) {
-  return plan ? align_up((size_t)plan->num_tiles * quality_subs(plan->prm.tile_w, plan->prm.tile_h) *
-                         sizeof(double2))
-              : 0;
+  return plan ? align_up((size_t)plan->p * quality_strips(plan->max_w) * sizeof(double2)) : 0;
 }
 
 int ug_image_quality(const ug_plan* plan, const float* image, const float* ref, float data_range, double* ssim,
@@ -642,8 +644,7 @@ int ug_image_quality(const ug_plan* plan, const float* image, const float* ref, 
   const double L = (double)data_range;
   q.c1 = (0.01 * L) * (0.01 * L);
   q.c2 = (0.03 * L) * (0.03 * L);
-  return hip_status(launch_quality(plan->d_pint, plan->d_tile_plane, plan->d_tile_org, plan->num_tiles, plan->p,
-                                   plan->prm.tile_w, plan->prm.tile_h, image, ref, q,
+  return hip_status(launch_quality(plan->d_pint, plan->p, quality_strips(plan->max_w), image, ref, q,
                                    static_cast<double2*>(workspace), ssim, mse, static_cast<hipStream_t>(stream)));
 }
 

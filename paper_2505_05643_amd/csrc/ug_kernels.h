@@ -96,9 +96,9 @@ struct QualityConst {
   double taps[11];  // normalised 1D Gaussian window
   double c1, c2;
 };
-uint32_t quality_subs(int tile_w, int tile_h);  // 8 x 8 sub-blocks per tile
-hipError_t launch_quality(const PlaneInt* pint, const uint32_t* tile_plane, const uint32_t* tile_org,
-                          uint32_t num_tiles, int32_t p, int tile_w, int tile_h, const float* img, const float* ref,
+uint32_t quality_strips(int32_t max_width);  // 8-pixel column strips of the widest plane
+// part: p x max_strips double2 of workspace
+hipError_t launch_quality(const PlaneInt* pint, int32_t p, uint32_t max_strips, const float* img, const float* ref,
                           const QualityConst& q, double2* part, double* ssim, double* mse, hipStream_t s);
 
 // ---- covariance parameterisation study (ug_params.hip)

@@ -284,7 +284,9 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        # at interpreter exit the module's globals may already be gone: the
+        # process is ending and the driver frees the device memory
+        if h is not None and h.value and lib is not None:
             lib.ug_plan_destroy(h)
             self._h = None
 
