@@ -100,3 +100,26 @@ def test_entry_points_reject_null_arguments(L):
     assert L.lib.ug_mse_grad(None, None, 10, None, None, None) == L.UG_ERR_INVALID_ARG
     assert L.lib.ug_adam_step(None, None, None, None, 10, 0.1, 0.9, 0.999, 1e-8, 1, None) == L.UG_ERR_INVALID_ARG
     L.lib.ug_plan_destroy(None)
+
+
+def test_newer_entry_points_reject_invalid_arguments(L):
+    """Host-side validation of the fused adjoint, the captured step, the
+    record hook, the scoring call and the parameterisation study (no device
+    work happens)."""
+    g = L.UgGaussians(None, None, None, None, 0)
+    pl = L.UgPlanes(None, None, None, 1)
+    gm = L.UgGaussiansMut(None, None, None, None, 0)
+    hp = L.UgAdamParams(1e-4, 1e-6, 10, 0.05, 0.9, 0.999, 1e-8)
+    bad = L.UG_ERR_INVALID_ARG
+    assert L.lib.ug_render_planes_backward_mse(None, ctypes.byref(g), ctypes.byref(pl), None, None, None, None,
+                                               None, None, None, 0, None, None) == bad
+    assert L.lib.ug_step_capture(None, ctypes.byref(gm), ctypes.byref(pl), None, None, None, ctypes.byref(gm),
+                                 ctypes.byref(gm), ctypes.byref(gm), ctypes.byref(hp), None, None, None, None) == bad
+    assert L.lib.ug_step_replay(None, None) == bad
+    assert L.lib.ug_debug_records(None, None, None, 0, None) == bad
+    assert L.lib.ug_image_quality(None, None, None, 1.0, None, None, None, None) == bad
+    assert L.lib.ug_quality_workspace_bytes(None) == 0
+    for kind, fp64, n in ((7, 0, 1), (0, 2, 1), (0, 0, -1)):
+        assert L.lib.ug_param_eval(kind, fp64, None, None, None, n, 1e-4, None, None, None, None) == bad
+    assert L.lib.ug_param_eval(L.UG_PARAM_TRI, 0, None, None, None, 5, 1e-4, None, None, None, None) == bad
+    assert L.lib.ug_param_eval(L.UG_PARAM_QUAT, 1, None, None, None, 0, 1e-4, None, None, None, None) == L.UG_OK
