@@ -322,6 +322,28 @@ typedef struct {
 int64_t ug_debug_records(const ug_plan *plan, const void *workspace, ug_record *host_out, int64_t cap,
                          void *stream);
 
+/* ---- test hook: the tile binning of the last render ---------------------- */
+
+/* Copies the keys of the last gather render as the radix sort left them
+ * (Section 4.4 binning: one key per (record, touched tile), sorted by tile
+ * id, stably, so a tile's keys keep the order in which they were emitted)
+ * and the tile ranges derived from them:
+ *   key_out[j]   key word: the tile id in its low 32 - Q bits, the tile's
+ *                8 x 8 sub-block coverage mask in its top Q bits
+ *                (Q = (tile_w / 8) (tile_h / 8); bit b = sub-block
+ *                (b % (tile_w / 8), b / (tile_w / 8)));
+ *   eidx_out[j]  position of key j in the emitted (unsorted) order;
+ *   rec_out[j]   record index (as ug_debug_records numbers them);
+ *   ranges_out   num_tiles + 1 entries: tile t's keys are [ranges_out[t],
+ *                ranges_out[t + 1]).
+ * Any of the four host pointers may be null (not copied); at most cap keys
+ * are copied.  Returns the number of keys (which may exceed cap), or a
+ * negative status (UG_ERR_INVALID_ARG for a scatter plan, which has no
+ * keys).  Synchronises the stream.  For tests; not for use under graph
+ * capture. */
+int64_t ug_debug_keys(const ug_plan *plan, const void *workspace, uint32_t *key_out, uint32_t *eidx_out,
+                      uint32_t *rec_out, uint32_t *ranges_out, int64_t cap, void *stream);
+
 /* ---- Densification and pruning between training steps.  Section 4.2
  * draws new means from a Gaussian through its triangular factor,
  * y = mu + L^-T z (back substitution with L^T, no general inverse); the
@@ -432,6 +454,30 @@ int ug_image_quality(const ug_plan *plan, const float *image, const float *ref, 
  * kind, n < 0 or a NULL pointer with n > 0.  No synchronisation. */
 int ug_param_eval(int32_t kind, int32_t fp64, const float *raw, const float *z, const float *delta, int64_t n,
                   float beta, void *sigma, void *draw, void *d2, void *stream);
+
+/* ---- Throughput probes (measurement only) --------------------------------
+ * The rates behind the roofline fractions the benchmark reports, measured
+ * on the device the library runs on:
+ *   UG_PROBE_FMA    8 independent FMA chains per thread, iters steps each
+ *                   (2 flop per FMA: 16 x iters x 256 x blocks flop);
+ *   UG_PROBE_EXP    8 chains of v_exp_f32 per thread (8 x iters x 256 x
+ *                   blocks transcendentals);
+ *   UG_PROBE_PAIRS  the forward accumulate's evaluation of one (record,
+ *                   pixel) pair (two FMAs, the cut-off compare, exp2, two
+ *                   sums) on registers only, 8 pairs per thread and step;
+ *   UG_PROBE_COPY   dst = src over n floats (n a multiple of 4, both 16-byte
+ *                   aligned), a grid-stride loop of blocks x 256 threads.
+ * For the first three, dst receives one float per thread (n >= blocks x
+ * 256) and src is unused.  Device pointers, caller-owned.  Times the launch
+ * with two events on stream, synchronises, and stores its milliseconds in
+ * *ms_host.  UG_ERR_INVALID_ARG for an unknown kind, blocks outside
+ * [1, 2^20], iters < 1 or a buffer too small or misaligned. */
+#define UG_PROBE_FMA 0
+#define UG_PROBE_EXP 1
+#define UG_PROBE_PAIRS 2
+#define UG_PROBE_COPY 3
+int ug_probe(int32_t kind, int32_t blocks, int32_t iters, const float *src, float *dst, int64_t n, float *ms_host,
+             void *stream);
 
 /* Human-readable text for a status code (static storage). */
 const char *ug_status_string(int status);

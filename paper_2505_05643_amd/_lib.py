@@ -28,6 +28,7 @@ UG_FLAG_COUNT_EVALS = 1
 UG_FLAG_SCATTER = 2
 UG_FLAG_BOX_SUPPORT = 4
 UG_PARAM_TRI, UG_PARAM_SYM, UG_PARAM_QUAT = 0, 1, 2
+UG_PROBE_FMA, UG_PROBE_EXP, UG_PROBE_PAIRS, UG_PROBE_COPY = 0, 1, 2, 3
 
 STAGES = ("setup", "cull_count", "cull_write", "record", "emit", "sort_hist", "sort_scan", "sort_scatter", "ranges",
           "accum", "bwd_prep", "accum_bwd", "record_adj", "gauss_grad", "scatter")
@@ -110,6 +111,8 @@ SIGNATURES = {
                                 c_vp]),
     "ug_step_replay": (c_i32, [c_vp, c_vp]),
     "ug_debug_records": (c_i64, [c_vp, c_vp, ctypes.POINTER(UgRecord), c_i64, c_vp]),
+    "ug_debug_keys": (c_i64, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]),
+    "ug_probe": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_vp, c_i64, ctypes.POINTER(c_f32), c_vp]),
     "ug_status_string": (ctypes.c_char_p, [c_i32]),
     "ug_plan_destroy": (None, [c_vp]),
 }

@@ -2,10 +2,12 @@
 
 Searches tile shape, pixels per lane, LDS batch and binning box for a given
 workload by timing the library's own forward + backward on the device, and
-checks that every candidate renders the same image: bit for bit within a
-tile shape; across shapes the tile-relative FP32 coordinates round
-differently, so to 2e-5 of the peak (a fifth of the parity tolerance) except
-for rare pixels whose pair sits on the cut-off.  Results can be cached per
+checks that every candidate renders the same image and back-propagates the
+same gradients: bit for bit within a tile shape; across shapes the
+tile-relative FP32 coordinates round differently, so images to 2e-5 of the
+peak (a fifth of the parity tolerance) except for rare pixels whose pair
+sits on the cut-off, and each gradient tensor to GRAD_REL of its largest
+entry (a hundredth of the parity tolerance).  Results can be cached per
 workload signature in a JSON file.
 """
 from __future__ import annotations
@@ -24,6 +26,7 @@ SHAPES = ((8, 8, 1), (16, 8, 2), (8, 16, 1), (16, 16, 2), (32, 8, 4), (32, 16, 4
 BATCHES = (32, 64, 128, 256)
 BOXES = (R._lib.UG_BOX_PAPER, R._lib.UG_BOX_CONIC, R._lib.UG_BOX_ROWS)
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+GRAD_REL = 1e-5
 
 
 def signature(n: int, wh) -> str:
@@ -53,7 +56,7 @@ def _time_candidate(params: R.Params, g, planes, wh, d_image, steps: int):
         plan.backward(g, planes, img, d_image, grads)
     t1.record()
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1) / steps, img.clone(), plan.status(counts=True)
+    return t0.elapsed_time(t1) / steps, img.clone(), plan.status(counts=True), [t.clone() for t in grads]
 
 
 def tune(g: R.GaussianTensors, planes: R.PlaneTensors, wh, base: R.Params | None = None, steps: int = 5,
@@ -66,12 +69,13 @@ def tune(g: R.GaussianTensors, planes: R.PlaneTensors, wh, base: R.Params | None
     d_image = torch.from_numpy(rng.standard_normal(npx).astype(np.float32)).to(g.means.device)
     results = []
     ref_img = {}
+    ref_grad = {}
     peak = None
 
     def run(tw, th, ppl, bg, box):
         nonlocal peak
         prm = dataclasses.replace(base, tile_w=tw, tile_h=th, px_per_lane=ppl, lds_batch=bg, box_mode=box)
-        ms, img, st = _time_candidate(prm, g, planes, wh, d_image, steps)
+        ms, img, st, grads = _time_candidate(prm, g, planes, wh, d_image, steps)
         if peak is None:
             peak = float(img.abs().max())
         key = (tw, th)
@@ -79,8 +83,18 @@ def tune(g: R.GaussianTensors, planes: R.PlaneTensors, wh, base: R.Params | None
         if key in ref_img:
             if not torch.equal(img, ref_img[key]):
                 raise RuntimeError(f"candidate {prm} renders a different image than its tile shape's first")
+            if not all(torch.equal(a, b) for a, b in zip(grads, ref_grad[key])):
+                raise RuntimeError(f"candidate {prm}: gradients differ from its tile shape's first")
         else:
             ref_img[key] = img
+            ref_grad[key] = grads
+            first_g = next(iter(ref_grad.values()))
+            for name, a, b in zip(("means", "lraw", "intensity", "opacity"), grads, first_g):
+                scale = float(b.abs().max())
+                err = float((a - b).abs().max()) / max(scale, 1e-30)
+                if err > GRAD_REL:
+                    raise RuntimeError(f"candidate {prm}: gradient {name} differs from the first tile shape's by "
+                                       f"{err:.3e} of its largest entry")
             first = next(iter(ref_img.values()))
             # Pixels with a pair on the cut-off (d^2 = chi^2 to rounding) may
             # legitimately flip between shapes; they must stay rare.

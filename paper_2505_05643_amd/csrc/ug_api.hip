@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "ug_kernels.h"
@@ -658,6 +659,31 @@ int ug_param_eval(int32_t kind, int32_t fp64, const float* raw, const float* z, 
                                       static_cast<hipStream_t>(stream)));
 }
 
+int ug_probe(int32_t kind, int32_t blocks, int32_t iters, const float* src, float* dst, int64_t n, float* ms_host,
+             void* stream) {
+  if (kind < UG_PROBE_FMA || kind > UG_PROBE_COPY || blocks < 1 || blocks > (1 << 20) || iters < 1 || !dst ||
+      !ms_host || n < 0)
+    return UG_ERR_INVALID_ARG;
+  if (kind == UG_PROBE_COPY) {
+    if (!src || n % 4 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+      return UG_ERR_INVALID_ARG;
+  } else if (n < (int64_t)blocks * 256) {
+    return UG_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int st = UG_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = UG_ERR_HIP;
+  if (st == UG_OK && (hipEventRecord(e0, s) != hipSuccess || launch_probe(kind, blocks, iters, src, dst, n, s) !=
+                                                                   hipSuccess ||
+                      hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                      hipEventElapsedTime(ms_host, e0, e1) != hipSuccess))
+    st = UG_ERR_HIP;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return st;
+}
+
 const char* ug_status_string(int status) {
   switch (status) {
     case UG_OK: return "ok";
@@ -766,6 +792,33 @@ int64_t ug_debug_records(const ug_plan* plan, const void* workspace, ug_record* 
       r.ty1 = gg.ty1;
     }
   }
+  return n;
+}
+
+int64_t ug_debug_keys(const ug_plan* plan, const void* workspace, uint32_t* key_out, uint32_t* eidx_out,
+                      uint32_t* rec_out, uint32_t* ranges_out, int64_t cap, void* stream) {
+  if (!plan || !workspace || cap < 0) return UG_ERR_INVALID_ARG;
+  if (plan->prm.flags & UG_FLAG_SCATTER) return UG_ERR_INVALID_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Layout& L = plan->lay;
+  void* ws = const_cast<void*>(workspace);
+  Ctrl c;
+  if (hipMemcpyAsync(&c, at<Ctrl>(ws, L.ctrl), sizeof(Ctrl), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return UG_ERR_HIP;
+  const int64_t n = (int64_t)c.n_key_eff;
+  const int64_t m = n < cap ? n : cap;
+  const Sorted so = sorted_set(plan, ws);
+  const std::pair<uint32_t*, const uint32_t*> arrays[3] = {{key_out, so.key}, {eidx_out, so.val}, {rec_out, so.rec}};
+  for (const auto& a : arrays) {
+    if (a.first && m > 0 &&
+        hipMemcpyAsync(a.first, a.second, (size_t)m * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return UG_ERR_HIP;
+  }
+  if (ranges_out && hipMemcpyAsync(ranges_out, at<uint32_t>(ws, L.tile_start), ((size_t)plan->num_tiles + 1) * 4,
+                                   hipMemcpyDeviceToHost, s) != hipSuccess)
+    return UG_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return UG_ERR_HIP;
   return n;
 }
 

@@ -232,6 +232,21 @@ class Plan:
             check(got, "ug_debug_records")
         return np.ctypeslib.as_array(arr)[:n].copy()
 
+    def debug_keys(self):
+        """The sorted keys of the last render (key words, emission positions,
+        record ids) and the tile ranges, as uint32 numpy arrays (synchronises).
+        A test hook."""
+        n = int(lib.ug_debug_keys(self._h, self._ws_ptr, None, None, None, None, 0, _stream()))
+        if n < 0:
+            check(n, "ug_debug_keys")
+        key, eidx, rec = (np.empty(max(n, 1), dtype=np.uint32) for _ in range(3))
+        ranges = np.empty(self.num_tiles + 1, dtype=np.uint32)
+        got = int(lib.ug_debug_keys(self._h, self._ws_ptr, key.ctypes.data, eidx.ctypes.data, rec.ctypes.data,
+                                    ranges.ctypes.data, n, _stream()))
+        if got < 0:
+            check(got, "ug_debug_keys")
+        return key[:n], eidx[:n], rec[:n], ranges
+
     def quality(self, image: torch.Tensor, ref: torch.Tensor, data_range: float = 1.0):
         """Per-plane (ssim, mse) float64 device tensors of ``image`` against
         ``ref`` (both packed like this plan's renders): mean SSIM over the

@@ -4,10 +4,35 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
+from oracle import pool
 
 IMAGE_TOL = 1e-4   # max abs error / peak |oracle| intensity
 GRAD_TOL = 1e-3    # max abs error / max |oracle gradient|, per tensor
 AMBIG_FRAC = 1e-3  # pixels allowed to rely on the cut-off ambiguity interval
+# Per element: |gpu - ref| <= GRAD_ELEM_REL |ref| + GRAD_ELEM_FLOOR max|ref|.
+# The floor covers entries that are sums of terms cancelling far below the
+# tensor's scale (FP32 keeps about 1e-7 of each term, not of their sum).
+GRAD_ELEM_REL = 1e-3
+GRAD_ELEM_FLOOR = 1e-5
+# Above this many Gaussian-point pairs the oracle runs in worker processes.
+POOL_PAIRS = 2e7
+
+
+def _big(g, m: int) -> bool:
+    return float(np.asarray(g.means).shape[0]) * m > POOL_PAIRS
+
+
+def reference_points(g, X, params):
+    """(c_hat, alpha_hat) of the oracle at the world points X."""
+    op = oracle_params(params)
+    return pool.render_points(g, X, op) if _big(g, X.shape[0]) else oracle.render_points(g, X, op)
+
+
+def reference_grad(g, X, dout, params):
+    """The oracle's gradient of sum dout(x) c_hat(x) at the world points X."""
+    op = oracle_params(params)
+    nz = int(np.count_nonzero(dout))
+    return pool.grad_points(g, X, dout, op) if _big(g, nz) else oracle.grad_points(g, X, dout, op)
 
 
 def oracle_params(params) -> oracle.Params:
@@ -17,12 +42,14 @@ def oracle_params(params) -> oracle.Params:
                          bg_alpha=float(f(params.bg_alpha)), bg_color=float(f(params.bg_color)))
 
 
-def check_image(gpu: np.ndarray, g, planes, params, pix=None, tol_rel=IMAGE_TOL, peak=None):
+def check_image(gpu: np.ndarray, g, planes, params, pix=None, tol_rel=IMAGE_TOL, peak=None, ref=None):
     """Element-wise parity; pixels off by more than tol must lie within tol of
-    the oracle's cut-off ambiguity interval.  Returns a stats dict."""
+    the oracle's cut-off ambiguity interval.  ``ref`` = the oracle's c_hat at
+    these pixels if already computed.  Returns a stats dict."""
     op = oracle_params(params)
     X = oracle.plane_points(planes, pix)
-    ref, _ = oracle.render_points(g, X, op)
+    if ref is None:
+        ref, _ = reference_points(g, X, params)
     gpu = np.asarray(gpu, dtype=np.float64).reshape(-1)
     assert gpu.shape == ref.shape
     assert np.all(np.isfinite(gpu)), "non-finite GPU output"
@@ -32,7 +59,8 @@ def check_image(gpu: np.ndarray, g, planes, params, pix=None, tol_rel=IMAGE_TOL,
     bad = np.nonzero(diff > tol)[0]
     n_amb = 0
     if bad.size:
-        lo, hi, k = oracle.ambiguity_points(g, X[bad], op)
+        amb = pool.ambiguity_points if _big(g, bad.size) else oracle.ambiguity_points
+        lo, hi, k = amb(g, X[bad], op)
         dist = np.maximum(lo - gpu[bad], gpu[bad] - hi)
         worst = int(np.argmax(dist))
         assert np.all(dist <= tol), (
@@ -66,13 +94,27 @@ def check_image_box_support(gpu: np.ndarray, g, planes, params, pix=None, tol_re
             "max_rel_peak": float(diff.max() / max(pk, 1e-30))}
 
 
-def check_grads(gpu: dict, ref: dict, tol_rel=GRAD_TOL):
+def check_grads(gpu: dict, ref: dict, tol_rel=GRAD_TOL, elem_rel=GRAD_ELEM_REL, elem_floor=GRAD_ELEM_FLOOR):
+    """Per tensor: max abs error / max |ref| <= tol_rel, and per element
+    |gpu - ref| <= elem_rel |ref| + elem_floor max|ref|.  Returns, per tensor,
+    the max-normalised error and the worst per-element ratio (error over its
+    bound)."""
     errs = {}
     for name in ("means", "lraw", "intensity", "opacity"):
         a = np.asarray(gpu[name], dtype=np.float64).reshape(ref[name].shape)
+        b = ref[name]
         assert np.all(np.isfinite(a)), f"non-finite gradient {name}"
-        scale = float(np.abs(ref[name]).max())
-        err = float(np.abs(a - ref[name]).max()) / max(scale, 1e-300)
-        errs[name] = err
+        scale = float(np.abs(b).max())
+        diff = np.abs(a - b)
+        err = float(diff.max()) / max(scale, 1e-300)
+        bound = elem_rel * np.abs(b) + elem_floor * max(scale, 1e-300)
+        ratio = diff / bound
+        worst = int(np.argmax(ratio))
+        # the same ratio with a floor ten times lower, reported only
+        tight = float(np.max(diff / (elem_rel * np.abs(b) + 0.1 * elem_floor * max(scale, 1e-300))))
+        errs[name] = {"max_rel": err, "elem_worst": float(ratio.reshape(-1)[worst]), "elem_worst_floor_1e-6": tight}
         assert err <= tol_rel, f"gradient {name}: relative max error {err:.3e} > {tol_rel}"
+        assert ratio.reshape(-1)[worst] <= 1.0, (
+            f"gradient {name}[{np.unravel_index(worst, b.shape)}]: gpu {a.reshape(-1)[worst]:.8g} oracle "
+            f"{b.reshape(-1)[worst]:.8g} exceeds {elem_rel} relative + {elem_floor} of max|ref| ({scale:.4g})")
     return errs

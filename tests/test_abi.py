@@ -117,6 +117,10 @@ def test_newer_entry_points_reject_invalid_arguments(L):
                                  ctypes.byref(gm), ctypes.byref(gm), ctypes.byref(hp), None, None, None, None) == bad
     assert L.lib.ug_step_replay(None, None) == bad
     assert L.lib.ug_debug_records(None, None, None, 0, None) == bad
+    assert L.lib.ug_debug_keys(None, None, None, None, None, None, 0, None) == bad
+    ms = ctypes.c_float()
+    for kind, blocks, iters, n in ((9, 1, 1, 256), (0, 0, 1, 256), (0, 1, 0, 256), (0, 2, 1, 256), (3, 1, 1, 6)):
+        assert L.lib.ug_probe(kind, blocks, iters, None, None, n, ctypes.byref(ms), None) == bad
     assert L.lib.ug_image_quality(None, None, None, 1.0, None, None, None, None) == bad
     assert L.lib.ug_quality_workspace_bytes(None) == 0
     for kind, fp64, n in ((7, 0, 1), (0, 2, 1), (0, 0, -1)):

@@ -94,10 +94,14 @@ def test_gradients_vs_fp64_finite_differences(R, chi2):
     print("fd", check_grads(gg, fd))
 
 
-@pytest.mark.parametrize("k,count", [(1, 400), (2, 200), (3, 150)])
+@pytest.mark.parametrize("k,count", [(1, 400), (2, 200), (3, 150), (4, 150)])
 def test_configs_sparse_upstream_gradient(R, k, count):
-    """Full-size renders; d_image is non-zero on seeded pixels only, so the
+    """Full-size renders and adjoints in the library's default launch
+    configuration and in the autotuner's stored pick (the configuration the
+    benchmark times); d_image is non-zero on seeded pixels only, so the
     oracle's exact gradient needs just those pixels."""
+    from tests.configs import launch_configs
+    from tests.parity import reference_grad
     g, pl, _ = synth.make_config(k)
     pix = synth.sample_pixels(pl, count, 600 + k)
     offs = pl.pixel_offsets()
@@ -106,9 +110,45 @@ def test_configs_sparse_upstream_gradient(R, k, count):
     vals = rng.standard_normal(count).astype(np.float32)
     dimg = np.zeros(pl.npix, dtype=np.float32)
     dimg[flat] = vals
-    _, gg, plan = _fwd_bwd(R, g, pl, dimg)
-    ref = oracle.grad_points(g, oracle.plane_points(pl, pix), vals.astype(np.float64), oracle_params(plan.params))
-    print(f"c{k} grads", check_grads(gg, ref))
+    ref = None
+    for name, params in launch_configs(R, g, pl):
+        _, gg, plan = _fwd_bwd(R, g, pl, dimg, params)
+        if ref is None:
+            ref = reference_grad(g, oracle.plane_points(pl, pix), vals.astype(np.float64), plan.params)
+        print(f"c{k} {name} {params.tile_w}x{params.tile_h} batch {params.lds_batch} box {params.box_mode} grads",
+              check_grads(gg, ref))
+
+
+def test_run_to_run_bitwise_adjoint(R):
+    """The adjoint is deterministic (no atomics; every sum in a fixed order):
+    two backward passes of the 200k anisotropic workload in its tuned
+    configuration, and the MSE-fused adjoint run twice, give the same
+    gradients bit for bit."""
+    from tests.configs import tuned_params
+    g, pl, tg = synth.make_config(2)
+    params = tuned_params(g, pl)
+    dev = torch.device("cuda", 0)
+    gd, pd, td = R.to_device(g, dev), R.to_device(pl, dev), R.to_device(tg, dev)
+    tplan = R.Plan(tg.n, pl.wh, params, device=dev)
+    tplan.fit(td, pd)
+    target = tplan.render(td, pd).clone()
+    del tplan
+    plan = R.Plan(g.n, pl.wh, params, device=dev)
+    plan.fit(gd, pd)
+    img = plan.render(gd, pd)
+    rng = np.random.default_rng(5)
+    dimg = torch.from_numpy(rng.standard_normal(plan.num_pixels).astype(np.float32)).to(dev)
+    a = [t.clone() for t in plan.backward(gd, pd, img, dimg)]
+    b = [t.clone() for t in plan.backward(gd, pd, img, dimg)]
+    c = [t.clone() for t in plan.backward_mse(gd, pd, img, target)]
+    img2 = plan.render(gd, pd)
+    d = [t.clone() for t in plan.backward_mse(gd, pd, img2, target)]
+    torch.cuda.synchronize()
+    assert torch.equal(img, img2)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    for x, y in zip(c, d):
+        assert torch.equal(x, y)
 
 
 def test_accumulate_flag_and_autograd(R):
