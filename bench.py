@@ -38,39 +38,45 @@ METRIC = "fwd+bwd planes/s and Gaussian-pixel evals/s vs plain per-plane, at 1e-
 #            w dL/dw (1), dc += gamma w (2), de0 (1), dT11 (3), dT12 (2),
 #            dT22 (3), du0 (1), dv0 (4)                                = 32
 FLOPS_PER_PAIR = {"accum": 16, "accum_bwd": 32}
-# Peak of the scalar (non-packed) FP32 vector ALU: 256 CUs x 4 SIMDs x 16
-# lanes x 2 flops (FMA) x 2.4 GHz.  The kernels are compiled without packed
-# FP32, so the packed 157.3 TFLOP/s figure does not apply.
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# The Phase-1 test of one (Gaussian, plane) pair: m3 = r3 . (mu - o) (3 sub,
+# 3 mul, 2 add), forward substitution L g = r3 with the Gaussian's reciprocal
+# diagonal (9), Sigma'_33 = |g|^2 (5), m3^2 <= chi^2 Sigma'_33 (3)      = 25
+FLOPS_PER_CULL_TEST = 25
+# MI355X's published FP32 vector peak (256 CUs x 2.4 GHz x 256 flop per CU
+# and clock; it needs packed FP32 instructions) and the peak of the scalar
+# FP32 forms these kernels are compiled to (packed FP32 stays disabled):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 157.3
+ALU_PEAK_SCALAR_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(k: int, n_px: int) -> dict:
-    """The FP64 oracle, forward + adjoint, on a seeded pixel sample of plane 0
-    with every Gaussian, in a single-threaded child process."""
-    code = f"""
-import json, sys, time
-sys.path.insert(0, {ROOT!r})
-import numpy as np
-import oracle
-from paper_2505_05643_amd import synth
-g, pl, _ = synth.make_config({k})
-one = pl.subset(0)
-pix = synth.sample_pixels(one, {n_px}, 901)
-X = oracle.plane_points(one, pix)
-t0 = time.perf_counter()
-out, _ = oracle.render_points(g, X)
-gr = oracle.grad_points(g, X, np.ones(len(X)))
-dt = time.perf_counter() - t0
-print(json.dumps({{"seconds": dt, "pix": pix.tolist(), "values": out.tolist(),
-                  "plane_px": int(one.wh[0, 0] * one.wh[0, 1])}}))
-"""
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
-               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
-    if r.returncode != 0:
-        raise RuntimeError("oracle baseline failed:\n" + r.stderr[-2000:])
-    return json.loads(r.stdout.strip().splitlines()[-1])
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, pl, n_px: int, workers: int) -> dict:
+    """The FP64 oracle, forward + adjoint, on a seeded sample of pixels spread
+    over all planes of the workload, against every Gaussian, on ``workers``
+    host processes (one chunk of the sample each)."""
+    import oracle
+    from oracle import pool
+    from paper_2505_05643_amd import synth
+    pix = synth.sample_pixels(pl, n_px, 901)
+    X = oracle.plane_points(pl, pix)
+    dout = np.random.default_rng(902).standard_normal(X.shape[0])
+    t0 = time.perf_counter()
+    out, _ = pool.render_points(g, X, workers=workers)
+    pool.grad_points(g, X, dout, workers=workers)
+    dt = time.perf_counter() - t0
+    return {"seconds": dt, "pix": pix, "values": out}
 
 
 def main():
@@ -78,7 +84,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4,
+                    help="workload 0-4 (default 4: 1M Gaussians, 256 planes of 256^2, the largest)")
     ap.add_argument("--tile", type=str, default=None, help="WxH[xPPL], e.g. 16x16x1")
     ap.add_argument("--lds-batch", type=int, default=None)
     ap.add_argument("--box", type=int, default=None, help="0 paper, 1 conic, 2 rows")
@@ -91,7 +98,8 @@ def main():
     ap.add_argument("--recon-steps", type=int, default=300, help="training steps per reconstruction case")
     ap.add_argument("--no-param-study", action="store_true",
                     help="skip the covariance parameterisation study (run with the default workload)")
-    ap.add_argument("--cpu-px", type=int, default=640)
+    ap.add_argument("--cpu-px", type=int, default=0,
+                    help="oracle baseline sample in pixels (default: sized for about 20 s on the host cores)")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch configuration")
     ap.add_argument("--retune", action="store_true",
@@ -99,6 +107,7 @@ def main():
     ap.add_argument("--tune-cache", type=str, default=None,
                     help="autotune cache file (default: the package's autotune_cache.json); a search stores its "
                          "pick there")
+    ap.add_argument("--peaks", action="store_true", help="print the chip's measured throughput probes and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="finish with 5 elementwise copies (dst = -src) of MIB MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -114,6 +123,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.peaks:
+        print(json.dumps(measured_peaks(dev)), flush=True)
+        return
     k = args.config
     g, pl, tg = synth.make_config(k)
     gd, pd, tgd = R.to_device(g, dev), R.to_device(pl, dev), R.to_device(tg, dev)
@@ -339,11 +351,18 @@ def main():
     for nm, (ms, n) in stages.items():
         avg = ms / max(n, 1)
         row = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps, "avg_launch_ms": avg}
-        if nm in FLOPS_PER_PAIR:
-            ach = n_eval * FLOPS_PER_PAIR[nm] / (avg / 1e3) / 1e12
+        if nm in FLOPS_PER_PAIR or nm == "cull_count":
+            if nm == "cull_count":
+                flop = FLOPS_PER_CULL_TEST * g.n * pl.p
+                work = f"{FLOPS_PER_CULL_TEST} flop x {g.n} x {pl.p} (Gaussian, plane) tests per launch"
+            else:
+                flop = FLOPS_PER_PAIR[nm] * n_eval
+                work = f"{FLOPS_PER_PAIR[nm]} flop x {n_eval} in-support pairs per launch"
+            ach = flop / (avg / 1e3) / 1e12
             row.update(bound="alu", achieved=ach, peak=ALU_PEAK_TFLOPS, unit="TFLOP/s", frac=ach / ALU_PEAK_TFLOPS,
-                       work=f"{FLOPS_PER_PAIR[nm]} flop x {n_eval} in-support pairs per launch",
-                       evaluated_pairs=n_exec)
+                       frac_scalar_fp32_peak=ach / ALU_PEAK_SCALAR_TFLOPS, work=work)
+            if nm in FLOPS_PER_PAIR:
+                row["evaluated_pairs"] = n_exec
         else:
             nbytes = kernel_bytes(nm, **sizes)
             ach = nbytes / (avg / 1e3) / 1e9
@@ -355,6 +374,9 @@ def main():
     roof = {"bound": d["bound"], "kernel": dom_name, "achieved": d["achieved"], "peak": d["peak"],
             "unit": d["unit"], "frac": d["frac"], "traffic": stored_traffic(dom_name, k, params, plan),
             "work": d["work"], "avg_launch_ms": d["avg_launch_ms"]}
+    if d["bound"] == "alu":
+        roof["peak_scalar_fp32"] = ALU_PEAK_SCALAR_TFLOPS
+        roof["frac_scalar_fp32_peak"] = d["frac_scalar_fp32_peak"]
     acc = {nm: kernels[nm] for nm in ("accum", "accum_bwd") if nm in kernels}
 
     out = {
@@ -393,6 +415,7 @@ def main():
         "accumulate_kernels": acc,
         "kernels": kernels,
         "roofline": roof,
+        "measured_peaks": measured_peaks(dev),
     }
     if k == 1 and not args.no_recon and not args.no_graph:
         out["reconstruction"] = reconstruction(dev, args.recon_steps)
@@ -402,17 +425,22 @@ def main():
                                    "throughput": paramstudy.throughput(device=dev)}
 
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(k, args.cpu_px)
-        frac_plane = len(cb["pix"]) / cb["plane_px"]
-        pix = np.asarray(cb["pix"])
-        img0 = image[: cb["plane_px"]].cpu().numpy().astype(np.float64)
-        w0 = int(pl.wh[0, 0])
-        gpu_vals = img0[pix[:, 2] * w0 + pix[:, 1]]
+        from oracle import pool
+        workers = pool.default_workers()
+        # about 20 s of host time: the oracle costs about 5.6e-7 s per
+        # (Gaussian, pixel) pair for forward + adjoint on one core
+        n_px = args.cpu_px or int(max(workers, min(pl.npix, 20.0 * workers / (5.6e-7 * g.n))))
+        cb = cpu_baseline(g, pl, n_px, workers)
+        pix = cb["pix"]
+        flat = pl.pixel_offsets()[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
+        gpu_vals = image.cpu().numpy().astype(np.float64)[flat]
         ref = np.asarray(cb["values"])
-        out["cpu_baseline"] = {"value": frac_plane / cb["seconds"], "unit": "planes/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{len(cb['pix'])} seeded pixels of plane 0 x all {g.n} Gaussians, "
-                                         f"FP64 forward + adjoint, {cb['seconds']:.1f} s, scaled to one plane"}
+        planes_equiv = len(pix) * pl.p / pl.npix  # the sample as a fraction of one step's planes
+        out["cpu_baseline"] = {"value": planes_equiv / cb["seconds"], "unit": "planes/s", "cores": workers,
+                               "kind": "oracle", "cpu": cpu_model(),
+                               "sample": f"{len(pix)} seeded pixels over all {pl.p} planes x all {g.n} Gaussians, "
+                                         f"FP64 forward + adjoint, {cb['seconds']:.1f} s on {workers} worker "
+                                         f"processes, scaled to planes of the workload's mean size"}
         out["parity_sample_max_rel"] = float(np.abs(gpu_vals - ref).max() / max(np.abs(ref).max(), 1e-30))
     print(json.dumps(out), flush=True)
 
@@ -497,6 +525,44 @@ def densify_ms(R, gd, dev, warmup, steps):
             "achieved_gbs": nbytes / (ms / 1e3) / 1e9, "frac_hbm": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
+def measured_peaks(dev) -> dict:
+    """The library's throughput probes (best of three launches each): FMA
+    chains (scalar FP32 VALU), v_exp_f32 chains, the forward's pair
+    evaluation on registers, and a 512 MiB device copy (HBM read + write)."""
+    import ctypes
+    import torch
+    from paper_2505_05643_amd import _lib
+    blocks, iters = 2048, 16384
+    out = torch.empty(blocks * 256, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    ms = ctypes.c_float()
+
+    def best(kind, b, it, src, dst, n):
+        t = []
+        for _ in range(3):
+            _lib.check(_lib.lib.ug_probe(kind, b, it, src, dst, n, ctypes.byref(ms), stream), "ug_probe")
+            t.append(ms.value)
+        return min(t)
+
+    res = {}
+    t = best(_lib.UG_PROBE_FMA, blocks, iters, None, out.data_ptr(), out.numel())
+    res["fma_tflops"] = 16.0 * iters * 256 * blocks / (t / 1e3) / 1e12
+    t = best(_lib.UG_PROBE_EXP, blocks, iters, None, out.data_ptr(), out.numel())
+    res["exp_per_s"] = 8.0 * iters * 256 * blocks / (t / 1e3)
+    t = best(_lib.UG_PROBE_PAIRS, blocks, iters, None, out.data_ptr(), out.numel())
+    res["forward_pairs_per_s"] = 8.0 * iters * 256 * blocks / (t / 1e3)
+    n = 128 << 20
+    src = torch.ones(n, device=dev)
+    dst = torch.empty_like(src)
+    t = best(_lib.UG_PROBE_COPY, 8192, 1, src.data_ptr(), dst.data_ptr(), n)
+    res["copy_gbs"] = 8.0 * n / (t / 1e3) / 1e9
+    res["scalar_fp32_peak_tflops"] = ALU_PEAK_SCALAR_TFLOPS
+    res["published_fp32_peak_tflops"] = ALU_PEAK_TFLOPS
+    res["published_hbm_gbs"] = HBM_PEAK_GBS
+    del src, dst, out
+    return res
+
+
 def replay_ms(fn, warmup, steps):
     """Average ms of fn captured once as a hipGraph and replayed."""
     import torch
@@ -561,7 +627,8 @@ def kernel_bytes(name, n, p, r, k, t, m, passes, w, rows, g_sort, dslots) -> int
     return 0
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_per_kernel_c1.md")
+def traffic_file(k: int) -> str:
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_per_kernel_c{k}.md")
 
 
 def stored_traffic(kernel, k, params, plan):
@@ -571,7 +638,7 @@ def stored_traffic(kernel, k, params, plan):
     with the current kernel sources; else None.  The summary file carries them
     on a line starting with "traffic-json: "."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(k)) as f:
             line = next((ln for ln in f if ln.startswith("traffic-json: ")), None)
         rec = json.loads(line[len("traffic-json: "):]) if line else {}
     except (OSError, ValueError):

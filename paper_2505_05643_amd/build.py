@@ -18,7 +18,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libug.so")
 
 SOURCES = ["ug_api.hip", "ug_preprocess.hip", "ug_sort.hip", "ug_raster.hip", "ug_scatter.hip", "ug_densify.hip",
-           "ug_train.hip", "ug_quality.hip", "ug_params.hip"]
+           "ug_train.hip", "ug_quality.hip", "ug_params.hip", "ug_probe.hip"]
 
 ARCH = "gfx950"
 HIPCC_FLAGS = [

@@ -105,6 +105,9 @@ hipError_t launch_quality(const PlaneInt* pint, int32_t p, uint32_t max_strips, 
 hipError_t launch_param_eval(int32_t kind, bool fp64, const float* raw, const float* z, const float* delta,
                              int64_t n, float beta, void* sigma, void* draw, void* d2, hipStream_t s);
 
+// ---- throughput probes (ug_probe.hip)
+hipError_t launch_probe(int kind, int blocks, int iters, const float* src, float* dst, int64_t n, hipStream_t s);
+
 // ---- accumulate (ug_raster.hip)
 int accum_default_ppl(int tile_w, int tile_h);
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);
