@@ -5,73 +5,87 @@ TEST INFRASTRUCTURE ONLY, like the rest of this package.
 Section 4.2 draws a new point from a Gaussian through its triangular factor,
 y = mu + L^-T z (``sample_gaussian``).  The clone / split / prune rule is only
 referred to by the paper (3D Gaussian splatting); the library's stated
-choice, followed here step by step:
+choice, evaluated here in float64:
 
-* size^2 = trace(Sigma) = the sum of squares of the entries of L^-1 (L lower
-  triangular, so L^-1 is written out entry by entry);
-* prune if sigmoid(a) < min_opacity (compared as a < logit(min_opacity)) or,
-  with max_size > 0, size^2 > max_size^2;
-* else if cnt > 0 and acc >= grad_thresh * cnt: split if size^2 >
-  split_size^2, otherwise clone;
+* size^2 = trace(Sigma), Sigma from the Section 4.2 forward substitution
+  (``covariance``);
+* prune if sigmoid(a) < min_opacity or, with max_size > 0,
+  size^2 > max_size^2;
+* else if cnt > 0 and the mean accumulated gradient acc / cnt reaches
+  grad_thresh (acc >= grad_thresh * cnt): split if size^2 > split_size^2,
+  otherwise clone;
 * else keep.
 
-These are integer outcomes of floating-point comparisons, so they are taken
-in float32 with every operation in the library's order (numpy rounds each
-float32 operation once, as the device does with contraction off).  The
-outputs are float64: kept and cloned Gaussians are copies; a split gives two
-children with means mu + L^-T z[i][c] and factor phi L (every standard
-deviation divided by phi), intensity and opacity copied.  Outputs are in
-Gaussian order, a Gaussian's children together.
+Each decision is an integer outcome of a comparison of real numbers, which a
+float32 evaluation may take the other way when the two sides are within its
+rounding.  A comparison whose sides differ by at most BAND (relative) is
+borderline, and ``decisions`` also returns every outcome the rule gives
+under any choice of the borderline comparisons.  Outputs are float64: kept
+and cloned Gaussians are copies; a split gives two children with means
+mu + L^-T z[i][c] and factor phi L (every standard deviation divided by
+phi), intensity and opacity copied.  Outputs are in Gaussian order, a
+Gaussian's children together.
 """
 from __future__ import annotations
 
-import math
+import itertools
 
 import numpy as np
 
-from .render import sample_gaussian
+from .render import covariance, sample_gaussian, sigmoid
 
 PRUNE, KEEP, CLONE, SPLIT = 0, 1, 2, 3
+# Relative half-width of the borderline band of a comparison (a float32
+# evaluation of either side is within a few 1e-7 of it).
+BAND = 1e-5
 
 
-def size2_f32(lraw, beta: float) -> np.ndarray:
-    """float32 trace of the covariance from the raw factor (Eq. 11)."""
-    f = np.float32
-    r = np.asarray(lraw, dtype=f).reshape(-1, 6)
-    b = f(beta)
-    l11 = r[:, 0] * r[:, 0] + b
-    l21, l31 = r[:, 1], r[:, 2]
-    l22 = r[:, 3] * r[:, 3] + b
-    l32 = r[:, 4]
-    l33 = r[:, 5] * r[:, 5] + b
-    one = f(1.0)
-    i11, i22, i33 = one / l11, one / l22, one / l33
-    i21 = -l21 * i11 * i22
-    i32 = -l32 * i22 * i33
-    i31 = (l21 * l32 - l22 * l31) * i11 * i22 * i33
-    return i11 * i11 + i21 * i21 + i22 * i22 + i31 * i31 + i32 * i32 + i33 * i33
+def size2(lraw, beta: float) -> np.ndarray:
+    """trace(Sigma) of each Gaussian (float64)."""
+    return np.trace(covariance(lraw, beta), axis1=1, axis2=2)
+
+
+def _rule(prune_op, prune_max, grow, split):
+    return np.where(prune_op | prune_max, PRUNE, np.where(grow, np.where(split, SPLIT, CLONE), KEEP))
 
 
 def decisions(lraw, opacity, acc, cnt, beta=1e-4, min_opacity=0.005, grad_thresh=2e-4, split_size=1.0,
-              max_size=0.0) -> np.ndarray:
-    """PRUNE / KEEP / CLONE / SPLIT per Gaussian."""
-    f = np.float32
-    s2 = size2_f32(lraw, beta)
-    a = np.asarray(opacity, dtype=f)
-    acc = np.asarray(acc, dtype=f)
-    cnt = np.asarray(cnt, dtype=np.int32)
-    t = float(min_opacity)
-    amin = f(-math.inf) if t <= 0.0 else (f(math.inf) if t >= 1.0 else f(math.log(t / (1.0 - t))))
-    split2 = f(split_size) * f(split_size)
-    max2 = f(max_size) * f(max_size)
-    d = np.full(a.shape[0], KEEP, dtype=np.int64)
-    grow = (cnt > 0) & (acc >= f(grad_thresh) * cnt.astype(f))
-    d[grow] = np.where(s2[grow] > split2, SPLIT, CLONE)
-    prune = ~(a >= amin)
-    if max2 > 0:
-        prune |= ~(s2 <= max2)
-    d[prune] = PRUNE
-    return d
+              max_size=0.0):
+    """(d, possible): d = PRUNE / KEEP / CLONE / SPLIT per Gaussian with every
+    comparison taken exactly in float64; possible [N, 4] marks every outcome
+    that some choice of the borderline comparisons gives (d included)."""
+    s2 = size2(lraw, beta)
+    alpha = sigmoid(np.asarray(opacity, dtype=np.float64))
+    acc = np.asarray(acc, dtype=np.float64)
+    cnt = np.asarray(cnt, dtype=np.int64)
+    t_op = float(min_opacity)
+    split2 = float(split_size) ** 2
+    max2 = float(max_size) ** 2
+    gc = float(grad_thresh) * cnt.astype(np.float64)
+    # (outcome, borderline) of the four comparisons
+    comps = [
+        (alpha < t_op, np.abs(alpha - t_op) <= BAND * abs(t_op)),
+        ((s2 > max2) if max2 > 0 else np.zeros(s2.shape, bool),
+         (np.abs(s2 - max2) <= BAND * max2) if max2 > 0 else np.zeros(s2.shape, bool)),
+        ((cnt > 0) & (acc >= gc), (cnt > 0) & (np.abs(acc - gc) <= BAND * np.abs(gc))),
+        (s2 > split2, np.abs(s2 - split2) <= BAND * split2),
+    ]
+    d = _rule(*(c[0] for c in comps))
+    possible = np.zeros((d.shape[0], 4), dtype=bool)
+    idx = np.arange(d.shape[0])
+    for flips in itertools.product((False, True), repeat=4):
+        alt = [np.where(b & f, ~o, o) for (o, b), f in zip(comps, flips)]
+        possible[idx, _rule(*alt)] = True
+    return d, possible
+
+
+def children(mu, lraw, z2, beta: float, phi: float):
+    """The two split children of one Gaussian: (means [2,3], lraw [2,6])."""
+    mu = np.asarray(mu, dtype=np.float64).reshape(1, 3)
+    raw = np.asarray(lraw, dtype=np.float64).reshape(1, 6)
+    z2 = np.asarray(z2, dtype=np.float64).reshape(2, 3)
+    means = np.stack([sample_gaussian(mu, raw, z2[c:c + 1], beta)[0] for c in range(2)])
+    return means, np.repeat(scaled_lraw(raw, beta, phi), 2, axis=0)
 
 
 def scaled_lraw(lraw, beta: float, phi: float) -> np.ndarray:
@@ -86,8 +100,9 @@ def scaled_lraw(lraw, beta: float, phi: float) -> np.ndarray:
 def densify(g, acc, cnt, z, beta=1e-4, min_opacity=0.005, grad_thresh=2e-4, split_size=1.0, max_size=0.0,
             split_factor=1.6):
     """(means, lraw, intensity, opacity, source index, decisions): the outputs
-    in Gaussian order (float64) and the input Gaussian each came from."""
-    d = decisions(g.lraw, g.opacity, acc, cnt, beta, min_opacity, grad_thresh, split_size, max_size)
+    in Gaussian order (float64) and the input Gaussian each came from, for
+    the float64 decisions."""
+    d, _ = decisions(g.lraw, g.opacity, acc, cnt, beta, min_opacity, grad_thresh, split_size, max_size)
     z = np.asarray(z, dtype=np.float64).reshape(-1, 2, 3)
     means, lraw, inten, opac, src = [], [], [], [], []
     mu = np.asarray(g.means, dtype=np.float64)
@@ -98,8 +113,9 @@ def densify(g, acc, cnt, z, beta=1e-4, min_opacity=0.005, grad_thresh=2e-4, spli
         n_out = 1 if d[i] == KEEP else 2
         for c in range(n_out):
             if d[i] == SPLIT:
-                means.append(sample_gaussian(mu[i:i + 1], raw[i:i + 1], z[i, c:c + 1], beta)[0])
-                lraw.append(scaled_lraw(raw[i:i + 1], beta, split_factor)[0])
+                cm, cl = children(mu[i], raw[i], z[i], beta, split_factor)
+                means.append(cm[c])
+                lraw.append(cl[c])
             else:
                 means.append(mu[i].copy())
                 lraw.append(raw[i].copy())

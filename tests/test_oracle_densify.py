@@ -1,6 +1,7 @@
 """Pins of the densify / prune reference (oracle/densify.py): closed forms
-for isotropic Gaussians, the covariance scaling of a split, and the size
-measure against the covariance computed independently."""
+for isotropic Gaussians, the covariance scaling of a split, the size measure
+against the covariance computed by a library inverse of the precision, and
+the borderline outcomes of constructed ties."""
 import math
 
 import numpy as np
@@ -26,10 +27,11 @@ def _iso(sigmas, a=1.0):
 
 
 def test_size_is_trace_of_covariance():
+    """size^2 against the trace of the library inverse of the precision L L^T."""
     g = synth.make_gaussians(500, 3, (0, 0, 0), (1, 1, 1), (0.01, 0.3), aniso_max=20.0)
-    s2 = D.size2_f32(g.lraw, BETA).astype(np.float64)
-    tr = np.trace(oracle.covariance(g.lraw, BETA), axis1=1, axis2=2)
-    np.testing.assert_allclose(s2, tr, rtol=2e-5)
+    L = oracle.activate_l(g.lraw, BETA)
+    tr = np.trace(np.linalg.inv(L @ np.transpose(L, (0, 2, 1))), axis1=1, axis2=2)
+    np.testing.assert_allclose(D.size2(g.lraw, BETA), tr, rtol=1e-9)
 
 
 def test_split_scaling_divides_every_std():
@@ -46,12 +48,29 @@ def test_decisions_on_constructed_cases():
     g.opacity[0] = math.log(0.001 / 0.999)  # alpha 0.001 < 0.005: prune
     acc = np.array([1.0, 0.0, 3e-3, 3e-3, 3e-3], np.float32)
     cnt = np.array([10, 0, 10, 10, 10], np.int32)
-    d = D.decisions(g.lraw, g.opacity, acc, cnt, BETA, 0.005, 2e-4, 1.0, 50.0)
+    d, possible = D.decisions(g.lraw, g.opacity, acc, cnt, BETA, 0.005, 2e-4, 1.0, 50.0)
     assert list(d) == [D.PRUNE, D.KEEP, D.CLONE, D.SPLIT, D.PRUNE]
+    assert np.array_equal(possible, np.eye(4, dtype=bool)[d])  # nothing borderline
     # just under / over the gradient threshold (acc / cnt = 1.9e-4, 2.1e-4)
-    d = D.decisions(g.lraw[:2], np.ones(2, np.float32), np.array([1.9e-3, 2.1e-3], np.float32),
-                    np.array([10, 10], np.int32), BETA, 0.005, 2e-4, 1.0, 0.0)
+    d, _ = D.decisions(g.lraw[:2], np.ones(2, np.float32), np.array([1.9e-3, 2.1e-3], np.float32),
+                       np.array([10, 10], np.int32), BETA, 0.005, 2e-4, 1.0, 0.0)
     assert list(d) == [D.KEEP, D.CLONE]
+
+
+def test_borderline_ties_give_both_outcomes():
+    """Comparisons whose sides are equal to float rounding admit either
+    outcome: alpha at the opacity floor (prune or keep), the mean gradient at
+    its threshold (keep or grow), size^2 at the split size (clone or split)."""
+    s_split = math.sqrt(1.0 / 3.0)            # isotropic: size^2 = 3 sigma^2 = 1
+    g = _iso([0.1, 0.1, s_split])
+    g.opacity[0] = np.float32(math.log(0.005 / 0.995))
+    acc = np.array([0.0, 2e-3, 1.0], np.float32)
+    cnt = np.array([0, 10, 1], np.int32)
+    d, possible = D.decisions(g.lraw, g.opacity, acc, cnt, BETA, 0.005, 2e-4, 1.0, 0.0)
+    assert set(np.nonzero(possible[0])[0]) == {D.PRUNE, D.KEEP}
+    assert set(np.nonzero(possible[1])[0]) == {D.KEEP, D.CLONE}
+    assert set(np.nonzero(possible[2])[0]) == {D.CLONE, D.SPLIT}
+    assert all(possible[i, d[i]] for i in range(3))
 
 
 def test_outputs_in_order_with_closed_form_children():
