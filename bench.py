@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--no-recon", action="store_true",
                     help="skip the synthetic reconstruction-quality workload (run with the default workload)")
     ap.add_argument("--recon-steps", type=int, default=300, help="training steps per reconstruction case")
+    ap.add_argument("--train-steps", type=int, default=2000,
+                    help="steps of the 1M-Gaussian training run on pool planes (workload 4; 0 skips it)")
     ap.add_argument("--no-param-study", action="store_true",
                     help="skip the covariance parameterisation study (run with the default workload)")
     ap.add_argument("--cpu-px", type=int, default=0,
@@ -417,6 +419,8 @@ def main():
         "roofline": roof,
         "measured_peaks": measured_peaks(dev),
     }
+    if k == 4 and args.train_steps > 0 and not args.no_graph:
+        out["config4_training"] = config4_training(dev, params, args.train_steps)
     if k == 1 and not args.no_recon and not args.no_graph:
         out["reconstruction"] = reconstruction(dev, args.recon_steps)
     if k == 1 and not args.no_param_study:
@@ -476,6 +480,83 @@ def reconstruction(dev, steps):
             "quality_kernel": {"ms": q_ms, "pixels": npx, "gpix_per_s": npx / (q_ms * 1e6),
                                "hbm_gbs": 8 * npx / (q_ms * 1e6),
                                "fp64_tflops": 240 * npx / (q_ms * 1e9)}}
+
+
+def config4_training(dev, params, steps: int, seed: int = 404) -> dict:
+    """The 1M-Gaussian workload trained as stated: every step draws 256
+    distinct planes of 256^2 (seeded) from the pool of 2,048 planes of 8
+    interleaved oblique sweeps, gathers their poses and target images (the
+    seed-204 Gaussian set rendered once on the whole pool) into the step's
+    fixed buffers, and replays the captured step (render, MSE adjoint, Adam).
+    Then the trained Gaussians are extracted as the 256 axial planes of the
+    256^3 volume in one forward launch."""
+    import torch
+    from paper_2505_05643_amd import raster as R
+    from paper_2505_05643_amd import synth
+    from paper_2505_05643_amd.step import AdamConfig, TrainStep
+    pool = synth.config4_training_pool()
+    P, per = pool.p, 256
+    wh = pool.wh[:per]
+    pool_d = R.to_device(pool, dev)
+    tg = R.to_device(synth.config_gaussians(4, target=True), dev)
+    tplan = R.Plan(tg.means.shape[0], wh, params, device=dev)
+    npx = int(wh[0, 0] * wh[0, 1])
+    targets = torch.empty(P, npx, device=dev)
+    for c in range(0, P, per):
+        sub = R.PlaneTensors(*(t[c:c + per] for t in pool_d))
+        tplan.fit(tg, sub)
+        tplan.render(tg, sub, targets[c:c + per].view(-1))
+    del tplan, tg
+    rng = np.random.default_rng(seed)
+    draws = np.stack([rng.choice(P, size=per, replace=False) for _ in range(steps)]).astype(np.int64)
+    idx = torch.from_numpy(draws).to(dev)
+    planes = R.PlaneTensors(*(t.index_select(0, idx[0]).contiguous() for t in pool_d))
+    target = targets.index_select(0, idx[0]).reshape(-1).contiguous()
+    gauss = R.to_device(synth.config_gaussians(4), dev)
+    ts = TrainStep(gauss, planes, wh, target, params, adam=AdamConfig(decay_steps=steps), headroom=1.3)
+    # capacities for the largest of a few draws (a render that still overflows
+    # skips its Adam update on the device; such steps are counted below)
+    for j in np.linspace(0, steps - 1, 8).astype(int):
+        for dst, src in zip(planes, pool_d):
+            torch.index_select(src, 0, idx[j], out=dst)
+        ts.plan.fit(ts.params, planes, 1.3)
+    loss = torch.zeros(steps, device=dev)
+
+    def gather(i):
+        for dst, src in zip(planes, pool_d):
+            torch.index_select(src, 0, idx[i], out=dst)
+        torch.index_select(targets, 0, idx[i], out=target.view(per, npx))
+
+    gather(0)
+    ts.capture()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for i in range(steps):
+        gather(i)
+        ts.replay()
+        loss[i:i + 1].copy_(ts.loss_buf[:1])
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    done = ts.step_count
+    lh = loss.cpu().numpy().astype(float)
+    # extraction: the 256 axial planes of the volume, one forward launch
+    ext = synth.config_planes(4)
+    ext_d = R.to_device(ext, dev)
+    eplan = R.Plan(ts.params.means.shape[0], ext.wh, params, device=dev)
+    eplan.fit(ts.params, ext_d)
+    vol = torch.empty(eplan.num_pixels, device=dev)
+    ext_ms = replay_ms(lambda: eplan.render(ts.params, ext_d, vol, check_status=False), 2, 10)
+    ok = eplan.status() == 0
+    marks = sorted({0, 1, 10, 100, steps // 2, steps - 1} & set(range(steps)))
+    return {"steps": steps, "planes_per_step": per, "pool_planes": P, "ms_per_step": ms,
+            "planes_per_s": per / (ms / 1e3), "adam_updates_done": done, "skipped_overflow": steps - done,
+            "loss_at_step": {str(m): lh[m] for m in marks},
+            "loss_mean_first_100": float(np.mean(lh[:100])), "loss_mean_last_100": float(np.mean(lh[-100:])),
+            "launch": "gather (torch index_select) + captured step replay per step",
+            "extraction_ms": ext_ms if ok else None, "extraction_planes": ext.p,
+            "extraction_voxels_per_s": (eplan.num_pixels / (ext_ms / 1e3)) if ok else None}
 
 
 def densify_ms(R, gd, dev, warmup, steps):

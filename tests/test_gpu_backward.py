@@ -223,3 +223,30 @@ def test_fused_mse_backward_equals_separate(R):
     plan.backward_mse(g0d, pd, img, target, loss_buf=loss)
     ref = float(np.mean((img.cpu().numpy().astype(np.float64) - 0.25) ** 2))
     assert abs(float(loss[0]) - ref) <= 1e-6 * ref
+
+
+def test_config4_training_pool_planes(R):
+    """The 1M-Gaussian workload's training planes (8 interleaved oblique
+    sweeps) in the launch configuration tuned for it: 16 seeded planes of the
+    2,048-plane pool, a sample of pixels against the oracle and the gradient
+    of a sparse upstream signal against the oracle's."""
+    from tests.configs import tuned_params
+    from tests.parity import check_image, reference_grad, reference_points
+    g = synth.config_gaussians(4)
+    pool = synth.config4_training_pool()
+    params = tuned_params(g, synth.config_planes(4))
+    sel = np.sort(np.random.default_rng(44).choice(pool.p, size=16, replace=False))
+    pl = pool.subset(sel)
+    pix = synth.sample_pixels(pl, 300, 644)
+    offs = pl.pixel_offsets()
+    flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
+    X = oracle.plane_points(pl, pix)
+    vals = np.random.default_rng(45).standard_normal(pix.shape[0]).astype(np.float32)
+    vals[150:] = 0.0  # the gradient of the first 150 sampled pixels
+    dimg = np.zeros(pl.npix, dtype=np.float32)
+    dimg[flat] = vals
+    img, gg, plan = _fwd_bwd(R, g, pl, dimg, params)
+    ref, _ = reference_points(g, X, plan.params)
+    print("pool planes", sel.tolist(), check_image(img[flat], g, pl, plan.params, pix=pix, ref=ref))
+    gref = reference_grad(g, X, vals.astype(np.float64), plan.params)
+    print("pool planes grads", check_grads(gg, gref))
