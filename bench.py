@@ -51,6 +51,14 @@ ALU_PEAK_SCALAR_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
+_T0 = time.perf_counter()
+
+
+def progress(what: str) -> None:
+    """One line on stderr as each leg of the run ends."""
+    print(f"bench: {what} ({time.perf_counter() - _T0:.1f} s)", file=sys.stderr, flush=True)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -195,6 +203,7 @@ def main():
     torch.cuda.synchronize()
     ms_total = t0.elapsed_time(t1)
     stages = plan.profile_read()
+    progress("eager steps timed")
     eager_ms_step = ms_total / args.steps
     eager_image = image.clone()
 
@@ -219,6 +228,7 @@ def main():
         t1.record()
         torch.cuda.synchronize()
         graph_ms_step = t0.elapsed_time(t1) / args.steps
+        progress("graph steps timed")
         assert torch.equal(image, eager_image), "graph replay must match the eager step"
         del graph
     ms_step = graph_ms_step if graph_ms_step is not None else eager_ms_step
@@ -250,6 +260,7 @@ def main():
         if ts.plan.status() != 0:  # a step that overflowed skipped its update: no valid time
             train_ms = None
         del ts, tparams
+        progress("forward alone and training step timed")
 
     # the paper's own accumulation (Phase 2 atomic scatter) on the same
     # records, for comparison with the gather forward above
@@ -280,6 +291,7 @@ def main():
         # how far the box support moves the image from the ellipsoid support
         scatter["box_support_max_change_by_peak"] = float((simg - image).abs().max()) / peak
         del bplan, simg
+        progress("Phase-2 scatter forms timed")
 
     # in-support pairs of one forward, counted by the kernel itself
     cparams = R.Params(**{**params.__dict__, "flags": 1})
@@ -340,6 +352,7 @@ def main():
                  "launch": "hipGraph replay" if graph_ms_step is not None else "eager",
                  "batched_speedup": pms / ms_step}
         del per
+        progress("plain per-plane form timed")
 
     # ---- roofline of every kernel; the dominant one is the headline ----
     # sort passes as launched (one histogram launch per pass); digit slots
@@ -419,8 +432,10 @@ def main():
         "roofline": roof,
         "measured_peaks": measured_peaks(dev),
     }
+    progress("kernel table and probes done")
     if k == 4 and args.train_steps > 0 and not args.no_graph:
         out["config4_training"] = config4_training(dev, params, args.train_steps)
+        progress("1M-Gaussian training run and extraction done")
     if k == 1 and not args.no_recon and not args.no_graph:
         out["reconstruction"] = reconstruction(dev, args.recon_steps)
     if k == 1 and not args.no_param_study:
@@ -446,6 +461,7 @@ def main():
                                          f"FP64 forward + adjoint, {cb['seconds']:.1f} s on {workers} worker "
                                          f"processes, scaled to planes of the workload's mean size"}
         out["parity_sample_max_rel"] = float(np.abs(gpu_vals - ref).max() / max(np.abs(ref).max(), 1e-30))
+        progress("oracle baseline done")
     print(json.dumps(out), flush=True)
 
     if args.copy_probe:
