@@ -47,6 +47,7 @@ extern "C" {
 #define UG_ERR_HIP (-4)         /* a HIP runtime call failed                 */
 #define UG_ERR_NO_DEVICE (-5)   /* no usable gfx950 device                   */
 #define UG_ERR_INTERNAL (-6)    /* a device-side consistency check failed    */
+#define UG_ERR_SCRATCH_SIZE (-7) /* the plan needs more workspace than ug_render_planes_noalloc holds */
 
 /* ---- binning boxes (all give identical images) ------------------------ */
 #define UG_BOX_PAPER 0 /* Eq. 13 box of the chi^2 ellipsoid, in-plane part b_{1:2} */
@@ -171,6 +172,34 @@ int ug_plan_measure(const ug_plan *plan, const ug_gaussians *g, const ug_planes 
  * With UG_FLAG_SCATTER the accumulation is the atomic scatter of Phase 2. */
 int ug_render_planes(const ug_plan *plan, const ug_gaussians *g, const ug_planes *planes,
                      float *image, void *workspace, void *stream);
+
+/* Forward render that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same operation, arguments, image layout
+ * and launches as ug_render_planes, with the workspace taken from a static
+ * device array of UG_NOALLOC_WORKSPACE_BYTES (64 MiB) that the library holds
+ * on every device it runs on until the process ends; its address is looked up
+ * once per device when a plan is created there (or at this call's first use
+ * on the device).  Nothing is allocated or freed and no library routine that
+ * allocates is called.  The render leaves nothing in the workspace that a
+ * later call reads, so nothing has to start at zero.
+ * Limits and caveats:
+ *   - the plan's ug_plan_workspace_bytes must be at most
+ *     UG_NOALLOC_WORKSPACE_BYTES, else UG_ERR_SCRATCH_SIZE (nothing enqueued);
+ *   - every call on one device shares that device's array, which keeps the
+ *     last call's contents: calls that overlap on one device (other streams,
+ *     other host threads, other plans) race and give wrong images;
+ *   - the workspace is not the caller's, so the render's device-side status
+ *     (capacity overflow, non-finite inputs) cannot be read with
+ *     ug_plan_status and there is no backward for this forward: on a
+ *     capacity overflow the image is background only, as with
+ *     ug_render_planes; size the plan with ug_plan_measure beforehand;
+ *   - the current device must be the one the plan was created on
+ *     (UG_ERR_INVALID_ARG otherwise).
+ * Other errors as ug_render_planes. */
+#define UG_NOALLOC_WORKSPACE_BYTES (64u << 20)
+int ug_render_planes_noalloc(const ug_plan *plan, const ug_gaussians *g, const ug_planes *planes,
+                             float *image, void *stream);
 
 /* Adjoint of ug_render_planes for an upstream gradient d_image (same layout
  * as image).  image and workspace must be those the matching forward wrote,

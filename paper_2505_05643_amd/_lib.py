@@ -18,6 +18,8 @@ UG_ERR_NONFINITE = -3
 UG_ERR_HIP = -4
 UG_ERR_NO_DEVICE = -5
 UG_ERR_INTERNAL = -6
+UG_ERR_SCRATCH_SIZE = -7
+UG_NOALLOC_WORKSPACE_BYTES = 64 << 20
 
 UG_BOX_PAPER = 0
 UG_BOX_CONIC = 1
@@ -84,6 +86,7 @@ SIGNATURES = {
     "ug_plan_measure": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp,
                                 ctypes.POINTER(c_i64), c_vp]),
     "ug_render_planes": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp, c_vp, c_vp]),
+    "ug_render_planes_noalloc": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp, c_vp]),
     "ug_render_planes_backward": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp,
                                           c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp]),
     "ug_render_planes_backward_mse": (c_i32, [c_vp, ctypes.POINTER(UgGaussians), ctypes.POINTER(UgPlanes), c_vp,

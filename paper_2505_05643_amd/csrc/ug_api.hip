@@ -2,6 +2,7 @@
 // validation and the enqueue order of the render and backward passes.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -9,6 +10,12 @@
 #include "ug_kernels.h"
 
 using namespace ug;
+
+// Workspace of ug_render_planes_noalloc: one array per device, allocated by
+// the loader with the code object and held until the process ends.  Host code
+// uses only the address hipGetSymbolAddress returns for the current device
+// (the array's name on the host is a stand-in, not a device address).
+static __device__ __align__(256) unsigned char scratch[UG_NOALLOC_WORKSPACE_BYTES];
 
 namespace {
 
@@ -254,6 +261,27 @@ Sorted sorted_set(const ug_plan* plan, void* ws) {
   return {at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.key_val0), at<uint32_t>(ws, L.rec_of_key)};
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Looks up (once per device, with that device current) the device address of
+// the static workspace; nullptr if the runtime call fails.
+void* scratch_for_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+int render_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes, float* image, void* workspace,
+                void* stream);
+
 }  // namespace
 
 extern "C" {
@@ -348,6 +376,9 @@ int ug_plan_create(int32_t n, int32_t p, const int32_t* wh_host, const ug_params
     return UG_ERR_HIP;
   }
   compute_layout(pl);
+  // set-up of the no-allocation forward's workspace on this device; a failure
+  // here is reported by that entry point, which tries again
+  (void)scratch_for_current_device();
   *out = pl;
   return UG_OK;
 }
@@ -396,6 +427,27 @@ int ug_plan_measure(const ug_plan* plan, const ug_gaussians* g, const ug_planes*
 
 int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes, float* image,
                      void* workspace, void* stream) {
+  return render_impl(plan, g, planes, image, workspace, stream);
+}
+
+int ug_render_planes_noalloc(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes, float* image,
+                             void* stream) {
+  if (!plan) return UG_ERR_INVALID_ARG;
+  if (plan->lay.total > (size_t)UG_NOALLOC_WORKSPACE_BYTES) return UG_ERR_SCRATCH_SIZE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return UG_ERR_HIP;
+  if (dev != plan->device) return UG_ERR_INVALID_ARG;  // the plan's tables live on its own device
+  void* ws = scratch_for_current_device();
+  if (!ws) return UG_ERR_HIP;
+  return render_impl(plan, g, planes, image, ws, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+int render_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes, float* image, void* workspace,
+                void* stream) {
   const int st = check_inputs(plan, g, planes, workspace);
   if (st != UG_OK) return st;
   if (!image) return UG_ERR_INVALID_ARG;
@@ -445,8 +497,6 @@ int ug_render_planes(const ug_plan* plan, const ug_gaussians* g, const ug_planes
                        plan->prm.bg_alpha, plan->prm.bg_color, plan->num_tiles, n_eval, s);
   return hip_status(e);
 }
-
-namespace {
 
 // The backward passes; with target (mse), dL/dc_hat is formed from it in the
 // first kernel and the loss goes to loss_dev (if not null).
@@ -499,6 +549,8 @@ int backward_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* p
 }
 
 }  // namespace
+
+extern "C" {
 
 int ug_render_planes_backward(const ug_plan* plan, const ug_gaussians* g, const ug_planes* planes,
                               const float* image, const float* d_image, void* workspace, float* d_means,
@@ -693,6 +745,8 @@ const char* ug_status_string(int status) {
     case UG_ERR_HIP: return "HIP runtime error";
     case UG_ERR_NO_DEVICE: return "no gfx950 device available";
     case UG_ERR_INTERNAL: return "internal consistency check failed (please report)";
+    case UG_ERR_SCRATCH_SIZE:
+      return "the plan needs more workspace than the no-allocation forward holds (UG_NOALLOC_WORKSPACE_BYTES)";
     default: return "unknown status";
   }
 }

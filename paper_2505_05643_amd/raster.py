@@ -177,6 +177,17 @@ class Plan:
                 check(code, "render status")
         return image
 
+    def render_noalloc(self, g: GaussianTensors, planes: PlaneTensors, image: torch.Tensor) -> torch.Tensor:
+        """The forward through ug_render_planes_noalloc: the library's static
+        per-device workspace instead of this plan's (no backward follows it,
+        and its device status cannot be read)."""
+        cg, cp = _c_gauss(g), _c_planes(planes)
+        if image.numel() != self.num_pixels or not image.is_contiguous() or image.dtype != torch.float32:
+            raise ValueError("image must be a contiguous float32 tensor of num_pixels elements")
+        check(lib.ug_render_planes_noalloc(self._h, ctypes.byref(cg), ctypes.byref(cp), image.data_ptr(), _stream()),
+              "ug_render_planes_noalloc")
+        return image
+
     def backward(self, g: GaussianTensors, planes: PlaneTensors, image: torch.Tensor, d_image: torch.Tensor,
                  grads: GaussianTensors | None = None, accumulate: bool = False) -> GaussianTensors:
         cg, cp = _c_gauss(g), _c_planes(planes)
