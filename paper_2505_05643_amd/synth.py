@@ -304,6 +304,27 @@ def config4_training_pool() -> Planes:
     return pack_planes(frames, origins, np.ones((2048, 2)), np.tile([256, 256], (2048, 1)))
 
 
+def rescale(g: Gaussians | None, planes: Planes | None, factor: float, beta: float = DEFAULT_BETA):
+    """The same scene in world units multiplied by ``factor`` (positions,
+    plane origins and pixel spacings scaled; precisions by 1 / factor^2, so
+    the factor L by 1 / factor: l_kk'^2 + beta = (l_kk^2 + beta) / factor).
+    Every squared distance, hence every image, is unchanged up to rounding.
+    Returns (gaussians, planes); either input may be None."""
+    go = po = None
+    if g is not None:
+        lr = g.lraw.astype(np.float64)
+        inv = 1.0 / factor
+        out = lr * inv
+        for j in (0, 3, 5):
+            out[:, j] = np.sqrt(lr[:, j] ** 2 * inv + (inv - 1.0) * beta)
+        go = Gaussians((g.means.astype(np.float64) * factor).astype(np.float32), out.astype(np.float32),
+                       g.intensity.copy(), g.opacity.copy())
+    if planes is not None:
+        po = Planes(planes.rot.copy(), (planes.origin.astype(np.float64) * factor).astype(np.float32),
+                    (planes.spacing.astype(np.float64) * factor).astype(np.float32), planes.wh.copy())
+    return go, po
+
+
 def config_gaussians(k: int, seed: int | None = None, target: bool = False) -> Gaussians:
     seed = (200 if target else 100) + k if seed is None else seed
     if k == 0:

@@ -92,3 +92,41 @@ def test_param_study_inputs_shapes_and_distances():
     w = np.einsum("nji,nj->ni", d["rots"], d["delta"].astype(np.float64)) / s
     length = np.linalg.norm(w, axis=1)
     assert length.min() >= 0.5 - 1e-3 and length.max() <= 2.8 + 1e-3
+
+
+def test_rescale_keeps_every_squared_distance():
+    # positions, origins and spacings scale by f, the precision by 1/f^2: the
+    # factor L (diagonal l^2 + beta) by 1/f, so d^2 = |L^T (X - mu)|^2 of a
+    # pixel point and a Gaussian is the same in both frames
+    g = synth.make_gaussians(40, 8, (0, 0, 0), (256, 256, 256), (0.5, 8.0))
+    pl = synth.random_planes(2, 9, (16, 12), 4.0, 100, 150)
+    f = 1.0 / 256.0
+    g2, pl2 = synth.rescale(g, pl, f)
+    beta = synth.DEFAULT_BETA
+
+    def factor(lr):
+        lr = lr.astype(np.float64)
+        L = np.zeros((lr.shape[0], 3, 3))
+        L[:, 0, 0] = lr[:, 0] ** 2 + beta
+        L[:, 1, 0], L[:, 2, 0] = lr[:, 1], lr[:, 2]
+        L[:, 1, 1] = lr[:, 3] ** 2 + beta
+        L[:, 2, 1] = lr[:, 4]
+        L[:, 2, 2] = lr[:, 5] ** 2 + beta
+        return L
+
+    np.testing.assert_allclose(factor(g2.lraw), factor(g.lraw) / f, rtol=2e-6)
+    np.testing.assert_allclose(g2.means, g.means * f, rtol=1e-6)
+    np.testing.assert_allclose(pl2.origin, pl.origin * f, rtol=1e-6)
+    np.testing.assert_allclose(pl2.spacing, pl.spacing * f, rtol=1e-6)
+    assert np.array_equal(pl2.rot, pl.rot) and np.array_equal(pl2.wh, pl.wh)
+    assert np.array_equal(g2.intensity, g.intensity) and np.array_equal(g2.opacity, g.opacity)
+
+    def d2(gg, pp):
+        R = pp.rot[0].astype(np.float64).reshape(3, 3)
+        x = (np.arange(16) + 0.5 - 8) * pp.spacing[0, 0]
+        y = (np.arange(12) + 0.5 - 6) * pp.spacing[0, 1]
+        X = pp.origin[0].astype(np.float64) + x[None, :, None] * R[:, 0] + y[:, None, None] * R[:, 1]
+        delta = X.reshape(-1, 1, 3) - gg.means.astype(np.float64)[None]
+        return np.sum(np.einsum("nji,pnj->pni", factor(gg.lraw), delta) ** 2, axis=2)
+
+    np.testing.assert_allclose(d2(g2, pl2), d2(g, pl), rtol=1e-5, atol=1e-6)
