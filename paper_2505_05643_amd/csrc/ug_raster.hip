@@ -248,12 +248,22 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const PlaneInt* __restrict__ p
 }
 
 // ---------------------------------------------------------------- backward
-// A wave loads 64 keys; their touched 8x8 sub-blocks become items (key,
-// sub-block), queued in key order, and lanes = items (64 pixels each).  An
-// item's seven sums go to an LDS slot; once a sub-chunk's items are done
-// each key adds its slots in sub-block order.  A sub-chunk is the longest
-// run of the wave's keys whose items fit the slots (at least one key: a key
-// has at most 16 items).
+// A wave loads 64 keys.  Each key's touched 8x8 sub-blocks become items
+// (key, sub-block), queued in key order.  For every item a first pass over
+// the queue (lanes = items) finds the rows of its sub-block that can hold a
+// pixel inside the record's ellipse: row y can only if the larger of the
+// exponents at the strip's two end columns -- or the row exponent itself
+// when t1 changes sign across the strip -- passes the cut-off (t1 is
+// monotone along the row, so no pixel between the ends does better); the
+// first and last such rows bound the item.  Items are then ranked by their
+// row count, largest first, and the evaluation pass (lanes = items in that
+// order) walks 64 items with similar row counts together, each lane
+// accumulating the record's seven sums over its rows in registers into the
+// item's LDS slot.  Once a sub-chunk's items are done each key adds its
+// slots in sub-block order.  A sub-chunk is the longest run of the wave's
+// keys whose items fit the slots (at least one key: a key has at most 16
+// items).  Rows an item skips would only add exact zeros, so the sums are
+// those of walking all 64 pixels of every touched sub-block.
 constexpr int kBwdSlots = 192;
 
 template <int TW, int TH>
@@ -266,13 +276,14 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
                                                    const float2* __restrict__ gq, float4* __restrict__ partial) {
   constexpr int K = TW / kSubBlock, Q = K * (TH / kSubBlock);
   constexpr int kMaskShift = key_mask_shift(TW, TH);
-  static_assert(Q <= 16 && kBwdSlots >= Q, "sub-blocks per tile");
+  static_assert(Q <= 16 && kBwdSlots >= Q && kBwdSlots <= 256, "sub-blocks per tile; slot ids fit a byte");
   __shared__ float4 kpA[4][64];     // t11, t12, t22, -t11 du0
   __shared__ float4 kpB[4][64];     // du0, dv0, e0, emin
   __shared__ float kpC[4][64];      // c
   __shared__ uint32_t kpT[4][64];   // tile
   __shared__ uint32_t qoff[4][65];  // first item of each key
-  __shared__ uint16_t queue[4][kBwdSlots];
+  __shared__ uint32_t queue[4][kBwdSlots];   // key | sub-block << 6 | first row << 10 | rows << 13
+  __shared__ uint8_t order[4][kBwdSlots];    // items with rows, by row count (largest first)
   __shared__ float slot[4][7][kBwdSlots];
   const uint32_t n = ctrl->n_key_eff;
   const float ln2 = (float)kLn2;
@@ -324,68 +335,138 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
         uint32_t q = off - base;
         while (mm) {
           const uint32_t sb = (uint32_t)__builtin_ctz(mm);
-          queue[wave][q++] = (uint16_t)((uint32_t)lane | (sb << 8));
+          queue[wave][q++] = (uint32_t)lane | sb << 6;
           mm &= mm - 1u;
         }
       }
       wave_lds_sync();
-      // ---- lanes = items: 8x8 pixels of one key each
+      // ---- lanes = items: the rows each item can reach; counts per row count
+      uint32_t bucket_tot[kSubBlock + 1];
+#pragma unroll
+      for (int b = 0; b <= kSubBlock; ++b) bucket_tot[b] = 0u;
       for (uint32_t q0 = 0; q0 < L; q0 += 64) {
         const uint32_t q = q0 + (uint32_t)lane;
         const bool has = q < L;
-        const uint32_t ent = has ? (uint32_t)queue[wave][q] : (uint32_t)k0;
-        const int kl = (int)(ent & 255u), sb = (int)(ent >> 8);
+        const uint32_t ent = has ? queue[wave][q] : (uint32_t)k0;
+        const int kl = (int)(ent & 63u), sb = (int)((ent >> 6) & 15u);
+        const float4 a = kpA[wave][kl];
+        const float4 b = kpB[wave][kl];
+        const float xa = (float)((sb % K) * kSubBlock), xb = xa + (float)(kSubBlock - 1);
+        const int by = (sb / K) * kSubBlock;
+        int ya = kSubBlock, yb = -1;
+#pragma unroll
+        for (int y = 0; y < kSubBlock; ++y) {
+          const float dv = (float)(by + y) - b.y;
+          const float B = fmaf(a.y, dv, a.w);
+          const float t2 = a.z * dv;
+          const float erow = fmaf(-t2, t2, b.z);
+          const float ta = fmaf(a.x, xa, B), tb = fmaf(a.x, xb, B);
+          const float tm = fabsf(ta) < fabsf(tb) ? ta : tb;
+          const float best = (ta <= 0.f) != (tb <= 0.f) ? erow : fmaf(-tm, tm, erow);
+          if (best >= b.w) {
+            ya = y < ya ? y : ya;
+            yb = y;
+          }
+        }
+        const int nr = has && yb >= ya ? yb - ya + 1 : 0;
+        if (has) {
+          queue[wave][q] = ent | (uint32_t)(nr ? ya : 0) << 10 | (uint32_t)nr << 13;
+          if (nr == 0) {  // no pixel of the sub-block is inside: its sums are zero
+#pragma unroll
+            for (int f = 0; f < 7; ++f) slot[wave][f][q] = 0.f;
+          }
+        }
+#pragma unroll
+        for (int r = 1; r <= kSubBlock; ++r) bucket_tot[r] += (uint32_t)__popcll(__ballot(nr == r));
+      }
+      // bucket starts, largest row count first
+      uint32_t bstart[kSubBlock + 1];
+      uint32_t run = 0u;
+#pragma unroll
+      for (int r = kSubBlock; r >= 1; --r) {
+        bstart[r] = run;
+        run += bucket_tot[r];
+      }
+      const uint32_t Ls = run;  // items with rows
+      wave_lds_sync();
+      for (uint32_t q0 = 0; q0 < L; q0 += 64) {
+        const uint32_t q = q0 + (uint32_t)lane;
+        const uint32_t nr = q < L ? queue[wave][q] >> 13 : 0u;
+        uint32_t pos = 0u;
+#pragma unroll
+        for (int r = 1; r <= kSubBlock; ++r) {
+          const unsigned long long bal = __ballot(nr == (uint32_t)r);
+          if (nr == (uint32_t)r) pos = bstart[r] + lanemask_lt_popc(bal);
+          bstart[r] += (uint32_t)__popcll(bal);
+        }
+        if (nr) order[wave][pos] = (uint8_t)q;
+      }
+      wave_lds_sync();
+      // ---- lanes = items by row count: the rows of one key's sub-block
+      for (uint32_t s0 = 0; s0 < Ls; s0 += 64) {
+        const uint32_t sidx = s0 + (uint32_t)lane;
+        const bool has = sidx < Ls;
+        const uint32_t q = has ? (uint32_t)order[wave][sidx] : 0u;
+        const uint32_t ent = has ? queue[wave][q] : (uint32_t)k0;
+        const int kl = (int)(ent & 63u), sb = (int)((ent >> 6) & 15u);
+        const int ry = (int)((ent >> 10) & 7u), nr = has ? (int)(ent >> 13) : 0;
         const float4 a = kpA[wave][kl];
         const float4 b = kpB[wave][kl];
         const float c = kpC[wave][kl];
         const uint32_t t = kpT[wave][kl];
         const float t11 = a.x, t12 = a.y, t22 = a.z, P = a.w;
-        const float e0 = b.z, emin = has ? b.w : INFINITY;
-        const int bx = (sb % K) * kSubBlock, by = (sb / K) * kSubBlock;
-        const float4* __restrict__ pq = reinterpret_cast<const float4*>(gq + (size_t)t * (TW * TH) + by * TW + bx);
+        const float e0 = b.z, emin = b.w;
+        const int bx0 = (sb % K) * kSubBlock, by = (sb / K) * kSubBlock + ry;
+        const float4* __restrict__ pq = reinterpret_cast<const float4*>(gq + (size_t)t * (TW * TH) + by * TW + bx0);
         float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
-        // rows of gamma are fetched one row ahead of their use
+        // row y of the item for y < nr; later rows (and lanes without an
+        // item) re-read the item's last row (or the key's first) with a
+        // cut-off no weight passes, so they add exact zeros.  The loop ends
+        // once no lane of the wave has rows left; rows of gamma are fetched
+        // one row ahead of their use.
+        const int nlast = nr > 0 ? nr - 1 : 0;
         float4 cur[kSubBlock / 2];
 #pragma unroll
         for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = pq[x2];
 #pragma unroll
         for (int y = 0; y < kSubBlock; ++y) {
+          if (!__any(y < nr)) break;  // uniform
           float4 nxt[kSubBlock / 2];
           if (y + 1 < kSubBlock) {
+            const int yn = y + 1 < nlast ? y + 1 : nlast;
 #pragma unroll
-            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) nxt[x2] = pq[(y + 1) * (TW / 2) + x2];
+            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) nxt[x2] = pq[yn * (TW / 2) + x2];
           }
+          const float lim = y < nr ? emin : INFINITY;
           const float dv = (float)(by + y) - b.y;
           const float B = fmaf(t12, dv, P);
           const float t2 = t22 * dv;
           const float erow = fmaf(-t2, t2, e0);
-          if (__any(erow >= emin)) {  // else no item's ellipse reaches this row
-            float rge = 0.f, ra = 0.f;
+          float rge = 0.f, ra = 0.f;
 #pragma unroll
-            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) {
-              const float4 gg2 = cur[x2];
+          for (int x2 = 0; x2 < kSubBlock / 2; ++x2) {
+            const float4 gg2 = cur[x2];
 #pragma unroll
-              for (int h = 0; h < 2; ++h) {
-                const float gx = h ? gg2.z : gg2.x, gy = h ? gg2.w : gg2.y;
-                const float xf = (float)(bx + 2 * x2 + h);
-                const float t1 = fmaf(t11, xf, B);
-                const float ee = fmaf(-t1, t1, erow);
-                const float w = ee >= emin ? fast_exp2(ee) : 0.f;
-                const float gw = fmaf(gx, c, -gy);  // dL/dw = gamma (c - c_hat)
-                const float ge = w * gw;
-                rge += ge;
-                Sdc = fmaf(gx, w, Sdc);
-                const float av = ge * t1;
-                ra += av;
-                Sau = fmaf(av, xf, Sau);
-              }
+            for (int h = 0; h < 2; ++h) {
+              const float gx = h ? gg2.z : gg2.x, gy = h ? gg2.w : gg2.y;
+              const float xf = (float)(bx0 + 2 * x2 + h);
+              const float t1 = fmaf(t11, xf, B);
+              const float ee = fmaf(-t1, t1, erow);
+              const float w = ee >= lim ? fast_exp2(ee) : 0.f;
+              const float gw = fmaf(gx, c, -gy);  // dL/dw = gamma (c - c_hat)
+              const float ge = w * gw;
+              rge += ge;
+              Sdc = fmaf(gx, w, Sdc);
+              const float av = ge * t1;
+              ra += av;
+              Sau = fmaf(av, xf, Sau);
             }
-            Sge += rge;
-            Sa += ra;
-            S12 = fmaf(dv, ra, S12);
-            Sb = fmaf(t2, rge, Sb);
-            S22 = fmaf(t2 * dv, rge, S22);
           }
+          Sge += rge;
+          Sa += ra;
+          S12 = fmaf(dv, ra, S12);
+          Sb = fmaf(t2, rge, Sb);
+          S22 = fmaf(t2 * dv, rge, S22);
           if (y + 1 < kSubBlock) {
 #pragma unroll
             for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = nxt[x2];
