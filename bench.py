@@ -498,23 +498,30 @@ def reconstruction(dev, steps):
                                "fp64_tflops": 240 * npx / (q_ms * 1e9)}}
 
 
-def config4_training(dev, params, steps: int, seed: int = 404) -> dict:
+def config4_training(dev, params, steps: int, seed: int = 404, check_every: int = 20) -> dict:
     """The 1M-Gaussian workload trained as stated: every step draws 256
     distinct planes of 256^2 (seeded) from the pool of 2,048 planes of 8
     interleaved oblique sweeps, gathers their poses and target images (the
     seed-204 Gaussian set rendered once on the whole pool) into the step's
     fixed buffers, and replays the captured step (render, MSE adjoint, Adam).
-    Then the trained Gaussians are extracted as the 256 axial planes of the
-    256^3 volume in one forward launch."""
+    The scene is expressed in the unit cube (the 256-voxel domain scaled by
+    1/256; images unchanged), the frame in which the Section 4.5 learning
+    rates are stated.  Every ``check_every`` steps the device step counter
+    recorded after each step is read: a step whose render overflowed its
+    capacity skipped its update on the device, so the plan is re-sized for the
+    current Gaussians on those draws, the step captured again and those steps
+    redone.  Then the trained Gaussians are extracted
+    as the 256 axial planes of the 256^3 volume in one forward launch."""
     import torch
     from paper_2505_05643_amd import raster as R
     from paper_2505_05643_amd import synth
     from paper_2505_05643_amd.step import AdamConfig, TrainStep
-    pool = synth.config4_training_pool()
+    unit = 1.0 / 256.0
+    _, pool = synth.rescale(None, synth.config4_training_pool(), unit)
     P, per = pool.p, 256
     wh = pool.wh[:per]
     pool_d = R.to_device(pool, dev)
-    tg = R.to_device(synth.config_gaussians(4, target=True), dev)
+    tg = R.to_device(synth.rescale(synth.config_gaussians(4, target=True), None, unit)[0], dev)
     tplan = R.Plan(tg.means.shape[0], wh, params, device=dev)
     npx = int(wh[0, 0] * wh[0, 1])
     targets = torch.empty(P, npx, device=dev)
@@ -528,15 +535,10 @@ def config4_training(dev, params, steps: int, seed: int = 404) -> dict:
     idx = torch.from_numpy(draws).to(dev)
     planes = R.PlaneTensors(*(t.index_select(0, idx[0]).contiguous() for t in pool_d))
     target = targets.index_select(0, idx[0]).reshape(-1).contiguous()
-    gauss = R.to_device(synth.config_gaussians(4), dev)
+    gauss = R.to_device(synth.rescale(synth.config_gaussians(4), None, unit)[0], dev)
     ts = TrainStep(gauss, planes, wh, target, params, adam=AdamConfig(decay_steps=steps), headroom=1.3)
-    # capacities for the largest of a few draws (a render that still overflows
-    # skips its Adam update on the device; such steps are counted below)
-    for j in np.linspace(0, steps - 1, 8).astype(int):
-        for dst, src in zip(planes, pool_d):
-            torch.index_select(src, 0, idx[j], out=dst)
-        ts.plan.fit(ts.params, planes, 1.3)
     loss = torch.zeros(steps, device=dev)
+    done_after = torch.zeros(steps, dtype=torch.int32, device=dev)  # device step counter after each step
 
     def gather(i):
         for dst, src in zip(planes, pool_d):
@@ -547,18 +549,40 @@ def config4_training(dev, params, steps: int, seed: int = 404) -> dict:
     ts.capture()
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    refits = redone = 0
     t0.record()
-    for i in range(steps):
-        gather(i)
-        ts.replay()
-        loss[i:i + 1].copy_(ts.loss_buf[:1])
+    todo = list(range(steps))
+    count = 0  # the device step counter before the window
+    while todo:
+        window, todo = todo[:check_every], todo[check_every:]
+        for i in window:
+            gather(i)
+            ts.replay()
+            loss[i:i + 1].copy_(ts.loss_buf[:1])
+            done_after[i:i + 1].copy_(ts.step_dev)
+        # the steps of this window whose Adam launch skipped itself (their
+        # render overflowed): the device counter did not advance
+        after = done_after[window].cpu().numpy().astype(np.int64)
+        before = np.concatenate([[count], after[:-1]])
+        skipped = [w for w, a, b0 in zip(window, after, before) if a == b0]
+        count = int(after[-1])
+        if skipped:
+            if refits >= 100:  # the Gaussians keep outgrowing every re-size: stop here
+                break
+            for w in skipped:  # capacities for the largest of the skipped draws
+                gather(w)
+                ts.plan.fit(ts.params, planes, 1.5)
+            ts.capture()
+            refits += 1
+            redone += len(skipped)
+            todo = skipped + todo
     t1.record()
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
     done = ts.step_count
+    ms = t0.elapsed_time(t1) / max(done, 1)
     lh = loss.cpu().numpy().astype(float)
     # extraction: the 256 axial planes of the volume, one forward launch
-    ext = synth.config_planes(4)
+    _, ext = synth.rescale(None, synth.config_planes(4), unit)
     ext_d = R.to_device(ext, dev)
     eplan = R.Plan(ts.params.means.shape[0], ext.wh, params, device=dev)
     eplan.fit(ts.params, ext_d)
@@ -567,10 +591,13 @@ def config4_training(dev, params, steps: int, seed: int = 404) -> dict:
     ok = eplan.status() == 0
     marks = sorted({0, 1, 10, 100, steps // 2, steps - 1} & set(range(steps)))
     return {"steps": steps, "planes_per_step": per, "pool_planes": P, "ms_per_step": ms,
-            "planes_per_s": per / (ms / 1e3), "adam_updates_done": done, "skipped_overflow": steps - done,
+            "planes_per_s": per / (ms / 1e3), "adam_updates_done": done, "capacity_refits": refits,
+            "steps_redone_after_overflow": redone,
             "loss_at_step": {str(m): lh[m] for m in marks},
             "loss_mean_first_100": float(np.mean(lh[:100])), "loss_mean_last_100": float(np.mean(lh[-100:])),
-            "launch": "gather (torch index_select) + captured step replay per step",
+            "frame": "unit cube (256-voxel domain scaled by 1/256)",
+            "launch": "gather (torch index_select) + captured step replay per step; step counter read every "
+                      f"{check_every} steps; ms_per_step = wall time incl. re-sizing and redone steps / updates done",
             "extraction_ms": ext_ms if ok else None, "extraction_planes": ext.p,
             "extraction_voxels_per_s": (eplan.num_pixels / (ext_ms / 1e3)) if ok else None}
 
