@@ -353,22 +353,21 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
         const float4 b = kpB[wave][kl];
         const float xa = (float)((sb % K) * kSubBlock), xb = xa + (float)(kSubBlock - 1);
         const int by = (sb / K) * kSubBlock;
-        int ya = kSubBlock, yb = -1;
+        uint32_t rows = 0u;
 #pragma unroll
         for (int y = 0; y < kSubBlock; ++y) {
           const float dv = (float)(by + y) - b.y;
           const float B = fmaf(a.y, dv, a.w);
           const float t2 = a.z * dv;
           const float erow = fmaf(-t2, t2, b.z);
+          // t1 at the strip's end columns; the median of (ta, 0, tb) is the
+          // end value nearest zero, or zero when t1 changes sign in between
           const float ta = fmaf(a.x, xa, B), tb = fmaf(a.x, xb, B);
-          const float tm = fabsf(ta) < fabsf(tb) ? ta : tb;
-          const float best = (ta <= 0.f) != (tb <= 0.f) ? erow : fmaf(-tm, tm, erow);
-          if (best >= b.w) {
-            ya = y < ya ? y : ya;
-            yb = y;
-          }
+          const float tm = __builtin_amdgcn_fmed3f(ta, 0.f, tb);
+          rows |= (fmaf(-tm, tm, erow) >= b.w ? 1u : 0u) << y;
         }
-        const int nr = has && yb >= ya ? yb - ya + 1 : 0;
+        const int ya = rows ? __builtin_ctz(rows) : 0, yb = rows ? 31 - __builtin_clz(rows) : -1;
+        const int nr = has && rows ? yb - ya + 1 : 0;
         if (has) {
           queue[wave][q] = ent | (uint32_t)(nr ? ya : 0) << 10 | (uint32_t)nr << 13;
           if (nr == 0) {  // no pixel of the sub-block is inside: its sums are zero
