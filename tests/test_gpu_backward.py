@@ -250,3 +250,78 @@ def test_config4_training_pool_planes(R):
     print("pool planes", sel.tolist(), check_image(img[flat], g, pl, plan.params, pix=pix, ref=ref))
     gref = reference_grad(g, X, vals.astype(np.float64), plan.params)
     print("pool planes grads", check_grads(gg, gref))
+
+
+def test_config1_gradients_vs_fp64_finite_differences(R):
+    """The 50k-Gaussian 16-plane sweep with its gradients checked against
+    FP64 finite differences of the oracle, at full size and in the tuned
+    launch configuration.  Twelve seeded Gaussians (footprints of at most
+    2,000 pixels over all planes) each get one seeded raw parameter; the
+    upstream gradient is non-zero on the pixels those Gaussians touch, minus
+    every pixel with a borderline pair (|d^2 - chi^2| <= 2e-4: the FP32 and
+    FP64 inclusion sets agree elsewhere).  A central difference of
+    L = sum dout c_hat only needs the pixels the perturbed Gaussian touches
+    (the others do not move); it is taken only where no pair of that
+    Gaussian changes side of the cut-off between theta - h and theta + h."""
+    from oracle import pool
+    from tests.configs import tuned_params
+    from tests.parity import oracle_params
+    g, pl, _ = synth.make_config(1)
+    params = tuned_params(g, pl)
+    op = oracle_params(params)
+    X = oracle.plane_points(pl)
+    rng = np.random.default_rng(4101)
+    chosen, touched = [], []
+    for i in rng.permutation(g.n):
+        d2 = oracle.d2_points(g.subset(np.array([i])), X, op)[:, 0]
+        t = np.nonzero(d2 <= op.chi2 * 1.01)[0]
+        if 50 <= t.size <= 2000:
+            chosen.append(int(i))
+            touched.append(t)
+        if len(chosen) == 12:
+            break
+    S = np.unique(np.concatenate(touched))
+    _, _, k = pool.ambiguity_points(g, X[S], op)
+    S = S[k == 0]
+    dimg = np.zeros(pl.npix, dtype=np.float32)
+    dimg[S] = rng.standard_normal(S.size).astype(np.float32)
+    _, gg, _ = _fwd_bwd(R, g, pl, dimg, params)
+    base = {f: np.array(getattr(g, f), dtype=np.float64) for f in ("means", "lraw", "intensity", "opacity")}
+    fields = [("means", j) for j in range(3)] + [("lraw", j) for j in range(6)] + [("intensity", None),
+                                                                                  ("opacity", None)]
+    # Gaussians that can reach a point: |x - mu| <= sqrt(chi^2) sigma_max
+    # (d^2 >= |x - mu|^2 / sigma_max^2), so the others add exact zeros there
+    sig_max = np.sqrt(np.linalg.eigvalsh(oracle.covariance(g.lraw, op.beta))[:, -1])
+    reach = np.sqrt(op.chi2) * sig_max * 1.001 + 1e-9
+    mu = np.asarray(g.means, dtype=np.float64)
+    checked = 0
+    for i, t in zip(chosen, touched):
+        f, j = fields[int(rng.integers(len(fields)))]
+        x0 = base[f][i] if j is None else base[f][i, j]
+        h = 1e-6 * max(1.0, abs(x0))
+        moved = []
+        for sgn in (1.0, -1.0):
+            a = {kk: vv.copy() for kk, vv in base.items()}
+            if j is None:
+                a[f][i] += sgn * h
+            else:
+                a[f][i, j] += sgn * h
+            moved.append(synth.Gaussians(**a))
+        d2p = oracle.d2_points(moved[0].subset(np.array([i])), X, op)[:, 0]
+        d2m = oracle.d2_points(moved[1].subset(np.array([i])), X, op)[:, 0]
+        if np.any((d2p <= op.chi2) != (d2m <= op.chi2)):
+            continue  # a pair of this Gaussian crosses the cut-off within the step
+        P = np.nonzero(((d2p <= op.chi2) | (d2m <= op.chi2)) & (dimg != 0))[0]
+        lo, hi = X[P].min(axis=0), X[P].max(axis=0)
+        gap = np.linalg.norm(np.maximum(np.maximum(lo - mu, mu - hi), 0.0), axis=1)
+        near = np.nonzero(gap <= reach)[0]
+        assert i in near
+        lp = oracle.render_points(moved[0].subset(near), X[P], op)[0] @ dimg[P].astype(np.float64)
+        lm = oracle.render_points(moved[1].subset(near), X[P], op)[0] @ dimg[P].astype(np.float64)
+        fd = (lp - lm) / (2 * h)
+        got = gg[f][i] if j is None else gg[f][i, j]
+        scale = float(np.abs(gg[f]).max())
+        assert abs(got - fd) <= 1e-3 * abs(fd) + 1e-5 * scale, (i, f, j, got, fd, scale)
+        checked += 1
+    assert checked >= 8, f"only {checked} parameters were free of cut-off crossings"
+    print(f"c1 finite differences: {checked} parameters, {S.size} upstream pixels")
