@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--tile", type=str, default=None, help="WxH[xPPL], e.g. 16x16x1")
     ap.add_argument("--lds-batch", type=int, default=None)
     ap.add_argument("--box", type=int, default=None, help="0 paper, 1 conic, 2 rows")
+    ap.add_argument("--split", type=int, default=None, choices=(0, 1),
+                    help="forward with two waves per 8-row band (UG_FLAG_SPLIT_FORWARD)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-plane comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scatter", action="store_true", help="skip timing the Phase-2 atomic scatter forward")
@@ -142,7 +144,7 @@ def main():
 
     params = R.Params()
     tuned = None
-    if not (args.tile or args.lds_batch or args.box is not None or args.no_autotune):
+    if not (args.tile or args.lds_batch or args.box is not None or args.split is not None or args.no_autotune):
         from paper_2505_05643_amd import autotune
         cache = args.tune_cache or autotune.CACHE
         sig = autotune.signature(g.n, pl.wh)
@@ -166,6 +168,9 @@ def main():
         params.lds_batch = args.lds_batch
     if args.box is not None:
         params.box_mode = args.box
+    if args.split is not None:
+        params.flags = (params.flags | R._lib.UG_FLAG_SPLIT_FORWARD) if args.split else (
+            params.flags & ~R._lib.UG_FLAG_SPLIT_FORWARD)
 
     # target image: the second seeded Gaussian set rendered on the same planes
     tplan = R.Plan(tg.n, pl.wh, params, device=dev)
@@ -294,7 +299,7 @@ def main():
         progress("Phase-2 scatter forms timed")
 
     # in-support pairs of one forward, counted by the kernel itself
-    cparams = R.Params(**{**params.__dict__, "flags": 1})
+    cparams = R.Params(**{**params.__dict__, "flags": params.flags | R._lib.UG_FLAG_COUNT_EVALS})
     cplan = R.Plan(g.n, pl.wh, cparams, device=dev)
     cplan.fit(gd, pd)
     cimg = cplan.render(gd, pd)
@@ -410,6 +415,7 @@ def main():
         "config": {"workload": synth.CONFIG_NAMES[k], "gaussians": g.n, "planes": pl.p,
                    "pixels": int(pl.npix), "tile": f"{params.tile_w}x{params.tile_h}",
                    "px_per_lane": plan_ppl(params), "lds_batch": params.lds_batch, "box_mode": params.box_mode,
+                   "split_forward": bool(params.flags & R._lib.UG_FLAG_SPLIT_FORWARD),
                    "step": "render + MSE adjoint (gradient of the loss formed in the first adjoint kernel)",
                    "launch": "hipGraph replay" if graph_ms_step is not None else "eager"},
         "autotune": tuned,
@@ -767,7 +773,10 @@ def stored_traffic(kernel, k, params, plan):
         rec = json.loads(line[len("traffic-json: "):]) if line else {}
     except (OSError, ValueError):
         return None
-    key = f"c{k}:{kernel}:{params.tile_w}x{params.tile_h}x{plan_ppl(params)}:{params.lds_batch}:{params.box_mode}"
+    from paper_2505_05643_amd import _lib
+    split = ":split" if params.flags & _lib.UG_FLAG_SPLIT_FORWARD else ""
+    key = (f"c{k}:{kernel}:{params.tile_w}x{params.tile_h}x{plan_ppl(params)}:{params.lds_batch}:{params.box_mode}"
+           f"{split}")
     if rec.get("sources") != sources_digest():
         return None
     return rec.get("bytes_per_launch", {}).get(key)

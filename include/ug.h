@@ -72,6 +72,14 @@ extern "C" {
                                  box corners outside the chi^2 ellipse count and the
                                  image differs from the ellipsoid support.  box_mode is
                                  ignored.  Without UG_FLAG_SCATTER: UG_ERR_INVALID_ARG */
+#define UG_FLAG_SPLIT_FORWARD 8 /* launch shape of the gather forward: two waves per 8-row
+                                 band of a tile, each summing alternate rounds of lds_batch
+                                 records, their sums added at the end (first + second).
+                                 More waves for launches with few tiles; each pixel's sum
+                                 is then grouped differently, so the image may differ from
+                                 the one-wave form in the last bits (still deterministic).
+                                 Not with tile_h = 32 and lds_batch = 256 (the staging
+                                 would exceed 128 KB of LDS): UG_ERR_INVALID_ARG */
 
 /* ---- pipeline stages (measurement hooks) ------------------------------- */
 #define UG_STAGE_SETUP 0         /* plane pose set-up                                  */

@@ -1,9 +1,10 @@
 """Launch-configuration autotuner for the probe-plane rasterizer.
 
-Searches tile shape, pixels per lane, LDS batch and binning box for a given
-workload by timing the library's own forward + backward on the device, and
-checks that every candidate renders the same image and back-propagates the
-same gradients: bit for bit within a tile shape; across shapes the
+Searches tile shape, pixels per lane, LDS batch, binning box and the
+forward's split (UG_FLAG_SPLIT_FORWARD) for a given workload by timing the
+library's own forward + backward on the device, and checks that every
+candidate renders the same image and back-propagates the same gradients:
+bit for bit within a tile shape (the split: shape, batch and box); across them the
 tile-relative FP32 coordinates round differently, so images to 2e-5 of the
 peak (a fifth of the parity tolerance) except for rare pixels whose pair
 sits on the cut-off, and gradients as GRAD_REL below says.  Results can be cached per
@@ -100,14 +101,19 @@ def tune(g: R.GaussianTensors, planes: R.PlaneTensors, wh, base: R.Params | None
     d_probe = torch.from_numpy(rng.standard_normal(int(np.sum(wh_pr[:, 0].astype(np.int64) * wh_pr[:, 1])))
                                .astype(np.float32)).to(g.means.device)
 
-    def run(tw, th, ppl, bg, box):
+    def run(tw, th, ppl, bg, box, split=False):
         nonlocal peak
-        prm = dataclasses.replace(base, tile_w=tw, tile_h=th, px_per_lane=ppl, lds_batch=bg, box_mode=box)
+        flags = (base.flags | R._lib.UG_FLAG_SPLIT_FORWARD) if split else (base.flags & ~R._lib.UG_FLAG_SPLIT_FORWARD)
+        prm = dataclasses.replace(base, tile_w=tw, tile_h=th, px_per_lane=ppl, lds_batch=bg, box_mode=box,
+                                  flags=flags)
         ms, img, st, grads = _time_candidate(prm, g, planes, wh, d_image, steps)
         probe = _probe_grads(prm, g_pr, pl_pr, wh_pr, d_probe) if n_pr > 0 else []
         if peak is None:
             peak = float(img.abs().max())
-        key = (tw, th)
+        # the split forward groups each pixel's sum by alternate rounds of
+        # lds_batch keys, so its image also depends on the batch and on the
+        # binning (which keys a tile holds)
+        key = (tw, th, bg, box) if split else (tw, th)
         off = 0
         gerr = {}
         if key in ref_img:
@@ -140,7 +146,8 @@ def tune(g: R.GaussianTensors, planes: R.PlaneTensors, wh, base: R.Params | None
             off = int(((img - first).abs() > 2e-5 * max(peak, 1e-30)).sum())
             if off > max(1, 1e-4 * img.numel()):
                 raise RuntimeError(f"candidate {prm}: {off} pixels differ from the first tile shape")
-        rec = {"tile_w": tw, "tile_h": th, "px_per_lane": ppl, "lds_batch": bg, "box_mode": box, "ms": ms,
+        rec = {"tile_w": tw, "tile_h": th, "px_per_lane": ppl, "lds_batch": bg, "box_mode": box,
+               "split_forward": split, "ms": ms,
                "records": st[1], "keys": st[2], "cutoff_flips": off,
                "grad_vs_first_shape": {k: {"workload_normwise": v[0], "probe_max_by_largest": v[1]}
                                        for k, v in gerr.items()}}
@@ -157,10 +164,21 @@ def tune(g: R.GaussianTensors, planes: R.PlaneTensors, wh, base: R.Params | None
         for bg in batches:
             if bg != 64:
                 run(b["tile_w"], b["tile_h"], b["px_per_lane"], bg, b["box_mode"])
+    # the forward split (two waves per band) for the three best so far
+    for b in sorted(results, key=lambda r: r["ms"])[:3]:
+        if split_ok(b["tile_h"], b["lds_batch"]):
+            run(b["tile_w"], b["tile_h"], b["px_per_lane"], b["lds_batch"], b["box_mode"], split=True)
     top = min(results, key=lambda r: r["ms"])
+    flags = base.flags | R._lib.UG_FLAG_SPLIT_FORWARD if top["split_forward"] else base.flags
     params = dataclasses.replace(base, tile_w=top["tile_w"], tile_h=top["tile_h"], px_per_lane=top["px_per_lane"],
-                                 lds_batch=top["lds_batch"], box_mode=top["box_mode"])
+                                 lds_batch=top["lds_batch"], box_mode=top["box_mode"], flags=flags)
     return params, results
+
+
+def split_ok(tile_h: int, lds_batch: int) -> bool:
+    """The split forward's staging fits (tile_h / 8 bands x 2 waves x
+    max(batch, 64) records x 80 B <= 128 KB)."""
+    return (tile_h // 8) * 2 * max(lds_batch, 64) * 80 <= 128 * 1024
 
 
 def load_cache(path: str = CACHE) -> dict:
@@ -174,13 +192,16 @@ def cached_params(sig: str, path: str = CACHE) -> R.Params | None:
     entry = load_cache(path).get(sig)
     if entry is None:
         return None
-    return R.Params(**{k: entry[k] for k in ("tile_w", "tile_h", "px_per_lane", "lds_batch", "box_mode")})
+    prm = R.Params(**{k: entry[k] for k in ("tile_w", "tile_h", "px_per_lane", "lds_batch", "box_mode")})
+    prm.flags = int(entry.get("flags", 0))
+    return prm
 
 
 def store(sig: str, params: R.Params, ms: float, path: str = CACHE):
     cache = load_cache(path)
     cache[sig] = {"tile_w": params.tile_w, "tile_h": params.tile_h, "px_per_lane": params.px_per_lane,
-                  "lds_batch": params.lds_batch, "box_mode": params.box_mode, "ms": ms}
+                  "lds_batch": params.lds_batch, "box_mode": params.box_mode,
+                  "flags": params.flags & R._lib.UG_FLAG_SPLIT_FORWARD, "ms": ms}
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)

@@ -117,9 +117,15 @@ bool valid_params(const ug_params& p) {
   if (!(p.bg_alpha > 0.f) || !std::isfinite(p.bg_alpha)) return false;
   if (!std::isfinite(p.bg_color)) return false;
   if (p.box_mode != UG_BOX_PAPER && p.box_mode != UG_BOX_CONIC && p.box_mode != UG_BOX_ROWS) return false;
-  if ((p.flags & ~(UG_FLAG_COUNT_EVALS | UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT)) != 0) return false;
+  if ((p.flags & ~(UG_FLAG_COUNT_EVALS | UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT | UG_FLAG_SPLIT_FORWARD)) != 0)
+    return false;
   if ((p.flags & UG_FLAG_BOX_SUPPORT) && !(p.flags & UG_FLAG_SCATTER)) return false;
   const int ppl = p.px_per_lane ? p.px_per_lane : accum_default_ppl(p.tile_w, p.tile_h);
+  // the split forward doubles the staging LDS: (TH / 8) bands x 2 waves x
+  // max(batch, 64) records x 80 B, kept within 128 KB
+  if ((p.flags & UG_FLAG_SPLIT_FORWARD) &&
+      (size_t)(p.tile_h / 8) * 2 * (size_t)(p.lds_batch > 64 ? p.lds_batch : 64) * 80 > (size_t)128 * 1024)
+    return false;
   return accum_config_supported(p.tile_w, p.tile_h, ppl, p.lds_batch);
 }
 
@@ -492,7 +498,8 @@ int render_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* pla
   if (e != hipSuccess) return UG_ERR_HIP;
   unsigned long long* n_eval = (plan->prm.flags & UG_FLAG_COUNT_EVALS) ? &ctrl->n_eval : nullptr;
   StageScope sc(plan, UG_STAGE_ACCUM, s);
-  e = launch_accum_fwd(plan->prm.tile_w, plan->prm.tile_h, plan->prm.lds_batch, plan->d_pint, plan->d_tile_plane,
+  e = launch_accum_fwd(plan->prm.tile_w, plan->prm.tile_h, plan->prm.lds_batch,
+                       (plan->prm.flags & UG_FLAG_SPLIT_FORWARD) ? 2 : 1, plan->d_pint, plan->d_tile_plane,
                        at<uint32_t>(ws, L.tile_start), so.key, so.rec, at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), image, at<float>(ws, L.dsave),
                        plan->prm.bg_alpha, plan->prm.bg_color, plan->num_tiles, n_eval, s);
   return hip_status(e);

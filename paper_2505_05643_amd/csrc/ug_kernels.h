@@ -111,10 +111,12 @@ hipError_t launch_probe(int kind, int blocks, int iters, const float* src, float
 // ---- accumulate (ug_raster.hip)
 int accum_default_ppl(int tile_w, int tile_h);
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);
-hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneInt* pint, const uint32_t* tile_plane,
-                            const uint32_t* tile_start, const uint32_t* skey, const uint32_t* srec,
-                            const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave, float bg_alpha,
-                            float bg_color, uint32_t num_tiles, unsigned long long* n_eval, hipStream_t s);
+// split = 2: two waves per 8-row band, taking alternate rounds of records.
+hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, int split, const PlaneInt* pint,
+                            const uint32_t* tile_plane, const uint32_t* tile_start, const uint32_t* skey,
+                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave,
+                            float bg_alpha, float bg_color, uint32_t num_tiles, unsigned long long* n_eval,
+                            hipStream_t s);
 // second = dL/dc_hat, or (mse) the target with dL/dc_hat = scale (image -
 // target) formed inside and per-block squared-difference sums in loss_part
 // (bwd_prep_blocks floats).

@@ -6,8 +6,10 @@
 // key emission), so both passes evaluate (record, pixel) pairs only inside
 // touched sub-blocks.
 //
-// Forward: one workgroup per tile, one wave per band of 8 pixel rows, lanes
-// = pixels (a lane owns one pixel in each of the band's TW/8 sub-blocks).
+// Forward: one workgroup per tile, one wave per band of 8 pixel rows (or two,
+// SPLIT = 2, taking alternate rounds of the tile's records and adding their
+// sums at the end), lanes = pixels (a lane owns one pixel in each of the
+// band's TW/8 sub-blocks).
 // Each wave streams the tile's records (sorted by record id, so every pixel
 // sums its Gaussians in the same order whatever the launch shape), keeps
 // those whose mask touches its band in a wave-private LDS list and walks the
@@ -31,8 +33,8 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 // counters[1] (a measurement variant; one more VALU op per pair).  BG records
 // are staged per wave and round (PER per lane; lanes beyond BG idle when
 // BG < 64).
-template <int TW, int TH, int BG, bool CNT>
-__global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
+template <int TW, int TH, int BG, bool CNT, int SPLIT>
+__global__ __launch_bounds__(64 * (TH / kSubBlock) * SPLIT) void k_accum_fwd(
     const PlaneInt* __restrict__ pint, const uint32_t* __restrict__ tile_plane,
     const uint32_t* __restrict__ tile_start, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ srec,
     const RecAcc* __restrict__ racc, const RecGeo* __restrict__ rgeo, float* __restrict__ image,
@@ -42,18 +44,20 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
   constexpr int PER = BG >= 64 ? BG / 64 : 1;
   constexpr int CAP = PER * 64;
   static_assert(TW % kSubBlock == 0 && TH % kSubBlock == 0 && K * NB <= 32, "tile shape");
+  static_assert(SPLIT == 1 || SPLIT == 2, "waves per band");
   // per kept record: (t11, emin, c, mask) and, per pixel row of the band,
   // (exponent at the row, t1 offset of the row) -- the row set-up is done
   // once per record while staging instead of once per record and lane
-  __shared__ float4 cA[NB][CAP];
-  __shared__ float2 cR[NB][CAP][kSubBlock];
+  __shared__ float4 cA[NB * SPLIT][CAP];
+  __shared__ float2 cR[NB * SPLIT][CAP][kSubBlock];
 
   const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t p = tile_plane[t];
   const PlaneInt PI = pint[p];
   const uint32_t lt = t - PI.tile_off;
   const int x0 = (int)(lt % (uint32_t)PI.ntx) * TW, y0 = (int)(lt / (uint32_t)PI.ntx) * TH;
-  const int lane = threadIdx.x & 63, band = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int band = wv % NB, half = wv / NB;  // half: which alternate rounds
   const int lrow = lane / kSubBlock, col0 = lane % kSubBlock;
   const int row = band * kSubBlock + lrow;
   constexpr int kMaskShift = key_mask_shift(TW, TH);
@@ -93,8 +97,9 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
       }
     }
   };
-  if (s < e) fetch(s);
-  for (uint32_t base = s; base < e; base += BG) {
+  const uint32_t s0 = s + (uint32_t)(half * BG);
+  if (s0 < e) fetch(s0);
+  for (uint32_t base = s0; base < e; base += SPLIT * BG) {
     // keep this round's records that touch the band, in order
     uint32_t n = 0;
 #pragma unroll
@@ -107,17 +112,17 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
         const float du0 = (float)(pg[q].ub - x0) + A.fu;
         const float dv0 = (float)(pg[q].vb - y0) + A.fv;
         const float P = -A.t11 * du0;
-        cA[band][slot] = make_float4(A.t11, A.emin, A.c, __uint_as_float(m));
+        cA[wv][slot] = make_float4(A.t11, A.emin, A.c, __uint_as_float(m));
 #pragma unroll
         for (int y = 0; y < kSubBlock; ++y) {
           const float dv = (float)(band * kSubBlock + y) - dv0;
           const float t2 = A.t22 * dv;
-          cR[band][slot][y] = make_float2(fmaf(-t2, t2, A.e0), fmaf(A.t12, dv, P));
+          cR[wv][slot][y] = make_float2(fmaf(-t2, t2, A.e0), fmaf(A.t12, dv, P));
         }
       }
       n += (uint32_t)__popcll(bal);
     }
-    if (base + BG < e) fetch(base + BG);
+    if (base + SPLIT * BG < e) fetch(base + SPLIT * BG);
     wave_lds_sync();
     auto eval_rec = [&](const float4& a, const float2& rb) {
       const uint32_t m = __builtin_amdgcn_readfirstlane(__float_as_uint(a.w));
@@ -139,13 +144,33 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
     // two records per iteration so their LDS reads overlap
     uint32_t j = 0;
     for (; j + 1 < n; j += 2) {
-      const float4 a0 = cA[band][j], a1 = cA[band][j + 1];
-      const float2 r0 = cR[band][j][lrow], r1 = cR[band][j + 1][lrow];
+      const float4 a0 = cA[wv][j], a1 = cA[wv][j + 1];
+      const float2 r0 = cR[wv][j][lrow], r1 = cR[wv][j + 1][lrow];
       eval_rec(a0, r0);
       eval_rec(a1, r1);
     }
-    if (j < n) eval_rec(cA[band][j], cR[band][j][lrow]);
+    if (j < n) eval_rec(cA[wv][j], cR[wv][j][lrow]);
     wave_lds_sync();
+  }
+  if constexpr (SPLIT == 2) {
+    // the band's second wave hands its sums over through its own staging
+    // area; the first adds them to its own (first half + second half)
+    float* xch = reinterpret_cast<float*>(&cR[NB + band][0][0]);
+    if (half == 1) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        xch[(2 * k) * 64 + lane] = Nacc[k];
+        xch[(2 * k + 1) * 64 + lane] = Dacc[k];
+      }
+    }
+    __syncthreads();
+    if (half == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        Nacc[k] += xch[(2 * k) * 64 + lane];
+        Dacc[k] += xch[(2 * k + 1) * 64 + lane];
+      }
+    }
   }
   const int v = y0 + row;
   if (v < PI.H) {
@@ -155,9 +180,11 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock)) void k_accum_fwd(
     for (int k = 0; k < K; ++k) {
       const int u = x0 + col0 + k * kSubBlock;
       if (u < PI.W) {
-        const float Dt = Dacc[k] + bg_alpha;
-        image[rowbase + u] = (Nacc[k] + bg_alpha * bg_color) / Dt;
-        dsave[rowbase + u] = Dt;
+        if (half == 0) {
+          const float Dt = Dacc[k] + bg_alpha;
+          image[rowbase + u] = (Nacc[k] + bg_alpha * bg_color) / Dt;
+          dsave[rowbase + u] = Dt;
+        }
         c += cnt[k];
       }
     }
@@ -519,20 +546,20 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
   X(16, 32)               \
   X(32, 32)
 
-template <int TW, int TH>
+template <int TW, int TH, int SPLIT>
 static hipError_t fwd_bg(int bg, dim3 grid, hipStream_t s, const PlaneInt* pint, const uint32_t* tp,
                          const uint32_t* ts, const uint32_t* skey, const uint32_t* srec, const RecAcc* ra,
                          const RecGeo* rg, float* img, float* ds, float ba, float bc, unsigned long long* n_eval) {
-  constexpr int NT = 64 * (TH / kSubBlock);
+  constexpr int NT = 64 * (TH / kSubBlock) * SPLIT;
   switch (bg) {
 #define UG_BG(B)                                                                                                   \
   case B:                                                                                                          \
     if (n_eval)                                                                                                    \
-      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, true>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec, ra, rg, \
-                         img, ds, ba, bc, n_eval);                                                                 \
+      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, true, SPLIT>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec,    \
+                         ra, rg, img, ds, ba, bc, n_eval);                                                         \
     else                                                                                                           \
-      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, false>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec, ra, rg, \
-                         img, ds, ba, bc, n_eval);                                                                 \
+      hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, false, SPLIT>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec,   \
+                         ra, rg, img, ds, ba, bc, n_eval);                                                         \
     return hipGetLastError();
     UG_BG(32)
     UG_BG(64)
@@ -559,15 +586,18 @@ bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch) {
   return false;
 }
 
-hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, const PlaneInt* pint, const uint32_t* tile_plane,
-                            const uint32_t* tile_start, const uint32_t* skey, const uint32_t* srec,
-                            const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave, float bg_alpha,
-                            float bg_color, uint32_t num_tiles, unsigned long long* n_eval, hipStream_t s) {
+hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, int split, const PlaneInt* pint,
+                            const uint32_t* tile_plane, const uint32_t* tile_start, const uint32_t* skey,
+                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave,
+                            float bg_alpha, float bg_color, uint32_t num_tiles, unsigned long long* n_eval,
+                            hipStream_t s) {
   const dim3 grid(num_tiles);
-#define UG_LAUNCH_SHAPE(W, H)                                                                                   \
-  if (tile_w == W && tile_h == H)                                                                               \
-    return fwd_bg<W, H>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, racc, rgeo, image, dsave, \
-                        bg_alpha, bg_color, n_eval);
+#define UG_LAUNCH_SHAPE(W, H)                                                                                    \
+  if (tile_w == W && tile_h == H)                                                                                \
+    return split == 2 ? fwd_bg<W, H, 2>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, racc, rgeo, \
+                                        image, dsave, bg_alpha, bg_color, n_eval)                                \
+                      : fwd_bg<W, H, 1>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, racc, rgeo, \
+                                        image, dsave, bg_alpha, bg_color, n_eval);
   UG_TILE_SHAPES(UG_LAUNCH_SHAPE)
 #undef UG_LAUNCH_SHAPE
   return hipErrorInvalidValue;

@@ -38,7 +38,7 @@ def test_library_exports_every_declared_symbol(L):
 
 
 def test_status_strings_and_defaults(L):
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = L.lib.ug_status_string(code).decode()
         assert s and s != "unknown status"
     assert L.lib.ug_status_string(-99).decode() == "unknown status"
@@ -62,7 +62,8 @@ def _create(L, n=10, wh=((16, 16),), **kw):
 
 @pytest.mark.parametrize("kw", [dict(n=-1), dict(wh=((0, 5),)), dict(wh=((40000, 5),)), dict(beta=0.0),
                                 dict(beta=float("nan")), dict(chi2=-1.0), dict(chi2=float("nan")),
-                                dict(bg_alpha=0.0), dict(box_mode=7), dict(flags=4), dict(flags=8), dict(tile_w=12),
+                                dict(bg_alpha=0.0), dict(box_mode=7), dict(flags=4), dict(flags=16), dict(tile_w=12),
+                                dict(flags=8, tile_w=32, tile_h=32, lds_batch=256),
                                 dict(lds_batch=48), dict(tile_w=8, tile_h=8, px_per_lane=2),
                                 dict(bg_color=float("inf")),
                                 # 32x32 tiles leave 16 bits of the key word for the tile id: 257 x 256 tiles

@@ -21,15 +21,18 @@ def test_tune_checks_every_candidate():
     gd, pd = R.to_device(g, dev), R.to_device(pl, dev)
     shapes = ((8, 8, 1), (16, 16, 2), (32, 32, 4), (16, 32, 2))
     params, results = autotune.tune(gd, pd, pl.wh, steps=2, shapes=shapes, batches=(64, 128))
-    assert len(results) == len(shapes) * len(autotune.BOXES) + 3
-    picked = (params.tile_w, params.tile_h, params.px_per_lane, params.lds_batch, params.box_mode)
-    assert picked in {(r["tile_w"], r["tile_h"], r["px_per_lane"], r["lds_batch"], r["box_mode"]) for r in results}
+    assert len(results) == len(shapes) * len(autotune.BOXES) + 3 + 3  # + batches and splits of the best three
+    assert sum(r["split_forward"] for r in results) == 3
+    picked = (params.tile_w, params.tile_h, params.px_per_lane, params.lds_batch, params.box_mode,
+              bool(params.flags & R._lib.UG_FLAG_SPLIT_FORWARD))
+    assert picked in {(r["tile_w"], r["tile_h"], r["px_per_lane"], r["lds_batch"], r["box_mode"], r["split_forward"])
+                      for r in results}
     for r in results:
         assert r["ms"] > 0
         for name, e in r["grad_vs_first_shape"].items():
             assert e["probe_max_by_largest"] <= autotune.GRAD_REL, (r, name)
             assert e["workload_normwise"] <= autotune.GRAD_REL_WORKLOAD, (r, name)
     # the first shape's candidates compare with themselves: exact
-    first = [r for r in results if (r["tile_w"], r["tile_h"]) == shapes[0][:2]]
+    first = [r for r in results if (r["tile_w"], r["tile_h"]) == shapes[0][:2] and not r["split_forward"]]
     assert all(e["probe_max_by_largest"] == 0.0 for r in first for e in r["grad_vs_first_shape"].values())
     assert np.isfinite([r["ms"] for r in results]).all()

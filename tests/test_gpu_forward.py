@@ -410,3 +410,44 @@ def test_widest_planes_gather_and_box_support(R):
     img, plan = _render(R, g, pl, R.Params(flags=UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT))
     check_image_box_support(img[flat], g, pl, plan.params, pix=pix)
     assert img.shape[0] == W * 8
+
+
+@pytest.mark.parametrize("k,count", [(1, 1200), (2, 600)])
+def test_split_forward_parity_and_determinism(R, k, count):
+    """UG_FLAG_SPLIT_FORWARD (two waves per band, alternate record rounds):
+    every tile shape and LDS batch on small ragged planes and the full c1 /
+    c2 workloads on sampled pixels against the oracle; run to run bitwise;
+    within 2e-5 of the peak of the one-wave image (the two halves' sums are
+    grouped differently), except for pixels with a pair on the cut-off."""
+    from tests.parity import reference_points
+    import oracle
+    flag = R._lib.UG_FLAG_SPLIT_FORWARD
+    g = synth.make_gaussians(500, 91, (0, 0, 0), (1, 1, 1), (0.02, 0.12), aniso_max=8.0, opacity="random")
+    pl = synth.random_planes(3, 92, (8, 8), 1 / 48, 0.35, 0.65)
+    pl.wh[:] = [[61, 47], [32, 32], [48, 17]]
+    for tw, th in ((8, 8), (16, 16), (32, 32), (16, 32), (32, 8)):
+        for bg in (32, 64, 128):
+            img, plan = _render(R, g, pl, R.Params(tile_w=tw, tile_h=th, lds_batch=bg, flags=flag))
+            check_image(img, g, pl, plan.params)
+    g, pl, _ = synth.make_config(k)
+    from tests.configs import tuned_params
+    base = tuned_params(g, pl)
+    params = R.Params(**{**base.__dict__, "flags": flag})
+    dev = torch.device("cuda", 0)
+    gd, pd = R.to_device(g, dev), R.to_device(pl, dev)
+    plan = R.Plan(g.n, pl.wh, params, device=dev)
+    plan.fit(gd, pd)
+    a = plan.render(gd, pd).clone()
+    b = plan.render(gd, pd).clone()
+    one = R.Plan(g.n, pl.wh, base, device=dev)
+    one.fit(gd, pd)
+    c = one.render(gd, pd)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    peak = float(c.abs().max())
+    assert int(((a - c).abs() > 2e-5 * peak).sum()) <= max(1, 1e-4 * a.numel())
+    pix = synth.sample_pixels(pl, count, 700 + k)
+    offs = pl.pixel_offsets()
+    flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
+    ref, _ = reference_points(g, oracle.plane_points(pl, pix), params)
+    print(f"c{k} split", check_image(a.cpu().numpy()[flat], g, pl, params, pix=pix, ref=ref))
