@@ -24,7 +24,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t ctrl, pconst, pcull, cnt_rec, accbits, off_rec, blk_g, blk_r;
-  size_t rec_pair, racc, rgeo, rec_nkey, rec_koff, side;
+  size_t rec_pair, recs, rec_nkey, rec_koff, side;
   size_t tile_start, dsave, gq, hist;
   size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, partial;
   size_t loss_part;
@@ -86,8 +86,7 @@ void compute_layout(ug_plan* pl) {
   L.blk_g = take((size_t)cull_blocks(pl->n, pl->p) * 4);
   L.blk_r = take((size_t)record_blocks(pl->rec_cap) * 4);
   L.rec_pair = take(R * 8);
-  L.racc = take(R * sizeof(RecAcc));
-  L.rgeo = take(R * sizeof(RecGeo));
+  L.recs = take(R * sizeof(Rec));
   L.rec_nkey = take(R * 4);
   L.rec_koff = take((R + 1) * 4);
   L.side = take(adjoint_side_floats(pl->rec_cap) * 4);
@@ -216,12 +215,12 @@ hipError_t enqueue_preprocess(const ug_plan* plan, const ug_gaussians& g, const 
   {
     StageScope sc(plan, UG_STAGE_RECORD, s);
     e = launch_record(g, at<PlaneConst>(ws, L.pconst), plan->d_pint, rp, at<uint2>(ws, L.rec_pair),
-                      at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), at<uint32_t>(ws, L.rec_nkey),
+                      at<Rec>(ws, L.recs), at<uint32_t>(ws, L.rec_nkey),
                       at<uint32_t>(ws, L.blk_r), ctrl, s);
   }
   if (e != hipSuccess || !emit) return e;
   StageScope sc(plan, UG_STAGE_EMIT, s);
-  return launch_emit(plan->d_pint, rp, at<uint2>(ws, L.rec_pair), at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo),
+  return launch_emit(plan->d_pint, rp, at<uint2>(ws, L.rec_pair), at<Rec>(ws, L.recs),
                      at<uint32_t>(ws, L.rec_nkey), at<uint32_t>(ws, L.blk_r), at<uint32_t>(ws, L.rec_koff), ctrl,
                      at<uint32_t>(ws, L.key_tile0), at<uint32_t>(ws, L.rec_of_key), s);
 }
@@ -477,8 +476,8 @@ int render_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* pla
       // box-support records carry their rectangle in pixels, others in tiles
       const bool px = rp.box_support != 0;
       StageScope sc(plan, UG_STAGE_SCATTER, s);
-      e = launch_scatter(ctrl, at<uint2>(ws, L.rec_pair), plan->d_pint, at<RecAcc>(ws, L.racc),
-                         at<RecGeo>(ws, L.rgeo), px ? 1 : plan->prm.tile_w, px ? 1 : plan->prm.tile_h,
+      e = launch_scatter(ctrl, at<uint2>(ws, L.rec_pair), plan->d_pint, at<Rec>(ws, L.recs),
+                         px ? 1 : plan->prm.tile_w, px ? 1 : plan->prm.tile_h,
                          plan->rec_cap, image, den, s);
     }
     if (e != hipSuccess) return UG_ERR_HIP;
@@ -500,7 +499,7 @@ int render_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* pla
   StageScope sc(plan, UG_STAGE_ACCUM, s);
   e = launch_accum_fwd(plan->prm.tile_w, plan->prm.tile_h, plan->prm.lds_batch,
                        (plan->prm.flags & UG_FLAG_SPLIT_FORWARD) ? 2 : 1, plan->d_pint, plan->d_tile_plane,
-                       at<uint32_t>(ws, L.tile_start), so.key, so.rec, at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo), image, at<float>(ws, L.dsave),
+                       at<uint32_t>(ws, L.tile_start), so.key, so.rec, at<Rec>(ws, L.recs), image, at<float>(ws, L.dsave),
                        plan->prm.bg_alpha, plan->prm.bg_color, plan->num_tiles, n_eval, s);
   return hip_status(e);
 }
@@ -533,7 +532,7 @@ int backward_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* p
   if (e != hipSuccess) return UG_ERR_HIP;
   {
     StageScope sc(plan, UG_STAGE_ACCUM_BWD, s);
-    e = launch_accum_bwd(plan->prm.tile_w, plan->prm.tile_h, ctrl, plan->d_tile_org, so.key, so.val, so.rec, at<RecAcc>(ws, L.racc), at<RecGeo>(ws, L.rgeo),
+    e = launch_accum_bwd(plan->prm.tile_w, plan->prm.tile_h, ctrl, plan->d_tile_org, so.key, so.val, so.rec, at<Rec>(ws, L.recs),
                          at<float>(ws, L.gq),
                          at<float>(ws, L.partial), plan->key_cap, s);
   }
@@ -823,19 +822,17 @@ int64_t ug_debug_records(const ug_plan* plan, const void* workspace, ug_record* 
   const int64_t m = n < cap ? n : cap;
   if (m > 0) {
     std::vector<uint2> pair((size_t)m);
-    std::vector<RecAcc> acc((size_t)m);
-    std::vector<RecGeo> geo((size_t)m);
+    std::vector<Rec> rec((size_t)m);
     if (hipMemcpyAsync(pair.data(), ws + L.rec_pair, (size_t)m * sizeof(uint2), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
-        hipMemcpyAsync(acc.data(), ws + L.racc, (size_t)m * sizeof(RecAcc), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(geo.data(), ws + L.rgeo, (size_t)m * sizeof(RecGeo), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(rec.data(), ws + L.recs, (size_t)m * sizeof(Rec), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return UG_ERR_HIP;
     for (int64_t i = 0; i < m; ++i) {
       ug_record& r = host_out[i];
       r.gaussian = (int32_t)pair[(size_t)i].x;
       r.plane = (int32_t)pair[(size_t)i].y;
-      const RecAcc& a = acc[(size_t)i];
+      const RecAcc& a = rec[(size_t)i].acc;
       r.t11 = a.t11;
       r.t12 = a.t12;
       r.t22 = a.t22;
@@ -844,7 +841,7 @@ int64_t ug_debug_records(const ug_plan* plan, const void* workspace, ug_record* 
       r.e0 = a.e0;
       r.emin = a.emin;
       r.c = a.c;
-      const RecGeo& gg = geo[(size_t)i];
+      const RecGeo& gg = rec[(size_t)i].geo;
       r.ub = gg.ub;
       r.vb = gg.vb;
       r.tx0 = gg.tx0;

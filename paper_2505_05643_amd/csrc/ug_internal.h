@@ -106,6 +106,16 @@ struct RecGeo {
 };
 static_assert(sizeof(RecGeo) == 16, "RecGeo layout");
 
+// A record as stored: both parts in one 64-byte slot, so the accumulate
+// kernels' gathers (one record per key, in tile order: random in record
+// order) fetch one 64-byte segment per key instead of two.
+struct Rec {
+  RecAcc acc;
+  RecGeo geo;
+  uint32_t pad[4];
+};
+static_assert(sizeof(Rec) == 64, "Rec layout");
+
 // Per-key partial derivatives written by the adjoint accumulate
 // (dt11, dt12, dt22, dfu, dfv, de0, dc, unused).
 struct Partial {

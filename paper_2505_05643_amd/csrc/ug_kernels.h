@@ -22,10 +22,10 @@ hipError_t launch_cull_write(const RenderParams& rp, const uint32_t* cnt_rec, co
 // key emission: per key its key word (tile id and sub-block mask) and record
 // id.
 hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
-                         const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* blk_tot,
+                         const uint2* rec_pair, Rec* recs, uint32_t* rec_nkey, uint32_t* blk_tot,
                          Ctrl* ctrl, hipStream_t s);
-hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const RecAcc* racc,
-                       const RecGeo* rgeo, const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
+hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const Rec* recs,
+                       const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
                        Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, hipStream_t s);
 // Backward of the record construction and the per-Gaussian sums: the record
 // adjoint finishes every Gaussian whose records sit in one wave of 64 and
@@ -75,8 +75,8 @@ uint32_t sort_blocks_for(uint32_t key_cap);
 // ---- Phase-2 atomic scatter forward (ug_scatter.hip): zero the sums, one
 // wave per record adds w c and w over its box, normalise in place.
 hipError_t launch_scatter_zero(float* num, float* den, uint64_t m, hipStream_t s);
-hipError_t launch_scatter(const Ctrl* ctrl, const uint2* rec_pair, const PlaneInt* pint, const RecAcc* racc,
-                          const RecGeo* rgeo, int tile_w, int tile_h, uint32_t rec_cap, float* num, float* den,
+hipError_t launch_scatter(const Ctrl* ctrl, const uint2* rec_pair, const PlaneInt* pint, const Rec* recs,
+                          int tile_w, int tile_h, uint32_t rec_cap, float* num, float* den,
                           hipStream_t s);
 hipError_t launch_scatter_norm(float* image, float* dsave, uint64_t m, float bg_alpha, float bg_color,
                                hipStream_t s);
@@ -114,7 +114,7 @@ bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);
 // split = 2: two waves per 8-row band, taking alternate rounds of records.
 hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, int split, const PlaneInt* pint,
                             const uint32_t* tile_plane, const uint32_t* tile_start, const uint32_t* skey,
-                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave,
+                            const uint32_t* srec, const Rec* recs, float* image, float* dsave,
                             float bg_alpha, float bg_color, uint32_t num_tiles, unsigned long long* n_eval,
                             hipStream_t s);
 // second = dL/dc_hat, or (mse) the target with dL/dc_hat = scale (image -
@@ -127,7 +127,7 @@ hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const u
 // tile_org[t] = pixel origin of tile t, x0 | y0 << 16.
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint32_t* tile_org,
                             const uint32_t* skey, const uint32_t* sval,
-                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo,
+                            const uint32_t* srec, const Rec* recs,
                             const float* gq, float* partial, uint32_t key_cap, hipStream_t s);
 
 // ---- training helpers (ug_train.hip)

@@ -287,8 +287,8 @@ __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, c
 // block's total.
 __global__ __launch_bounds__(256) void k_record(ug_gaussians g, const PlaneConst* __restrict__ pc,
                                                 const PlaneInt* __restrict__ pint, RenderParams rp,
-                                                const uint2* __restrict__ rec_pair, RecAcc* __restrict__ racc,
-                                                RecGeo* __restrict__ rgeo, uint32_t* __restrict__ rec_nkey,
+                                                const uint2* __restrict__ rec_pair, Rec* __restrict__ recs,
+                                                uint32_t* __restrict__ rec_nkey,
                                                 uint32_t* __restrict__ blk_tot, const Ctrl* __restrict__ ctrl) {
   __shared__ uint32_t s_tot;
   const uint32_t nrec = ctrl->n_rec_eff;
@@ -320,8 +320,8 @@ __global__ __launch_bounds__(256) void k_record(ug_gaussians g, const PlaneConst
       f.acc = RecAcc{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       f.geo = RecGeo{0, 0, 1, 0, 1, 0};
     }
-    racc[r] = f.acc;
-    rgeo[r] = f.geo;
+    recs[r].acc = f.acc;
+    recs[r].geo = f.geo;
     rec_nkey[r] = f.keys;
     mine += f.keys;
   }
@@ -333,8 +333,8 @@ __global__ __launch_bounds__(256) void k_record(ug_gaussians g, const PlaneConst
 // Key offsets (block prefix + in-block scan) and key emission.  The last
 // active block publishes the key total and the capacity check.
 __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint, RenderParams rp,
-                                              const uint2* __restrict__ rec_pair, const RecAcc* __restrict__ racc,
-                                              const RecGeo* __restrict__ rgeo, const uint32_t* __restrict__ rec_nkey,
+                                              const uint2* __restrict__ rec_pair, const Rec* __restrict__ recs,
+                                              const uint32_t* __restrict__ rec_nkey,
                                               const uint32_t* __restrict__ blk_tot, uint32_t* __restrict__ rec_koff,
                                               Ctrl* __restrict__ ctrl, uint32_t* __restrict__ key_tile,
                                               uint32_t* __restrict__ rec_of_key) {
@@ -355,8 +355,8 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
   PlaneInt PI{};
   if (act) {
     nk = rec_nkey[r];
-    ra = racc[r];
-    ge = rgeo[r];
+    ra = recs[r].acc;
+    ge = recs[r].geo;
     PI = pint[rec_pair[r].y];
   }
   unsigned long long carry = block_prefix(blk_tot, blockIdx.x, s_sh);
@@ -367,8 +367,8 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
       nk = 0u;
       if (act) {
         nk = rec_nkey[r];
-        ra = racc[r];
-        ge = rgeo[r];
+        ra = recs[r].acc;
+        ge = recs[r].geo;
         PI = pint[rec_pair[r].y];
       }
     }
@@ -652,18 +652,18 @@ hipError_t launch_cull_write(const RenderParams& rp, const uint32_t* cnt_rec, co
 }
 
 hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
-                         const uint2* rec_pair, RecAcc* racc, RecGeo* rgeo, uint32_t* rec_nkey, uint32_t* blk_tot,
+                         const uint2* rec_pair, Rec* recs, uint32_t* rec_nkey, uint32_t* blk_tot,
                          Ctrl* ctrl, hipStream_t s) {
   hipLaunchKernelGGL(k_record, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, g, pc, pint, rp,
-                     rec_pair, racc, rgeo, rec_nkey, blk_tot, ctrl);
+                     rec_pair, recs, rec_nkey, blk_tot, ctrl);
   return hipGetLastError();
 }
 
-hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const RecAcc* racc,
-                       const RecGeo* rgeo, const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
+hipError_t launch_emit(const PlaneInt* pint, const RenderParams& rp, const uint2* rec_pair, const Rec* recs,
+                       const uint32_t* rec_nkey, const uint32_t* blk_tot, uint32_t* rec_koff,
                        Ctrl* ctrl, uint32_t* key_tile, uint32_t* rec_of_key, hipStream_t s) {
   hipLaunchKernelGGL(k_emit, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, pint, rp,
-                     rec_pair, racc, rgeo, rec_nkey, blk_tot, rec_koff, ctrl, key_tile, rec_of_key);
+                     rec_pair, recs, rec_nkey, blk_tot, rec_koff, ctrl, key_tile, rec_of_key);
   return hipGetLastError();
 }
 

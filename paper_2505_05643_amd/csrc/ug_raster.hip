@@ -37,7 +37,7 @@ template <int TW, int TH, int BG, bool CNT, int SPLIT>
 __global__ __launch_bounds__(64 * (TH / kSubBlock) * SPLIT) void k_accum_fwd(
     const PlaneInt* __restrict__ pint, const uint32_t* __restrict__ tile_plane,
     const uint32_t* __restrict__ tile_start, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ srec,
-    const RecAcc* __restrict__ racc, const RecGeo* __restrict__ rgeo, float* __restrict__ image,
+    const Rec* __restrict__ recs, float* __restrict__ image,
     float* __restrict__ dsave, float bg_alpha, float bg_color, unsigned long long* __restrict__ counters) {
   constexpr int K = TW / kSubBlock;   // pixels per lane = sub-blocks per band
   constexpr int NB = TH / kSubBlock;  // bands = waves
@@ -92,8 +92,8 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock) * SPLIT) void k_accum_fwd(
       const uint32_t m = (kw[q] >> bshift) & bmask;
       pm[q] = m;
       if (m) {
-        pa[q] = racc[rid[q]];
-        pg[q] = rgeo[rid[q]];
+        pa[q] = recs[rid[q]].acc;
+        pg[q] = recs[rid[q]].geo;
       }
     }
   };
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
                                                    const uint32_t* __restrict__ skey,
                                                    const uint32_t* __restrict__ sval,
                                                    const uint32_t* __restrict__ srec,
-                                                   const RecAcc* __restrict__ racc, const RecGeo* __restrict__ rgeo,
+                                                   const Rec* __restrict__ recs,
                                                    const float2* __restrict__ gq, float4* __restrict__ partial) {
   constexpr int K = TW / kSubBlock, Q = K * (TH / kSubBlock);
   constexpr int kMaskShift = key_mask_shift(TW, TH);
@@ -328,8 +328,8 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
       m = kw >> kMaskShift;
       const uint32_t t = kw & ((1u << kMaskShift) - 1u);
       const uint32_t r = srec[i];
-      const RecAcc A = racc[r];
-      const RecGeo Gg = rgeo[r];
+      const RecAcc A = recs[r].acc;
+      const RecGeo Gg = recs[r].geo;
       const uint32_t org = tile_org[t];  // x0 | y0 << 16
       const int x0 = (int)(org & 0xffffu), y0 = (int)(org >> 16);
       const float du0 = (float)(Gg.ub - x0) + A.fu;
@@ -548,18 +548,18 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
 
 template <int TW, int TH, int SPLIT>
 static hipError_t fwd_bg(int bg, dim3 grid, hipStream_t s, const PlaneInt* pint, const uint32_t* tp,
-                         const uint32_t* ts, const uint32_t* skey, const uint32_t* srec, const RecAcc* ra,
-                         const RecGeo* rg, float* img, float* ds, float ba, float bc, unsigned long long* n_eval) {
+                         const uint32_t* ts, const uint32_t* skey, const uint32_t* srec, const Rec* rc,
+                         float* img, float* ds, float ba, float bc, unsigned long long* n_eval) {
   constexpr int NT = 64 * (TH / kSubBlock) * SPLIT;
   switch (bg) {
 #define UG_BG(B)                                                                                                   \
   case B:                                                                                                          \
     if (n_eval)                                                                                                    \
       hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, true, SPLIT>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec,    \
-                         ra, rg, img, ds, ba, bc, n_eval);                                                         \
+                         rc, img, ds, ba, bc, n_eval);                                                             \
     else                                                                                                           \
       hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, false, SPLIT>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec,   \
-                         ra, rg, img, ds, ba, bc, n_eval);                                                         \
+                         rc, img, ds, ba, bc, n_eval);                                                             \
     return hipGetLastError();
     UG_BG(32)
     UG_BG(64)
@@ -588,15 +588,15 @@ bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch) {
 
 hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, int split, const PlaneInt* pint,
                             const uint32_t* tile_plane, const uint32_t* tile_start, const uint32_t* skey,
-                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo, float* image, float* dsave,
+                            const uint32_t* srec, const Rec* recs, float* image, float* dsave,
                             float bg_alpha, float bg_color, uint32_t num_tiles, unsigned long long* n_eval,
                             hipStream_t s) {
   const dim3 grid(num_tiles);
 #define UG_LAUNCH_SHAPE(W, H)                                                                                    \
   if (tile_w == W && tile_h == H)                                                                                \
-    return split == 2 ? fwd_bg<W, H, 2>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, racc, rgeo, \
+    return split == 2 ? fwd_bg<W, H, 2>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, recs,       \
                                         image, dsave, bg_alpha, bg_color, n_eval)                                \
-                      : fwd_bg<W, H, 1>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, racc, rgeo, \
+                      : fwd_bg<W, H, 1>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, recs,       \
                                         image, dsave, bg_alpha, bg_color, n_eval);
   UG_TILE_SHAPES(UG_LAUNCH_SHAPE)
 #undef UG_LAUNCH_SHAPE
@@ -632,7 +632,7 @@ hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const u
 
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint32_t* tile_org,
                             const uint32_t* skey, const uint32_t* sval,
-                            const uint32_t* srec, const RecAcc* racc, const RecGeo* rgeo,
+                            const uint32_t* srec, const Rec* recs,
                             const float* gq, float* partial, uint32_t key_cap, hipStream_t s) {
   const float2* g2 = reinterpret_cast<const float2*>(gq);
   float4* p4 = reinterpret_cast<float4*>(partial);
@@ -641,7 +641,7 @@ hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint
 #define UG_BWD(W, H)                                                                                          \
   if (tile_w == W && tile_h == H) {                                                                           \
     hipLaunchKernelGGL((k_accum_bwd<W, H>), dim3(blocks), dim3(256), 0, s, ctrl, tile_org, skey, sval, srec, \
-                       racc, rgeo, g2, p4);                                                                   \
+                       recs, g2, p4);                                                                         \
     return hipGetLastError();                                                                                 \
   }
   UG_TILE_SHAPES(UG_BWD)

@@ -30,16 +30,16 @@ __global__ __launch_bounds__(256) void k_scatter_zero(float* __restrict__ num, f
 }
 
 __global__ __launch_bounds__(256) void k_scatter(const Ctrl* __restrict__ ctrl, const uint2* __restrict__ rec_pair,
-                                                 const PlaneInt* __restrict__ pint, const RecAcc* __restrict__ racc,
-                                                 const RecGeo* __restrict__ rgeo, int TW, int TH,
+                                                 const PlaneInt* __restrict__ pint, const Rec* __restrict__ recs,
+                                                 int TW, int TH,
                                                  float* __restrict__ num, float* __restrict__ den) {
   const uint32_t nrec = ctrl->n_rec_eff;
   const int lane = threadIdx.x & 63;
   const uint32_t nw = gridDim.x * 4u;
   for (uint32_t r = blockIdx.x * 4u + (threadIdx.x >> 6); r < nrec; r += nw) {
-    const RecGeo g = rgeo[r];
+    const RecGeo g = recs[r].geo;
     if (g.tx0 > g.tx1 || g.ty0 > g.ty1) continue;  // footprint off the image (uniform)
-    const RecAcc A = racc[r];
+    const RecAcc A = recs[r].acc;
     const PlaneInt PI = pint[rec_pair[r].y];
     // tile rectangle of the record, cut to the plane
     int u0 = g.tx0 * TW, u1 = min(g.tx1 * TW + TW - 1, PI.W - 1);
@@ -97,12 +97,12 @@ hipError_t launch_scatter_zero(float* num, float* den, uint64_t m, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const Ctrl* ctrl, const uint2* rec_pair, const PlaneInt* pint, const RecAcc* racc,
-                          const RecGeo* rgeo, int tile_w, int tile_h, uint32_t rec_cap, float* num, float* den,
+hipError_t launch_scatter(const Ctrl* ctrl, const uint2* rec_pair, const PlaneInt* pint, const Rec* recs,
+                          int tile_w, int tile_h, uint32_t rec_cap, float* num, float* den,
                           hipStream_t s) {
   const uint32_t want = (rec_cap + 3u) / 4u;  // four records (waves) per block
   const unsigned blocks = want < 1u ? 1u : (want > 65536u ? 65536u : want);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, s, ctrl, rec_pair, pint, racc, rgeo, tile_w, tile_h,
+  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, s, ctrl, rec_pair, pint, recs, tile_w, tile_h,
                      num, den);
   return hipGetLastError();
 }
