@@ -500,7 +500,8 @@ int render_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* pla
   e = launch_accum_fwd(plan->prm.tile_w, plan->prm.tile_h, plan->prm.lds_batch,
                        (plan->prm.flags & UG_FLAG_SPLIT_FORWARD) ? 2 : 1, plan->d_pint, plan->d_tile_plane,
                        at<uint32_t>(ws, L.tile_start), so.key, so.rec, at<Rec>(ws, L.recs), image, at<float>(ws, L.dsave),
-                       plan->prm.bg_alpha, plan->prm.bg_color, plan->num_tiles, n_eval, s);
+                       plan->prm.bg_alpha, plan->prm.bg_color, std::isfinite(plan->prm.chi2), plan->num_tiles,
+                       n_eval, s);
   return hip_status(e);
 }
 
@@ -534,7 +535,7 @@ int backward_impl(const ug_plan* plan, const ug_gaussians* g, const ug_planes* p
     StageScope sc(plan, UG_STAGE_ACCUM_BWD, s);
     e = launch_accum_bwd(plan->prm.tile_w, plan->prm.tile_h, ctrl, plan->d_tile_org, so.key, so.val, so.rec, at<Rec>(ws, L.recs),
                          at<float>(ws, L.gq),
-                         at<float>(ws, L.partial), plan->key_cap, s);
+                         at<float>(ws, L.partial), std::isfinite(plan->prm.chi2), plan->key_cap, s);
   }
   if (e != hipSuccess) return UG_ERR_HIP;
   {

@@ -112,11 +112,13 @@ hipError_t launch_probe(int kind, int blocks, int iters, const float* src, float
 int accum_default_ppl(int tile_w, int tile_h);
 bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch);
 // split = 2: two waves per 8-row band, taking alternate rounds of records.
+// cut: the launch has a finite chi^2 cut-off (Eq. 12); the same flag goes to
+// the adjoint.
 hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, int split, const PlaneInt* pint,
                             const uint32_t* tile_plane, const uint32_t* tile_start, const uint32_t* skey,
                             const uint32_t* srec, const Rec* recs, float* image, float* dsave,
-                            float bg_alpha, float bg_color, uint32_t num_tiles, unsigned long long* n_eval,
-                            hipStream_t s);
+                            float bg_alpha, float bg_color, bool cut, uint32_t num_tiles,
+                            unsigned long long* n_eval, hipStream_t s);
 // second = dL/dc_hat, or (mse) the target with dL/dc_hat = scale (image -
 // target) formed inside and per-block squared-difference sums in loss_part
 // (bwd_prep_blocks floats).
@@ -128,7 +130,7 @@ hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const u
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint32_t* tile_org,
                             const uint32_t* skey, const uint32_t* sval,
                             const uint32_t* srec, const Rec* recs,
-                            const float* gq, float* partial, uint32_t key_cap, hipStream_t s);
+                            const float* gq, float* partial, bool cut, uint32_t key_cap, hipStream_t s);
 
 // ---- training helpers (ug_train.hip)
 hipError_t launch_mse(const float* image, const float* target, int64_t m, float* d_image, float* loss,

@@ -21,11 +21,41 @@
 // 64 pixels and accumulating the record's seven partial derivatives in
 // registers.  The items of a key are summed in sub-block order into the
 // key's partial, so no atomic is needed and the result is deterministic.
+#include <cfloat>
+
 #include "ug_kernels.h"
 
 namespace ug {
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// A pair's weight 2^(e0 - t1^2 - t2^2) (Eq. 8 in log2 units) is evaluated as
+// s 2^x with x = d - t1^2 - t2^2, d = e0 - sig and s = 2^sig per record.
+// Under a cut-off (Eq. 12) sig = emin, so the support is x >= 0, and one
+// signed-integer max of x's bits against the bits of -inf (kCutBits) maps
+// every x < 0 to -inf, whose 2^x is 0: the compare and select of the test
+// become one instruction.  sig stays within 64 of e0, so the scaled weights
+// stay below 2^64 (for chi^2 > 64 / (log2(e) / 2) = 88.7 the cut then drops
+// only weights below 2^-64 of the Gaussian's peak instead of those beyond
+// chi^2).  Without a cut-off sig = e0 and the max is against INT_MIN (no
+// operation).  A record whose sig is -inf (zero amplitude) gets d = -inf.
+constexpr int kCutBits = (int)0xff800000u;  // bits of -inf
+constexpr int kNoCutBits = (int)0x80000000u;
+
+struct WeightScale {
+  float d, s;
+};
+
+__device__ __forceinline__ WeightScale weight_scale(float e0, float emin, bool cut) {
+  const float sig = cut ? fmaxf(emin, e0 - 64.f) : e0;
+  if (!(sig > -INFINITY)) return {-INFINITY, 0.f};
+  return {e0 - sig, exp2f(sig)};
+}
+
+// x with every value outside the support mapped to -inf (see above).
+__device__ __forceinline__ float support_clamp(float x, int kcut) {
+  return __int_as_float(max(__float_as_int(x), kcut));
+}
 
 // ---------------------------------------------------------------- forward
 // CNT: also count the in-support pairs of pixels inside the plane and the
@@ -38,16 +68,17 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock) * SPLIT) void k_accum_fwd(
     const PlaneInt* __restrict__ pint, const uint32_t* __restrict__ tile_plane,
     const uint32_t* __restrict__ tile_start, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ srec,
     const Rec* __restrict__ recs, float* __restrict__ image,
-    float* __restrict__ dsave, float bg_alpha, float bg_color, unsigned long long* __restrict__ counters) {
+    float* __restrict__ dsave, float bg_alpha, float bg_color, int kcut, unsigned long long* __restrict__ counters) {
   constexpr int K = TW / kSubBlock;   // pixels per lane = sub-blocks per band
   constexpr int NB = TH / kSubBlock;  // bands = waves
   constexpr int PER = BG >= 64 ? BG / 64 : 1;
   constexpr int CAP = PER * 64;
   static_assert(TW % kSubBlock == 0 && TH % kSubBlock == 0 && K * NB <= 32, "tile shape");
   static_assert(SPLIT == 1 || SPLIT == 2, "waves per band");
-  // per kept record: (t11, emin, c, mask) and, per pixel row of the band,
-  // (exponent at the row, t1 offset of the row) -- the row set-up is done
-  // once per record while staging instead of once per record and lane
+  // per kept record: (t11, s, s c, mask) and, per pixel row of the band,
+  // (scaled exponent d - t2^2 at the row, t1 offset of the row) -- the row
+  // set-up is done once per record while staging instead of once per record
+  // and lane
   __shared__ float4 cA[NB * SPLIT][CAP];
   __shared__ float2 cR[NB * SPLIT][CAP][kSubBlock];
 
@@ -72,6 +103,7 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock) * SPLIT) void k_accum_fwd(
     Dacc[k] = 0.f;
     cnt[k] = 0u;
   }
+  const bool cut = kcut != kNoCutBits;
   const uint32_t s = tile_start[t], e = tile_start[t + 1];
   RecAcc pa[PER];
   RecGeo pg[PER];
@@ -112,12 +144,13 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock) * SPLIT) void k_accum_fwd(
         const float du0 = (float)(pg[q].ub - x0) + A.fu;
         const float dv0 = (float)(pg[q].vb - y0) + A.fv;
         const float P = -A.t11 * du0;
-        cA[wv][slot] = make_float4(A.t11, A.emin, A.c, __uint_as_float(m));
+        const WeightScale ws = weight_scale(A.e0, A.emin, cut);
+        cA[wv][slot] = make_float4(A.t11, ws.s, ws.s * A.c, __uint_as_float(m));
 #pragma unroll
         for (int y = 0; y < kSubBlock; ++y) {
           const float dv = (float)(band * kSubBlock + y) - dv0;
           const float t2 = A.t22 * dv;
-          cR[wv][slot][y] = make_float2(fmaf(-t2, t2, A.e0), fmaf(A.t12, dv, P));
+          cR[wv][slot][y] = make_float2(fmaf(-t2, t2, ws.d), fmaf(A.t12, dv, P));
         }
       }
       n += (uint32_t)__popcll(bal);
@@ -131,12 +164,12 @@ __global__ __launch_bounds__(64 * (TH / kSubBlock) * SPLIT) void k_accum_fwd(
       for (int k = 0; k < K; ++k) {
         if (K > 1 && !((m >> k) & 1u)) continue;  // uniform
         const float t1 = fmaf(a.x, ucol[k], B);
-        const float ee = fmaf(-t1, t1, erow);
-        const float w = ee >= a.y ? fast_exp2(ee) : 0.f;
-        Dacc[k] += w;
+        const float xs = support_clamp(fmaf(-t1, t1, erow), kcut);
+        const float w = fast_exp2(xs);  // the weight over s
+        Dacc[k] = fmaf(w, a.y, Dacc[k]);
         Nacc[k] = fmaf(w, a.z, Nacc[k]);
         if constexpr (CNT) {
-          cnt[k] += ee >= a.y ? 1u : 0u;
+          cnt[k] += xs != -INFINITY ? 1u : 0u;
           ++nexec;
         }
       }
@@ -300,12 +333,13 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
                                                    const uint32_t* __restrict__ sval,
                                                    const uint32_t* __restrict__ srec,
                                                    const Rec* __restrict__ recs,
-                                                   const float2* __restrict__ gq, float4* __restrict__ partial) {
+                                                   const float2* __restrict__ gq, float4* __restrict__ partial,
+                                                   int kcut) {
   constexpr int K = TW / kSubBlock, Q = K * (TH / kSubBlock);
   constexpr int kMaskShift = key_mask_shift(TW, TH);
   static_assert(Q <= 16 && kBwdSlots >= Q && kBwdSlots <= 256, "sub-blocks per tile; slot ids fit a byte");
   __shared__ float4 kpA[4][64];     // t11, t12, t22, -t11 du0
-  __shared__ float4 kpB[4][64];     // du0, dv0, e0, emin
+  __shared__ float4 kpB[4][64];     // du0, dv0, d, s (the weight's scaled form)
   __shared__ float kpC[4][64];      // c
   __shared__ uint32_t kpT[4][64];   // tile
   __shared__ uint32_t qoff[4][65];  // first item of each key
@@ -314,6 +348,10 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
   __shared__ float slot[4][7][kBwdSlots];
   const uint32_t n = ctrl->n_key_eff;
   const float ln2 = (float)kLn2;
+  const bool cut = kcut != kNoCutBits;
+  // rows pass the pre-pass test iff their best pixel is in the support;
+  // without a cut-off only zero-amplitude records (d = -inf) fail it
+  const float thr = cut ? 0.f : -FLT_MAX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t nchunks = (n + 63u) / 64u;
   const uint32_t W = gridDim.x * 4u;
@@ -334,8 +372,9 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
       const int x0 = (int)(org & 0xffffu), y0 = (int)(org >> 16);
       const float du0 = (float)(Gg.ub - x0) + A.fu;
       const float dv0 = (float)(Gg.vb - y0) + A.fv;
+      const WeightScale ws = weight_scale(A.e0, A.emin, cut);
       kpA[wave][lane] = make_float4(A.t11, A.t12, A.t22, -A.t11 * du0);
-      kpB[wave][lane] = make_float4(du0, dv0, A.e0, A.emin);
+      kpB[wave][lane] = make_float4(du0, dv0, ws.d, ws.s);
       kpC[wave][lane] = A.c;
       kpT[wave][lane] = t;
     }
@@ -391,7 +430,7 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
           // end value nearest zero, or zero when t1 changes sign in between
           const float ta = fmaf(a.x, xa, B), tb = fmaf(a.x, xb, B);
           const float tm = __builtin_amdgcn_fmed3f(ta, 0.f, tb);
-          rows |= (fmaf(-tm, tm, erow) >= b.w ? 1u : 0u) << y;
+          rows |= (fmaf(-tm, tm, erow) >= thr ? 1u : 0u) << y;
         }
         const int ya = rows ? __builtin_ctz(rows) : 0, yb = rows ? 31 - __builtin_clz(rows) : -1;
         const int nr = has && rows ? yb - ya + 1 : 0;
@@ -441,13 +480,13 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
         const float c = kpC[wave][kl];
         const uint32_t t = kpT[wave][kl];
         const float t11 = a.x, t12 = a.y, t22 = a.z, P = a.w;
-        const float e0 = b.z, emin = b.w;
+        const float d = b.z;
         const int bx0 = (sb % K) * kSubBlock, by = (sb / K) * kSubBlock + ry;
         const float4* __restrict__ pq = reinterpret_cast<const float4*>(gq + (size_t)t * (TW * TH) + by * TW + bx0);
         float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
         // row y of the item for y < nr; later rows (and lanes without an
         // item) re-read the item's last row (or the key's first) with a
-        // cut-off no weight passes, so they add exact zeros.  The loop ends
+        // row exponent of -inf, so they add exact zeros.  The loop ends
         // once no lane of the wave has rows left; rows of gamma are fetched
         // one row ahead of their use.
         const int nlast = nr > 0 ? nr - 1 : 0;
@@ -463,11 +502,10 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
 #pragma unroll
             for (int x2 = 0; x2 < kSubBlock / 2; ++x2) nxt[x2] = pq[yn * (TW / 2) + x2];
           }
-          const float lim = y < nr ? emin : INFINITY;
           const float dv = (float)(by + y) - b.y;
           const float B = fmaf(t12, dv, P);
           const float t2 = t22 * dv;
-          const float erow = fmaf(-t2, t2, e0);
+          const float erow = y < nr ? fmaf(-t2, t2, d) : -INFINITY;
           float rge = 0.f, ra = 0.f;
 #pragma unroll
           for (int x2 = 0; x2 < kSubBlock / 2; ++x2) {
@@ -477,8 +515,7 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
               const float gx = h ? gg2.z : gg2.x, gy = h ? gg2.w : gg2.y;
               const float xf = (float)(bx0 + 2 * x2 + h);
               const float t1 = fmaf(t11, xf, B);
-              const float ee = fmaf(-t1, t1, erow);
-              const float w = ee >= lim ? fast_exp2(ee) : 0.f;
+              const float w = fast_exp2(support_clamp(fmaf(-t1, t1, erow), kcut));  // the weight over s
               const float gw = fmaf(gx, c, -gy);  // dL/dw = gamma (c - c_hat)
               const float ge = w * gw;
               rge += ge;
@@ -522,8 +559,10 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
     }
     if (act) {
       const float4 a = kpA[wave][lane];
-      const float du0 = kpB[wave][lane].x;
-      const float Sge = acc[0], Sa = acc[1], Sau = acc[2], S12 = acc[3], S22 = acc[4], Sb = acc[5], Sdc = acc[6];
+      const float du0 = kpB[wave][lane].x, sw = kpB[wave][lane].w;
+      // every sum is linear in the weights: scale them back by s once
+      const float Sge = acc[0] * sw, Sa = acc[1] * sw, Sau = acc[2] * sw, S12 = acc[3] * sw, S22 = acc[4] * sw,
+                  Sb = acc[5] * sw, Sdc = acc[6] * sw;
       // w = 2^(e0 - t1^2 - t2^2):  dL/ds = -ln2 w dL/dw, s = t1^2 + t2^2.
       const float k2 = 2.f * ln2;
       const uint32_t eidx = sval[i];
@@ -549,17 +588,17 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
 template <int TW, int TH, int SPLIT>
 static hipError_t fwd_bg(int bg, dim3 grid, hipStream_t s, const PlaneInt* pint, const uint32_t* tp,
                          const uint32_t* ts, const uint32_t* skey, const uint32_t* srec, const Rec* rc,
-                         float* img, float* ds, float ba, float bc, unsigned long long* n_eval) {
+                         float* img, float* ds, float ba, float bc, int kcut, unsigned long long* n_eval) {
   constexpr int NT = 64 * (TH / kSubBlock) * SPLIT;
   switch (bg) {
 #define UG_BG(B)                                                                                                   \
   case B:                                                                                                          \
     if (n_eval)                                                                                                    \
       hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, true, SPLIT>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec,    \
-                         rc, img, ds, ba, bc, n_eval);                                                             \
+                         rc, img, ds, ba, bc, kcut, n_eval);                                                       \
     else                                                                                                           \
       hipLaunchKernelGGL((k_accum_fwd<TW, TH, B, false, SPLIT>), grid, dim3(NT), 0, s, pint, tp, ts, skey, srec,   \
-                         rc, img, ds, ba, bc, n_eval);                                                             \
+                         rc, img, ds, ba, bc, kcut, n_eval);                                                       \
     return hipGetLastError();
     UG_BG(32)
     UG_BG(64)
@@ -589,15 +628,16 @@ bool accum_config_supported(int tile_w, int tile_h, int ppl, int lds_batch) {
 hipError_t launch_accum_fwd(int tile_w, int tile_h, int lds_batch, int split, const PlaneInt* pint,
                             const uint32_t* tile_plane, const uint32_t* tile_start, const uint32_t* skey,
                             const uint32_t* srec, const Rec* recs, float* image, float* dsave,
-                            float bg_alpha, float bg_color, uint32_t num_tiles, unsigned long long* n_eval,
-                            hipStream_t s) {
+                            float bg_alpha, float bg_color, bool cut, uint32_t num_tiles,
+                            unsigned long long* n_eval, hipStream_t s) {
   const dim3 grid(num_tiles);
+  const int kcut = cut ? kCutBits : kNoCutBits;
 #define UG_LAUNCH_SHAPE(W, H)                                                                                    \
   if (tile_w == W && tile_h == H)                                                                                \
     return split == 2 ? fwd_bg<W, H, 2>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, recs,       \
-                                        image, dsave, bg_alpha, bg_color, n_eval)                                \
+                                        image, dsave, bg_alpha, bg_color, kcut, n_eval)                          \
                       : fwd_bg<W, H, 1>(lds_batch, grid, s, pint, tile_plane, tile_start, skey, srec, recs,       \
-                                        image, dsave, bg_alpha, bg_color, n_eval);
+                                        image, dsave, bg_alpha, bg_color, kcut, n_eval);
   UG_TILE_SHAPES(UG_LAUNCH_SHAPE)
 #undef UG_LAUNCH_SHAPE
   return hipErrorInvalidValue;
@@ -633,7 +673,7 @@ hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const u
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint32_t* tile_org,
                             const uint32_t* skey, const uint32_t* sval,
                             const uint32_t* srec, const Rec* recs,
-                            const float* gq, float* partial, uint32_t key_cap, hipStream_t s) {
+                            const float* gq, float* partial, bool cut, uint32_t key_cap, hipStream_t s) {
   const float2* g2 = reinterpret_cast<const float2*>(gq);
   float4* p4 = reinterpret_cast<float4*>(partial);
   uint32_t want = (key_cap / 64u + 4u) / 4u;
@@ -641,7 +681,7 @@ hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint
 #define UG_BWD(W, H)                                                                                          \
   if (tile_w == W && tile_h == H) {                                                                           \
     hipLaunchKernelGGL((k_accum_bwd<W, H>), dim3(blocks), dim3(256), 0, s, ctrl, tile_org, skey, sval, srec, \
-                       recs, g2, p4);                                                                         \
+                       recs, g2, p4, cut ? kCutBits : kNoCutBits);                                            \
     return hipGetLastError();                                                                                 \
   }
   UG_TILE_SHAPES(UG_BWD)
