@@ -356,19 +356,39 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
   const uint32_t nchunks = (n + 63u) / 64u;
   const uint32_t W = gridDim.x * 4u;
   const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x) * 4u + (uint32_t)wave;
-  for (uint32_t chunk = wid; chunk < nchunks; chunk += W) {
-    // ---- load the chunk's keys; item offsets in key order
+  // The wave's chunks are fetched two ahead: while a chunk is processed,
+  // the records and tile origins of the wave's next chunk (a random gather)
+  // and the key words and record ids of the one after are in flight.  Lanes
+  // past the last key read record 0 and tile 0 (both exist whenever there
+  // is a key) and are masked off.
+  const uint32_t kmask = (1u << kMaskShift) - 1u;
+  auto fetch_keys = [&](uint32_t ch, uint32_t& kw, uint32_t& r) {
+    const uint32_t j = ch * 64u + (uint32_t)lane;
+    kw = j < n ? skey[j] : 0u;
+    r = j < n ? srec[j] : 0u;
+  };
+  uint32_t chunk = wid;
+  uint32_t kwN = 0u, rN = 0u, kwNN = 0u, rNN = 0u, orgN = 0u;
+  RecAcc AN{};
+  RecGeo GN{};
+  if (chunk < nchunks) {
+    fetch_keys(chunk, kwN, rN);
+    AN = recs[rN].acc;
+    GN = recs[rN].geo;
+    orgN = tile_org[kwN & kmask];
+    fetch_keys(chunk + W, kwNN, rNN);
+  }
+  for (; chunk < nchunks; chunk += W) {
+    // ---- the chunk's keys; item offsets in key order
     const uint32_t i = chunk * 64u + (uint32_t)lane;
     const bool act = i < n;
-    uint32_t m = 0u;
+    uint32_t eidx = act ? sval[i] : 0u;  // where the key's partial goes
+    const uint32_t m = act ? kwN >> kMaskShift : 0u;
     if (act) {
-      const uint32_t kw = skey[i];
-      m = kw >> kMaskShift;
-      const uint32_t t = kw & ((1u << kMaskShift) - 1u);
-      const uint32_t r = srec[i];
-      const RecAcc A = recs[r].acc;
-      const RecGeo Gg = recs[r].geo;
-      const uint32_t org = tile_org[t];  // x0 | y0 << 16
+      const uint32_t t = kwN & kmask;
+      const RecAcc A = AN;
+      const RecGeo Gg = GN;
+      const uint32_t org = orgN;  // x0 | y0 << 16
       const int x0 = (int)(org & 0xffffu), y0 = (int)(org >> 16);
       const float du0 = (float)(Gg.ub - x0) + A.fu;
       const float dv0 = (float)(Gg.vb - y0) + A.fv;
@@ -388,6 +408,13 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
     const uint32_t off = x - pop;
     qoff[wave][lane] = off;
     if (lane == 63) qoff[wave][64] = x;
+    // the next chunk's records (its keys arrived during the previous chunk)
+    // and the keys of the one after
+    AN = recs[rNN].acc;
+    GN = recs[rNN].geo;
+    orgN = tile_org[kwNN & kmask];
+    kwN = kwNN;
+    fetch_keys(chunk + 2u * W, kwNN, rNN);
     wave_lds_sync();
     float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < 64;) {
@@ -417,7 +444,7 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
         const int kl = (int)(ent & 63u), sb = (int)((ent >> 6) & 15u);
         const float4 a = kpA[wave][kl];
         const float4 b = kpB[wave][kl];
-        const float xa = (float)((sb % K) * kSubBlock), xb = xa + (float)(kSubBlock - 1);
+        const float xa = (float)((sb % K) * kSubBlock);
         const int by = (sb / K) * kSubBlock;
         uint32_t rows = 0u;
 #pragma unroll
@@ -426,9 +453,10 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
           const float B = fmaf(a.y, dv, a.w);
           const float t2 = a.z * dv;
           const float erow = fmaf(-t2, t2, b.z);
-          // t1 at the strip's end columns; the median of (ta, 0, tb) is the
-          // end value nearest zero, or zero when t1 changes sign in between
-          const float ta = fmaf(a.x, xa, B), tb = fmaf(a.x, xb, B);
+          // t1 at the strip's end columns, as the evaluation forms them; the
+          // median of (ta, 0, tb) is the end value nearest zero, or zero when
+          // t1 changes sign in between
+          const float ta = fmaf(a.x, xa, B), tb = fmaf(a.x, (float)(kSubBlock - 1), ta);
           const float tm = __builtin_amdgcn_fmed3f(ta, 0.f, tb);
           rows |= (fmaf(-tm, tm, erow) >= thr ? 1u : 0u) << y;
         }
@@ -482,58 +510,60 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
         const float t11 = a.x, t12 = a.y, t22 = a.z, P = a.w;
         const float d = b.z;
         const int bx0 = (sb % K) * kSubBlock, by = (sb / K) * kSubBlock + ry;
+        const float bxf = (float)bx0;
         const float4* __restrict__ pq = reinterpret_cast<const float4*>(gq + (size_t)t * (TW * TH) + by * TW + bx0);
         float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
         // row y of the item for y < nr; later rows (and lanes without an
         // item) re-read the item's last row (or the key's first) with a
         // row exponent of -inf, so they add exact zeros.  The loop ends
-        // once no lane of the wave has rows left; rows of gamma are fetched
-        // one row ahead of their use.
+        // once no lane of the wave has rows left.  Each row's gamma is
+        // loaded at the row's start: with four waves per SIMD the wait is
+        // mostly hidden, and loading it a row ahead measured slower.
         const int nlast = nr > 0 ? nr - 1 : 0;
-        float4 cur[kSubBlock / 2];
-#pragma unroll
-        for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = pq[x2];
 #pragma unroll
         for (int y = 0; y < kSubBlock; ++y) {
           if (!__any(y < nr)) break;  // uniform
-          float4 nxt[kSubBlock / 2];
-          if (y + 1 < kSubBlock) {
-            const int yn = y + 1 < nlast ? y + 1 : nlast;
+          const int yl = y < nlast ? y : nlast;
+          float4 cur[kSubBlock / 2];
 #pragma unroll
-            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) nxt[x2] = pq[yn * (TW / 2) + x2];
-          }
+          for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = pq[yl * (TW / 2) + x2];
           const float dv = (float)(by + y) - b.y;
-          const float B = fmaf(t12, dv, P);
+          const float B0 = fmaf(t11, bxf, fmaf(t12, dv, P));  // t1 at the strip's first column
           const float t2 = t22 * dv;
           const float erow = y < nr ? fmaf(-t2, t2, d) : -INFINITY;
-          float rge = 0.f, ra = 0.f;
+          // per row: sum ge, sum ge j, sum ge j^2 over the strip's columns
+          // j = 0..7; with t1 = B0 + t11 j the row's sum ge t1 and sum ge t1 x
+          // (x = bx0 + j) follow from them, which saves the per-pixel
+          // product ge t1 and the sums over it
+          float rge = 0.f, rj = 0.f, rjj = 0.f;
 #pragma unroll
           for (int x2 = 0; x2 < kSubBlock / 2; ++x2) {
             const float4 gg2 = cur[x2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
+              const int j = 2 * x2 + h;
               const float gx = h ? gg2.z : gg2.x, gy = h ? gg2.w : gg2.y;
-              const float xf = (float)(bx0 + 2 * x2 + h);
-              const float t1 = fmaf(t11, xf, B);
+              const float t1 = j ? fmaf(t11, (float)j, B0) : B0;
               const float w = fast_exp2(support_clamp(fmaf(-t1, t1, erow), kcut));  // the weight over s
               const float gw = fmaf(gx, c, -gy);  // dL/dw = gamma (c - c_hat)
               const float ge = w * gw;
               rge += ge;
               Sdc = fmaf(gx, w, Sdc);
-              const float av = ge * t1;
-              ra += av;
-              Sau = fmaf(av, xf, Sau);
+              if (j) {
+                rj = fmaf(ge, (float)j, rj);
+                rjj = fmaf(ge, (float)(j * j), rjj);
+              }
             }
           }
+          const float ra = fmaf(t11, rj, B0 * rge);  // sum ge t1
+          Sau = fmaf(bxf, ra, Sau);                   // + sum ge t1 x = bx0 ra + t11 rjj + B0 rj
+          Sau = fmaf(t11, rjj, Sau);
+          Sau = fmaf(B0, rj, Sau);
           Sge += rge;
           Sa += ra;
           S12 = fmaf(dv, ra, S12);
           Sb = fmaf(t2, rge, Sb);
           S22 = fmaf(t2 * dv, rge, S22);
-          if (y + 1 < kSubBlock) {
-#pragma unroll
-            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = nxt[x2];
-          }
         }
         if (has) {
           slot[wave][0][q] = Sge;
@@ -565,7 +595,9 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
                   Sb = acc[5] * sw, Sdc = acc[6] * sw;
       // w = 2^(e0 - t1^2 - t2^2):  dL/ds = -ln2 w dL/dw, s = t1^2 + t2^2.
       const float k2 = 2.f * ln2;
-      const uint32_t eidx = sval[i];
+      // keeps the address arithmetic here: moved up beside the load, it
+      // would wait for it at the chunk's start
+      asm volatile("" : "+v"(eidx));
       partial[2 * (size_t)eidx] = make_float4(-k2 * (Sau - du0 * Sa), -k2 * S12, -k2 * S22, k2 * a.x * Sa);
       partial[2 * (size_t)eidx + 1] = make_float4(k2 * (a.y * Sa + a.z * Sb), ln2 * Sge, Sdc, 0.f);
     }
