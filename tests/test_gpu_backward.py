@@ -58,6 +58,25 @@ def test_mse_loss_gradients_random_opacity(R):
         check_grads(gg, ref)
 
 
+@pytest.mark.parametrize("chi2", [60.0, 200.0])
+def test_large_cutoff_forward_and_gradients(R, chi2):
+    """Cut-offs near and beyond chi^2 = 88.7, where the kernels' scaled
+    weights switch to dropping weights below 2^-64 of a Gaussian's peak (a
+    stated reading of Eq. 12 for such chi^2): image and gradients against the
+    oracle's exact cut-off, no overflow or non-finite value anywhere."""
+    from tests.parity import check_image
+    g = synth.make_gaussians(200, 61, (0, 0, 0), (1, 1, 1), (0.03, 0.12), aniso_max=6.0, opacity="random")
+    pl = synth.random_planes(3, 62, (36, 30), 1 / 32, 0.35, 0.65)
+    rng = np.random.default_rng(63)
+    dimg = rng.standard_normal(pl.npix).astype(np.float32).astype(np.float64)
+    for tw, th in ((16, 16), (32, 16)):
+        img, gg, plan = _fwd_bwd(R, g, pl, dimg, R.Params(chi2=chi2, tile_w=tw, tile_h=th, box_mode=2))
+        assert np.all(np.isfinite(img)) and all(np.all(np.isfinite(v)) for v in gg.values())
+        check_image(img, g, pl, plan.params)
+        ref = oracle.grad(g, pl, dimg, oracle_params(plan.params))
+        print((chi2, tw, th), check_grads(gg, ref))
+
+
 def _fd_oracle(g, X, dout, prm, h=1e-6):
     base = {k: np.array(getattr(g, k), dtype=np.float64) for k in ("means", "lraw", "intensity", "opacity")}
     out = {}
