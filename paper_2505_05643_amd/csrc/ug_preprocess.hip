@@ -424,6 +424,44 @@ __device__ __forceinline__ void write_gauss_grad(const ug_gaussians& g, int i, c
 // whose records all sit in one wave gets its gradient here.  Each wave also
 // leaves its first and last segment sums in side[] for the Gaussians that
 // span waves (k_gauss_grad).  Deterministic, no atomics.
+// Float plane constants as the record adjoint stages them in LDS (o, R^-1,
+// e1, e2, |det R|, sx, sy): launches with up to kStagePlanes planes read
+// them from LDS instead of gathering each record's plane from memory (a
+// wave's 64 records touch many planes, and the gathers queue on the
+// vector-memory address path).
+constexpr int kPlaneFloats = 21;
+constexpr int kStagePlanes = 256;
+
+__device__ __forceinline__ void plane_to_lds(const PlaneT<float>& P, float* d) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d[k] = P.o[k];
+    d[12 + k] = P.e1[k];
+    d[15 + k] = P.e2[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) d[3 + k] = P.rinv[k];
+  d[18] = P.absdet;
+  d[19] = P.sx;
+  d[20] = P.sy;
+}
+
+__device__ __forceinline__ PlaneT<float> plane_from_lds(const float* d) {
+  PlaneT<float> P;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    P.o[k] = d[k];
+    P.e1[k] = d[12 + k];
+    P.e2[k] = d[15 + k];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) P.rinv[k] = d[3 + k];
+  P.absdet = d[18];
+  P.sx = d[19];
+  P.sy = d[20];
+  return P;
+}
+
 __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const PlaneConst* __restrict__ pc,
                                                         RenderParams rp, const Ctrl* __restrict__ ctrl,
                                                         const uint2* __restrict__ rec_pair,
@@ -434,6 +472,12 @@ __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const Pl
                                                         float* __restrict__ side, float* __restrict__ d_means,
                                                         float* __restrict__ d_lraw, float* __restrict__ d_int,
                                                         float* __restrict__ d_op, int accumulate) {
+  extern __shared__ float s_plane[];  // rp.p x kPlaneFloats when staged
+  const bool staged = rp.p <= kStagePlanes;
+  if (staged) {
+    for (int q = threadIdx.x; q < rp.p; q += 256) plane_to_lds(plane_as<float>(pc[q]), s_plane + q * kPlaneFloats);
+    __syncthreads();
+  }
   const bool ok = (ctrl->flags & (kFlagRecCap | kFlagKeyCap)) == 0;
   const uint32_t nrec = ok ? ctrl->n_rec_eff : 0u;
   const uint32_t nw = (nrec + 63u) / 64u;
@@ -472,7 +516,7 @@ __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const Pl
         const float dr[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
         GaussT<float> G;
         load_gauss<float>(g, (int)gp.x, rp.beta, G);
-        const PlaneT<float> P = plane_as<float>(pc[gp.y]);
+        const PlaneT<float> P = staged ? plane_from_lds(s_plane + gp.y * kPlaneFloats) : plane_as<float>(pc[gp.y]);
         ConicT<float> k;
         conic_cull(G, P, chi2, k);
         conic_full(G, P, k);
@@ -675,8 +719,12 @@ hipError_t launch_record_adjoint(const ug_gaussians& g, const PlaneConst* pc, co
                                  float* side, float* d_means, float* d_lraw, float* d_int, float* d_op,
                                  int accumulate, hipStream_t s) {
   uint32_t want = (rp.rec_cap + 255u) / 256u;
-  const uint32_t blocks = want < 1 ? 1 : (want > 8192 ? 8192 : want);
-  hipLaunchKernelGGL(k_record_adjoint, dim3(blocks), dim3(256), 0, s, g, pc, rp, ctrl, rec_pair, rec_koff,
+  // with staged planes every block loads them once: fewer, longer blocks
+  const bool staged = rp.p <= kStagePlanes;
+  const uint32_t cap = staged ? 2048u : 8192u;
+  const uint32_t blocks = want < 1 ? 1 : (want > cap ? cap : want);
+  const size_t lds = staged ? (size_t)rp.p * kPlaneFloats * sizeof(float) : 0;
+  hipLaunchKernelGGL(k_record_adjoint, dim3(blocks), dim3(256), lds, s, g, pc, rp, ctrl, rec_pair, rec_koff,
                      reinterpret_cast<const float4*>(partial), cnt_rec, off_rec, side, d_means, d_lraw, d_int, d_op,
                      accumulate);
   return hipGetLastError();
