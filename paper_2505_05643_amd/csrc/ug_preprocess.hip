@@ -283,28 +283,52 @@ __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, c
   }
 }
 
+// Launches with up to kStagePlanes planes give the record kernel and the
+// record adjoint their planes' constants from LDS (copied once per block)
+// instead of gathering each record's plane from memory: a wave's 64 records
+// touch many planes, and those gathers queue on the vector-memory address
+// path.
+constexpr int kStagePlanes = 256;
+static_assert(sizeof(PlaneConst) % 8 == 0 && sizeof(PlaneInt) % 8 == 0, "LDS plane staging layout");
+
 // FP64 in-plane conic and footprint of each record; key counts and the
-// block's total.
-__global__ __launch_bounds__(256) void k_record(ug_gaussians g, const PlaneConst* __restrict__ pc,
-                                                const PlaneInt* __restrict__ pint, RenderParams rp,
-                                                const uint2* __restrict__ rec_pair, Rec* __restrict__ recs,
-                                                uint32_t* __restrict__ rec_nkey,
-                                                uint32_t* __restrict__ blk_tot, const Ctrl* __restrict__ ctrl) {
+// block's total.  STAGE (launches of up to kStagePlanes planes): the planes'
+// constants are copied to LDS once per block (512 threads, so the 56 KB of
+// a 256-plane launch still leaves the 16 waves per CU the registers allow)
+// instead of being gathered per record from memory.
+template <bool STAGE>
+__global__ __launch_bounds__(STAGE ? 512 : 256) void k_record(ug_gaussians g, const PlaneConst* __restrict__ pc,
+                                                              const PlaneInt* __restrict__ pint, RenderParams rp,
+                                                              const uint2* __restrict__ rec_pair,
+                                                              Rec* __restrict__ recs, uint32_t* __restrict__ rec_nkey,
+                                                              uint32_t* __restrict__ blk_tot,
+                                                              const Ctrl* __restrict__ ctrl) {
+  constexpr uint32_t NT = STAGE ? 512u : 256u;
+  extern __shared__ double s_planes[];  // STAGE: rp.p PlaneConst, then rp.p PlaneInt
   __shared__ uint32_t s_tot;
   const uint32_t nrec = ctrl->n_rec_eff;
   const uint32_t rpb = record_rpb_dev(nrec, gridDim.x);
   const uint32_t r_begin = blockIdx.x * rpb;
   if (r_begin >= nrec) return;  // uniform
+  PlaneConst* s_pc = reinterpret_cast<PlaneConst*>(s_planes);
+  PlaneInt* s_pi = reinterpret_cast<PlaneInt*>(s_pc + rp.p);
+  if (STAGE) {
+    for (int q = (int)threadIdx.x; q < rp.p; q += (int)NT) {
+      s_pc[q] = pc[q];
+      s_pi[q] = pint[q];
+    }
+  }
   if (threadIdx.x == 0) s_tot = 0;
   __syncthreads();
   const double chi2 = (double)rp.chi2;
   uint32_t mine = 0;
   const uint32_t r_end = min(r_begin + rpb, nrec);
-  for (uint32_t r = r_begin + threadIdx.x; r < r_end; r += 256) {
+  for (uint32_t r = r_begin + threadIdx.x; r < r_end; r += NT) {
     const uint2 gp = rec_pair[r];
     GaussIn G;
     load_gauss(g, (int)gp.x, (double)rp.beta, G);
-    const PlaneConst& P = pc[gp.y];
+    const PlaneConst& P = STAGE ? s_pc[gp.y] : pc[gp.y];
+    const PlaneInt& PI = STAGE ? s_pi[gp.y] : pint[gp.y];
     const PlaneT<double> Pd = plane_as<double>(P);
     Conic k;
     const bool meets = conic_cull(G, Pd, chi2, k);
@@ -312,8 +336,8 @@ __global__ __launch_bounds__(256) void k_record(ug_gaussians g, const PlaneConst
     Footprint f;
     // Box support: the FP64 Phase-1 decision is final (a pair the
     // conservative float cull let through would otherwise fill its box).
-    const bool ok = rp.box_support ? (meets && make_box_record(G, P, pint[gp.y], k, chi2, f))
-                                   : make_footprint(G, P, pint[gp.y], k, chi2, rp.box_mode, rp.tile_w, rp.tile_h, f);
+    const bool ok = rp.box_support ? (meets && make_box_record(G, P, PI, k, chi2, f))
+                                   : make_footprint(G, P, PI, k, chi2, rp.box_mode, rp.tile_w, rp.tile_h, f);
     if (!ok) {
       // the plane cuts the ellipsoid (or box) outside the image: a record with no keys
       f.keys = 0;
@@ -425,12 +449,8 @@ __device__ __forceinline__ void write_gauss_grad(const ug_gaussians& g, int i, c
 // leaves its first and last segment sums in side[] for the Gaussians that
 // span waves (k_gauss_grad).  Deterministic, no atomics.
 // Float plane constants as the record adjoint stages them in LDS (o, R^-1,
-// e1, e2, |det R|, sx, sy): launches with up to kStagePlanes planes read
-// them from LDS instead of gathering each record's plane from memory (a
-// wave's 64 records touch many planes, and the gathers queue on the
-// vector-memory address path).
+// e1, e2, |det R|, sx, sy).
 constexpr int kPlaneFloats = 21;
-constexpr int kStagePlanes = 256;
 
 __device__ __forceinline__ void plane_to_lds(const PlaneT<float>& P, float* d) {
 #pragma unroll
@@ -698,8 +718,14 @@ hipError_t launch_cull_write(const RenderParams& rp, const uint32_t* cnt_rec, co
 hipError_t launch_record(const ug_gaussians& g, const PlaneConst* pc, const PlaneInt* pint, const RenderParams& rp,
                          const uint2* rec_pair, Rec* recs, uint32_t* rec_nkey, uint32_t* blk_tot,
                          Ctrl* ctrl, hipStream_t s) {
-  hipLaunchKernelGGL(k_record, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, g, pc, pint, rp,
-                     rec_pair, recs, rec_nkey, blk_tot, ctrl);
+  if (rp.p <= kStagePlanes) {
+    const size_t lds = (size_t)rp.p * (sizeof(PlaneConst) + sizeof(PlaneInt));
+    hipLaunchKernelGGL(k_record<true>, dim3(record_blocks(rp.rec_cap)), dim3(512), lds, s, g, pc, pint, rp,
+                       rec_pair, recs, rec_nkey, blk_tot, ctrl);
+  } else {
+    hipLaunchKernelGGL(k_record<false>, dim3(record_blocks(rp.rec_cap)), dim3(256), 0, s, g, pc, pint, rp,
+                       rec_pair, recs, rec_nkey, blk_tot, ctrl);
+  }
   return hipGetLastError();
 }
 
