@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_bwd_prep(const PlaneInt* __restrict__ p
 // those of walking all 64 pixels of every touched sub-block.
 constexpr int kBwdSlots = 192;
 
-template <int TW, int TH>
+template <int TW, int TH, bool GT>
 __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl,
                                                    const uint32_t* __restrict__ tile_org,
                                                    const uint32_t* __restrict__ skey,
@@ -346,6 +346,18 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
   __shared__ uint32_t queue[4][kBwdSlots];   // key | sub-block << 6 | first row << 10 | rows << 13
   __shared__ uint8_t order[4][kBwdSlots];    // items with rows, by row count (largest first)
   __shared__ float slot[4][7][kBwdSlots];
+  // GT (tiles of at most 512 pixels, launches with many keys): each wave
+  // copies the gamma of its chunk's first tile (at most 4 KB) into LDS, and
+  // items of that tile (nearly all: a tile holds many chunks) read their
+  // rows there instead of through the L1, whose accesses otherwise set the
+  // kernel's pace.  It costs a wave per SIMD of occupancy (LDS), which
+  // small launches feel more than they gain; larger tiles would take too
+  // much LDS.  Without it every row is read from memory.
+  static_assert(!GT || TW * TH <= 512, "staged tile size");
+  constexpr bool kGT = GT;
+  constexpr int kGTQ = kGT ? TW * TH / 2 : 1;  // float4 per staged tile
+  constexpr int kGTL = (kGTQ + 63) / 64;       // of them per lane
+  __shared__ float4 gt[4][kGTQ];
   const uint32_t n = ctrl->n_key_eff;
   const float ln2 = (float)kLn2;
   const bool cut = kcut != kNoCutBits;
@@ -384,6 +396,15 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
     const bool act = i < n;
     uint32_t eidx = act ? sval[i] : 0u;  // where the key's partial goes
     const uint32_t m = act ? kwN >> kMaskShift : 0u;
+    // the staged tile: lane 0's key's (the wave's LDS syncs below order
+    // these writes before the evaluation reads them)
+    const uint32_t t0 = __builtin_amdgcn_readfirstlane(kwN & kmask);
+    if constexpr (kGT) {
+      const float4* __restrict__ src = reinterpret_cast<const float4*>(gq + (size_t)t0 * (TW * TH));
+#pragma unroll
+      for (int j = 0; j < kGTL; ++j)
+        if (j * 64 + lane < kGTQ) gt[wave][j * 64 + lane] = src[j * 64 + lane];
+    }
     if (act) {
       const uint32_t t = kwN & kmask;
       const RecAcc A = AN;
@@ -512,6 +533,8 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
         const int bx0 = (sb % K) * kSubBlock, by = (sb / K) * kSubBlock + ry;
         const float bxf = (float)bx0;
         const float4* __restrict__ pq = reinterpret_cast<const float4*>(gq + (size_t)t * (TW * TH) + by * TW + bx0);
+        const bool staged = kGT && t == t0;
+        const int gbase = by * (TW / 2) + bx0 / 2;  // the item's first row in the staged tile (float4)
         float Sge = 0.f, Sa = 0.f, Sau = 0.f, S12 = 0.f, S22 = 0.f, Sb = 0.f, Sdc = 0.f;
         // row y of the item for y < nr; later rows (and lanes without an
         // item) re-read the item's last row (or the key's first) with a
@@ -525,8 +548,13 @@ __global__ __launch_bounds__(256) void k_accum_bwd(const Ctrl* __restrict__ ctrl
           if (!__any(y < nr)) break;  // uniform
           const int yl = y < nlast ? y : nlast;
           float4 cur[kSubBlock / 2];
+          if (staged) {
 #pragma unroll
-          for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = pq[yl * (TW / 2) + x2];
+            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = gt[wave][gbase + yl * (TW / 2) + x2];
+          } else {
+#pragma unroll
+            for (int x2 = 0; x2 < kSubBlock / 2; ++x2) cur[x2] = pq[yl * (TW / 2) + x2];
+          }
           const float dv = (float)(by + y) - b.y;
           const float B0 = fmaf(t11, bxf, fmaf(t12, dv, P));  // t1 at the strip's first column
           const float t2 = t22 * dv;
@@ -702,6 +730,26 @@ hipError_t launch_bwd_prep(int tile_w, int tile_h, const PlaneInt* pint, const u
   return hipErrorInvalidValue;
 }
 
+// Launches with at least this key capacity (about 100,000 64-key chunks)
+// stage their chunks' gamma tiles in LDS when the tile fits.
+constexpr uint32_t kGTMinKeys = 1u << 22;
+
+template <int TW, int TH>
+static hipError_t bwd_launch(bool gt, uint32_t blocks, hipStream_t s, const Ctrl* ctrl, const uint32_t* tile_org,
+                             const uint32_t* skey, const uint32_t* sval, const uint32_t* srec, const Rec* recs,
+                             const float2* g2, float4* p4, int kcut) {
+  if constexpr (TW * TH <= 512) {
+    if (gt) {
+      hipLaunchKernelGGL((k_accum_bwd<TW, TH, true>), dim3(blocks), dim3(256), 0, s, ctrl, tile_org, skey, sval,
+                         srec, recs, g2, p4, kcut);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_accum_bwd<TW, TH, false>), dim3(blocks), dim3(256), 0, s, ctrl, tile_org, skey, sval, srec,
+                     recs, g2, p4, kcut);
+  return hipGetLastError();
+}
+
 hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint32_t* tile_org,
                             const uint32_t* skey, const uint32_t* sval,
                             const uint32_t* srec, const Rec* recs,
@@ -710,12 +758,10 @@ hipError_t launch_accum_bwd(int tile_w, int tile_h, const Ctrl* ctrl, const uint
   float4* p4 = reinterpret_cast<float4*>(partial);
   uint32_t want = (key_cap / 64u + 4u) / 4u;
   const uint32_t blocks = want < 1u ? 1u : (want > 16384u ? 16384u : want);
+  const bool gt = key_cap >= kGTMinKeys;
 #define UG_BWD(W, H)                                                                                          \
-  if (tile_w == W && tile_h == H) {                                                                           \
-    hipLaunchKernelGGL((k_accum_bwd<W, H>), dim3(blocks), dim3(256), 0, s, ctrl, tile_org, skey, sval, srec, \
-                       recs, g2, p4, cut ? kCutBits : kNoCutBits);                                            \
-    return hipGetLastError();                                                                                 \
-  }
+  if (tile_w == W && tile_h == H) return bwd_launch<W, H>(gt, blocks, s, ctrl, tile_org, skey, sval, srec, recs, \
+                                                          g2, p4, cut ? kCutBits : kNoCutBits);
   UG_TILE_SHAPES(UG_BWD)
 #undef UG_BWD
   return hipErrorInvalidValue;
