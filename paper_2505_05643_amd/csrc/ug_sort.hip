@@ -101,9 +101,10 @@ __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t* __restrict__ cn
 // kItems keys per thread and round: 8 for small inputs (more blocks, less
 // LDS), 16 when every block walks several rounds.
 
-// Every key carries two payload words (emission index, record id).  The
-// ranking touches only the keys; the payload is read when the reordered
-// round is written out, from the round's own input window.
+// Every key carries two payload words (emission index, record id).  They
+// are loaded with the keys (coalesced, in flight during the ranking) and
+// follow them through the same LDS slots one word at a time: the keys are
+// reordered and written, then the emission indices, then the record ids.
 struct SortSet {
   uint32_t* key;
   uint32_t* val;  // emission index; generated (= position) in the first pass
@@ -119,8 +120,7 @@ __device__ __forceinline__ void radix_scatter(const Ctrl* __restrict__ ctrl, Sor
                                                                 uint32_t T) {
   constexpr int kRound = kSortThreads * kItems;
   const uint32_t* __restrict__ kin = in.key;
-  __shared__ uint32_t s_key[kRound];
-  __shared__ uint32_t s_src[kRound];  // input position of the key in each slot
+  __shared__ uint32_t s_key[kRound];  // the round reordered by digit: keys, then each payload word
   constexpr int kPer = D / kSortThreads;  // digits per thread, consecutive
   __shared__ uint32_t run[D];      // global output position of the next key of each digit
   __shared__ uint32_t loc[D];      // first LDS slot of each digit in this round
@@ -168,7 +168,7 @@ __device__ __forceinline__ void radix_scatter(const Ctrl* __restrict__ ctrl, Sor
     // the round's keys split evenly over the waves, in whole loads of 64
     const uint32_t n_round = min((uint32_t)kRound, e - base);
     const uint32_t seg = ((n_round + 255u) / 256u) * 64u;
-    uint32_t kk[kItems], rr[kItems];
+    uint32_t kk[kItems], rr[kItems], vv[kItems], rc[kItems];
     // all of the round's loads first: the ranking's wave fences would
     // otherwise keep each load behind the previous key's LDS update
 #pragma unroll
@@ -176,6 +176,8 @@ __device__ __forceinline__ void radix_scatter(const Ctrl* __restrict__ ctrl, Sor
       const uint32_t i = base + (uint32_t)wave * seg + (uint32_t)(it * 64 + lane);
       const bool valid = (uint32_t)(it * 64) < seg && i < e;
       kk[it] = valid ? kin[i] : 0u;
+      vv[it] = gen_val ? i : (valid ? in.val[i] : 0u);
+      rc[it] = valid ? in.rec[i] : 0u;
     }
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
@@ -229,44 +231,42 @@ __device__ __forceinline__ void radix_scatter(const Ctrl* __restrict__ ctrl, Sor
       }
     }
     __syncthreads();
+    // slot of each of the thread's keys in the reordered round
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       if (rr[it] != 0xffffffffu) {
         const uint32_t d = (kk[it] >> shift) & dmask;
-        const uint32_t slot = loc[d] + wcnt[wave][d] + rr[it];
-        s_key[slot] = kk[it];
-        s_src[slot] = base + (uint32_t)wave * seg + (uint32_t)(it * 64 + lane);  // the key's input position
+        rr[it] += loc[d] + wcnt[wave][d];
+        s_key[rr[it]] = kk[it];
       }
     }
     __syncthreads();
-    // write-out: every slot's payload is gathered before any store (the
-    // input and output sets are different arrays, which the compiler cannot
-    // know, so interleaved loads would wait for the stores before them)
-    constexpr int kHalf = kItems < 8 ? kItems : 8;  // slots gathered per batch
+    // keys out, as contiguous runs per digit; each slot's output position is
+    // kept for the payload words
+    uint32_t opos[kItems];
 #pragma unroll
-    for (int h = 0; h < kItems; h += kHalf) {
-      uint32_t opos[kHalf], okey[kHalf], oval[kHalf], orec[kHalf];
-#pragma unroll
-      for (int j = 0; j < kHalf; ++j) {
-        const uint32_t i = (uint32_t)tid + (uint32_t)((h + j) * kSortThreads);
-        opos[j] = 0xffffffffu;
-        if (i < n_round) {
-          const uint32_t k = s_key[i], src = s_src[i];
-          const uint32_t d = (k >> shift) & dmask;
-          opos[j] = run[d] + (i - loc[d]);
-          okey[j] = k;
-          oval[j] = gen_val ? src : in.val[src];
-          orec[j] = in.rec[src];
-        }
+    for (int j = 0; j < kItems; ++j) {
+      const uint32_t i = (uint32_t)tid + (uint32_t)(j * kSortThreads);
+      opos[j] = 0xffffffffu;
+      if (i < n_round) {
+        const uint32_t k = s_key[i];
+        const uint32_t d = (k >> shift) & dmask;
+        opos[j] = run[d] + (i - loc[d]);
+        out.key[opos[j]] = k;
       }
+    }
+    // the two payload words through the same slots
 #pragma unroll
-      for (int j = 0; j < kHalf; ++j) {
-        if (opos[j] != 0xffffffffu) {
-          out.key[opos[j]] = okey[j];
-          out.val[opos[j]] = oval[j];
-          out.rec[opos[j]] = orec[j];
-        }
-      }
+    for (int w = 0; w < 2; ++w) {
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < kItems; ++it)
+        if (rr[it] != 0xffffffffu) s_key[rr[it]] = w == 0 ? vv[it] : rc[it];
+      __syncthreads();
+      uint32_t* __restrict__ dst = w == 0 ? out.val : out.rec;
+#pragma unroll
+      for (int j = 0; j < kItems; ++j)
+        if (opos[j] != 0xffffffffu) dst[opos[j]] = s_key[(uint32_t)tid + (uint32_t)(j * kSortThreads)];
     }
     __syncthreads();
 #pragma unroll
