@@ -262,6 +262,46 @@ def test_binning_keys_and_ranges(R):
             print((tw, th, bm), "keys", n, "records", len(recs))
 
 
+def test_emission_layout_small_and_whole_plane_records(R):
+    """Key emission for rounds of 256 records of a few keys each (512 small
+    Gaussians) and rounds of tens of thousands (256 that cover the whole
+    plane): the keys are laid out record by record, each record's tiles
+    row-major inside its tile rectangle (all of it for conic boxes), the
+    sort is numpy's stable argsort, and the image matches the oracle."""
+    small = synth.make_gaussians(512, 91, (0.05, 0.05, 0.49), (0.95, 0.95, 0.51), (0.004, 0.01), opacity="random")
+    big = synth.make_gaussians(256, 92, (0.4, 0.4, 0.45), (0.6, 0.6, 0.55), (0.2, 0.3), opacity="random")
+    g = synth.Gaussians(*(np.concatenate([getattr(small, f), getattr(big, f)])
+                          for f in ("means", "lraw", "intensity", "opacity")))
+    pl = synth.pack_planes([np.eye(3)], [(0.5, 0.5, 0.5)], [(1 / 96, 1 / 96)], [(96, 96)])
+    for bm in (1, 2):
+        params = R.Params(tile_w=8, tile_h=8, box_mode=bm)
+        img, plan = _render(R, g, pl, params)
+        check_image(img, g, pl, plan.params)
+        key, eidx, rec, _ = plan.debug_keys()
+        recs = plan.debug_records()
+        n = key.size
+        tile = (key & np.uint32((1 << 31) - 1)).astype(np.int64)
+        emitted_tile = np.empty(n, dtype=np.int64)
+        emitted_rec = np.empty(n, dtype=np.int64)
+        emitted_tile[eidx] = tile
+        emitted_rec[eidx] = rec
+        assert np.array_equal(np.sort(eidx), np.arange(n, dtype=np.uint32))
+        assert np.all(np.diff(emitted_rec) >= 0), "keys are emitted record by record"
+        assert np.array_equal(np.argsort(emitted_tile, kind="stable"), eidx.astype(np.int64))
+        # within a record: its tiles in row-major order inside its rectangle
+        r = recs[emitted_rec]
+        tx, ty = emitted_tile % 12, emitted_tile // 12
+        assert np.all((tx >= r["tx0"]) & (tx <= r["tx1"]) & (ty >= r["ty0"]) & (ty <= r["ty1"]))
+        same = emitted_rec[1:] == emitted_rec[:-1]
+        assert np.all(emitted_tile[1:][same] > emitted_tile[:-1][same])
+        if bm == 1:  # conic boxes: every tile of the rectangle
+            area = (recs["tx1"].astype(np.int64) - recs["tx0"] + 1) * (recs["ty1"].astype(np.int64) - recs["ty0"] + 1)
+            assert np.array_equal(np.bincount(emitted_rec, minlength=len(recs)), area)
+        per_round = np.bincount(emitted_rec // 256)
+        assert per_round.max() > 16 * 256 and per_round.min() < 4 * 256, per_round
+        print("box", bm, "keys per round of 256 records", per_round)
+
+
 @pytest.mark.parametrize("k,count", [(1, 1500), (4, 300)])
 def test_configs_sampled_pixels_phase2_scatter(R, k, count):
     """The Phase-2 atomic scatter on full-size workloads: a seeded sample of
