@@ -369,42 +369,52 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
   if (r_begin >= nrec) return;  // uniform
   const uint32_t nact = (nrec + rpb - 1) / rpb;
   const uint32_t r_end = min(r_begin + rpb, nrec);
-  // the first round's record data does not depend on the block prefix:
-  // issue its loads before the prefix so the two round trips overlap
+  // Each round's record data is loaded one round ahead (the first round's
+  // before the block prefix), so its round trip overlaps the previous
+  // round's scan and emission.  Lanes past the block's records load its last
+  // record and drop it (no branch around the loads: the wait at a branch's
+  // join would take every load in flight).  The plane lookup needs the plane
+  // index first; it is issued at the end of the previous round, before the
+  // next prefetch, so the emission waits for it and not for the prefetch
+  // (loads complete in issue order as far as the waits can tell).
   uint32_t r = r_begin + threadIdx.x;
   bool act = r < r_end;
-  uint32_t nk = 0u;
-  RecAcc ra{};
-  RecGeo ge{};
-  PlaneInt PI{};
-  if (act) {
-    nk = rec_nkey[r];
-    ra = recs[r].acc;
-    ge = recs[r].geo;
-    PI = pint[rec_pair[r].y];
+  uint32_t pl, nk;
+  RecAcc ra;
+  RecGeo ge;
+  {
+    const uint32_t rl = act ? r : r_end - 1u;
+    pl = rec_pair[rl].y;
+    ra = recs[rl].acc;
+    ge = recs[rl].geo;
+    nk = act ? rec_nkey[rl] : 0u;
   }
   unsigned long long carry = block_prefix(blk_tot, blockIdx.x, s_sh);
+  PlaneInt PI = pint[pl];
   for (uint32_t r0 = r_begin; r0 < r_end; r0 += 256) {
-    if (r0 != r_begin) {
-      r = r0 + threadIdx.x;
-      act = r < r_end;
-      nk = 0u;
-      if (act) {
-        nk = rec_nkey[r];
-        ra = recs[r].acc;
-        ge = recs[r].geo;
-        PI = pint[rec_pair[r].y];
-      }
-    }
+    const uint32_t rn = r + 256u;
+    const bool actn = rn < r_end;
+    const uint32_t rl = actn ? rn : r_end - 1u;
+    const uint32_t pln = rec_pair[rl].y;
+    const RecAcc ran = recs[rl].acc;
+    const RecGeo gen = recs[rl].geo;
+    const uint32_t nkl = rec_nkey[rl];
+    const uint32_t nkn = actn ? nkl : 0u;
     unsigned long long tot;
     const unsigned long long koff = carry + block_exscan_256<unsigned long long>(nk, s_sh, tot);
     carry += tot;
     if (act) {
       rec_koff[r] = (uint32_t)(koff < rp.key_cap ? koff : rp.key_cap);
       if (nk > 0 && koff + nk <= rp.key_cap)
-        emit_keys(ra, ge, PI, rp.box_mode, rp.tile_w, rp.tile_h, r, (uint32_t)koff, (uint32_t)(koff + nk), key_tile,
-                  rec_of_key);
+        emit_keys(ra, ge, PI, rp.box_mode, rp.tile_w, rp.tile_h, r, (uint32_t)koff, (uint32_t)(koff + nk),
+                  key_tile, rec_of_key);
     }
+    r = rn;
+    act = actn;
+    nk = nkn;
+    ra = ran;
+    ge = gen;
+    PI = pint[pln];
   }
   if (blockIdx.x == nact - 1 && threadIdx.x == 0) {
     ctrl->n_key = carry;
