@@ -70,21 +70,38 @@ __device__ __forceinline__ PlaneT<T> plane_as(const PlaneConst& P) {
   return q;
 }
 
+// A Gaussian's stored parameters as loaded (split from their set-up so a
+// kernel can issue the loads early, beside other loads it waits for).
+struct GaussRaw {
+  float mu[3], l[6], a, c;
+};
+
+__device__ __forceinline__ GaussRaw load_gauss_raw(const ug_gaussians& g, int i) {
+  GaussRaw r;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r.mu[k] = g.means[3 * i + k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.l[k] = g.lraw[6 * i + k];
+  r.a = g.opacity[i];
+  r.c = g.intensity[i];
+  return r;
+}
+
 template <typename T>
-__device__ __forceinline__ void load_gauss(const ug_gaussians& g, int i, T beta, GaussT<T>& G) {
+__device__ __forceinline__ void gauss_setup(const GaussRaw& r, T beta, GaussT<T>& G) {
   bool fin = true;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    G.mu[k] = (T)g.means[3 * i + k];
+    G.mu[k] = (T)r.mu[k];
     fin = fin && __builtin_isfinite(G.mu[k]);
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    G.l[k] = (T)g.lraw[6 * i + k];
+    G.l[k] = (T)r.l[k];
     fin = fin && __builtin_isfinite(G.l[k]);
   }
-  G.a = (T)g.opacity[i];
-  G.c = (T)g.intensity[i];
+  G.a = (T)r.a;
+  G.c = (T)r.c;
   fin = fin && __builtin_isfinite(G.a) && __builtin_isfinite(G.c);
   G.finite = fin;
   // Eq. 11: diagonal entries squared plus beta.
@@ -104,6 +121,11 @@ __device__ __forceinline__ void load_gauss(const ug_gaussians& g, int i, T beta,
   const float sp = fmaxf(na, 0.f) + log1pf(expf(-fabsf(na)));
   G.log2a = (T)(-sp * (float)(1.0 / kLn2));
   G.alpha = (T)(1.f / (1.f + expf(na)));
+}
+
+template <typename T>
+__device__ __forceinline__ void load_gauss(const ug_gaussians& g, int i, T beta, GaussT<T>& G) {
+  gauss_setup(load_gauss_raw(g, i), beta, G);
 }
 
 // Forward substitution y = L^-1 q.

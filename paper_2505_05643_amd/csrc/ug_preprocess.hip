@@ -524,6 +524,9 @@ __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const Pl
       const uint2 gp = rec_pair[r];
       gid = gp.x;
       const uint32_t k0 = rec_koff[r], k1 = rec_koff[r + 1];
+      // the Gaussian's parameters are loaded with the key range, so the two
+      // round trips overlap
+      const GaussRaw gr = load_gauss_raw(g, (int)gp.x);
       float4 a = make_float4(0.f, 0.f, 0.f, 0.f), c = a;
       // two keys per step, both loaded before either is added (same order
       // of additions as one key at a time)
@@ -545,7 +548,7 @@ __global__ __launch_bounds__(256) void k_record_adjoint(ug_gaussians g, const Pl
       if (k1 > k0) {
         const float dr[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
         GaussT<float> G;
-        load_gauss<float>(g, (int)gp.x, rp.beta, G);
+        gauss_setup(gr, rp.beta, G);
         const PlaneT<float> P = staged ? plane_from_lds(s_plane + gp.y * kPlaneFloats) : plane_as<float>(pc[gp.y]);
         ConicT<float> k;
         conic_cull(G, P, chi2, k);
