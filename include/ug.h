@@ -80,6 +80,14 @@ extern "C" {
                                  the one-wave form in the last bits (still deterministic).
                                  Not with tile_h = 32 and lds_batch = 256 (the staging
                                  would exceed 128 KB of LDS): UG_ERR_INVALID_ARG */
+#define UG_FLAG_CULL_EACH_PLANE 16 /* Phase-1 cull (Sec. 4.4) by testing every (Gaussian,
+                                 plane) pair.  Without it, launches of up to 256 planes
+                                 group the planes that differ only in the origin's third
+                                 coordinate (a stack of parallel slices) and test, per
+                                 Gaussian, only the planes of a group inside a window
+                                 that bounds the test's acceptance; the same test then
+                                 decides each of them, so the records are the same
+                                 either way.  A test and measurement switch            */
 
 /* ---- pipeline stages (measurement hooks) ------------------------------- */
 #define UG_STAGE_SETUP 0         /* plane pose set-up                                  */

@@ -30,6 +30,7 @@ UG_FLAG_COUNT_EVALS = 1
 UG_FLAG_SCATTER = 2
 UG_FLAG_BOX_SUPPORT = 4
 UG_FLAG_SPLIT_FORWARD = 8
+UG_FLAG_CULL_EACH_PLANE = 16
 UG_PARAM_TRI, UG_PARAM_SYM, UG_PARAM_QUAT = 0, 1, 2
 UG_PROBE_FMA, UG_PROBE_EXP, UG_PROBE_PAIRS, UG_PROBE_COPY = 0, 1, 2, 3
 

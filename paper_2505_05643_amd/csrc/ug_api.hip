@@ -23,7 +23,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t ctrl, pconst, pcull, cnt_rec, accbits, off_rec, blk_g, blk_r;
+  size_t ctrl, pconst, pcull, pgroups, cnt_rec, accbits, off_rec, blk_g, blk_r;
   size_t rec_pair, recs, rec_nkey, rec_koff, side;
   size_t tile_start, dsave, gq, hist;
   size_t key_tile0, key_tile1, key_val0, key_val1, rec_of_key, srec, partial;
@@ -80,6 +80,7 @@ void compute_layout(ug_plan* pl) {
   L.ctrl = take(sizeof(Ctrl));
   L.pconst = take(P * sizeof(PlaneConst));
   L.pcull = take(P * sizeof(PlaneCull));
+  L.pgroups = take(sizeof(PlaneGroups));
   L.cnt_rec = take(n * 4);
   L.accbits = take(accbits_words(pl->n, pl->p) * 8);
   L.off_rec = take(n * 8);
@@ -116,7 +117,8 @@ bool valid_params(const ug_params& p) {
   if (!(p.bg_alpha > 0.f) || !std::isfinite(p.bg_alpha)) return false;
   if (!std::isfinite(p.bg_color)) return false;
   if (p.box_mode != UG_BOX_PAPER && p.box_mode != UG_BOX_CONIC && p.box_mode != UG_BOX_ROWS) return false;
-  if ((p.flags & ~(UG_FLAG_COUNT_EVALS | UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT | UG_FLAG_SPLIT_FORWARD)) != 0)
+  if ((p.flags & ~(UG_FLAG_COUNT_EVALS | UG_FLAG_SCATTER | UG_FLAG_BOX_SUPPORT | UG_FLAG_SPLIT_FORWARD |
+                   UG_FLAG_CULL_EACH_PLANE)) != 0)
     return false;
   if ((p.flags & UG_FLAG_BOX_SUPPORT) && !(p.flags & UG_FLAG_SCATTER)) return false;
   const int ppl = p.px_per_lane ? p.px_per_lane : accum_default_ppl(p.tile_w, p.tile_h);
@@ -196,12 +198,13 @@ hipError_t enqueue_preprocess(const ug_plan* plan, const ug_gaussians& g, const 
   hipError_t e;
   {
     StageScope sc(plan, UG_STAGE_SETUP, s);
-    e = launch_init(pl, plan->d_pint, at<PlaneConst>(ws, L.pconst), at<PlaneCull>(ws, L.pcull), ctrl, s);
+    e = launch_init(pl, plan->d_pint, at<PlaneConst>(ws, L.pconst), at<PlaneCull>(ws, L.pcull),
+                    at<PlaneGroups>(ws, L.pgroups), (plan->prm.flags & UG_FLAG_CULL_EACH_PLANE) == 0, ctrl, s);
   }
   if (e != hipSuccess) return e;
   {
     StageScope sc(plan, UG_STAGE_CULL_COUNT, s);
-    e = launch_cull_count(g, at<PlaneCull>(ws, L.pcull), rp, at<uint32_t>(ws, L.cnt_rec),
+    e = launch_cull_count(g, at<PlaneCull>(ws, L.pcull), at<PlaneGroups>(ws, L.pgroups), rp, at<uint32_t>(ws, L.cnt_rec),
                           at<unsigned long long>(ws, L.accbits), at<uint32_t>(ws, L.blk_g), ctrl, s);
   }
   if (e != hipSuccess) return e;

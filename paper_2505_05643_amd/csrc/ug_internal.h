@@ -70,6 +70,20 @@ struct PlaneCull {
 };
 static_assert(sizeof(PlaneCull) == 32, "PlaneCull layout");
 
+// Planes grouped for the Phase-1 cull: a group holds the valid planes whose
+// cull constants agree bit for bit except the origin's third coordinate
+// (r3, o[0], o[1]), sorted by that coordinate; written by the plane set-up
+// for launches of up to kGroupMaxPlanes planes (use = 0 otherwise, or when
+// no group is large enough to be worth a search).
+constexpr int kGroupMaxPlanes = 256;
+struct PlaneGroups {
+  uint32_t use;
+  uint32_t pad[3];
+  uint32_t perm[kGroupMaxPlanes];  // plane at each sorted position
+  float oz[kGroupMaxPlanes];       // its origin's third coordinate
+  uint32_t end[kGroupMaxPlanes];   // one past the last position of its group
+};
+
 // ---------------------------------------------------------------- records
 // One accepted (Gaussian, plane) pair as the accumulate kernels use it.
 // In pixel-index units, with du = u - (ub + fu), dv = v - (vb + fv):

@@ -8,13 +8,14 @@ namespace ug {
 // ---- preprocess (ug_preprocess.hip)
 uint32_t cull_blocks(int n, int p);
 uint32_t record_blocks(uint32_t rec_cap);
-hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, PlaneCull* pcf, Ctrl* ctrl,
-                       hipStream_t s);
+hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, PlaneCull* pcf, PlaneGroups* pg,
+                       bool group, Ctrl* ctrl, hipStream_t s);
 // Phase-1 cull: per-(Gaussian, plane) acceptance bits and per-Gaussian record
 // counts, then record offsets and the compact (Gaussian, plane) pair list.
 size_t accbits_words(int n, int p);
-hipError_t launch_cull_count(const ug_gaussians& g, const PlaneCull* pcf, const RenderParams& rp, uint32_t* cnt_rec,
-                             unsigned long long* accbits, uint32_t* blk_tot, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_cull_count(const ug_gaussians& g, const PlaneCull* pcf, const PlaneGroups* pg,
+                             const RenderParams& rp, uint32_t* cnt_rec, unsigned long long* accbits, uint32_t* blk_tot,
+                             Ctrl* ctrl, hipStream_t s);
 hipError_t launch_cull_write(const RenderParams& rp, const uint32_t* cnt_rec, const unsigned long long* accbits,
                              const uint32_t* blk_tot, unsigned long long* off_rec, uint2* rec_pair, Ctrl* ctrl,
                              hipStream_t s);

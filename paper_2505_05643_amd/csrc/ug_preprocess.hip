@@ -8,29 +8,18 @@
 // of the blocks before it (at most 2048 of them, read coalesced), so offsets
 // never depend on scheduling and no block waits on another: records are
 // Gaussian-major with planes in order, and keys are in record order.
+#include <cfloat>
+
 #include "ug_conic.h"
 #include "ug_kernels.h"
 
 namespace ug {
 
 // ---------------------------------------------------------------- plane set-up
-// One thread per plane: FP64 constants of the pose (an invalid pose is marked
-// and skipped; the cull raises the flag).  Thread 0 clears the control block.
-__global__ __launch_bounds__(256) void k_init(ug_planes pl, const PlaneInt* __restrict__ pint,
-                                              PlaneConst* __restrict__ pc, PlaneCull* __restrict__ pcf,
-                                              Ctrl* __restrict__ ctrl) {
-  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid == 0) {
-    ctrl->n_rec = 0;
-    ctrl->n_key = 0;
-    ctrl->n_eval = 0;
-    ctrl->n_exec = 0;
-    ctrl->flags = 0;
-    ctrl->n_rec_eff = 0;
-    ctrl->n_key_eff = 0;
-  }
-  const int p = (int)gid;
-  if (p >= pl.p) return;
+// FP64 constants of plane p's pose (an invalid pose is marked and skipped; the
+// cull raises the flag) and the float constants of its cull.
+__device__ __forceinline__ PlaneCull plane_setup(const ug_planes& pl, const PlaneInt* __restrict__ pint, int p,
+                                                 PlaneConst* __restrict__ pc, PlaneCull* __restrict__ pcf) {
   double R[9];
   bool fin = true;
 #pragma unroll
@@ -78,21 +67,153 @@ __global__ __launch_bounds__(256) void k_init(ug_planes pl, const PlaneInt* __re
   q.valid = c.valid;
   q.pad = 0;
   pcf[p] = q;
+  return q;
+}
+
+// Bits of a float in the order of its value (-0 before +0).
+__device__ __forceinline__ uint32_t float_order(float x) {
+  const uint32_t b = __float_as_uint(x);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Whether two planes' group keys (validity, r3, o[0], o[1]) agree bit for bit.
+__device__ __forceinline__ bool group_key_eq(const PlaneCull& a, const PlaneCull& b) {
+  return a.valid == b.valid && __float_as_uint(a.r3[0]) == __float_as_uint(b.r3[0]) &&
+         __float_as_uint(a.r3[1]) == __float_as_uint(b.r3[1]) && __float_as_uint(a.r3[2]) == __float_as_uint(b.r3[2]) &&
+         __float_as_uint(a.o[0]) == __float_as_uint(b.o[0]) && __float_as_uint(a.o[1]) == __float_as_uint(b.o[1]);
+}
+
+// A 32-bit mix of the group key's bits (equal keys, equal hashes).
+__device__ __forceinline__ uint32_t group_key_hash(const PlaneCull& q) {
+  const uint32_t w[6] = {(uint32_t)q.valid, __float_as_uint(q.r3[0]), __float_as_uint(q.r3[1]),
+                         __float_as_uint(q.r3[2]), __float_as_uint(q.o[0]), __float_as_uint(q.o[1])};
+  uint32_t h = 0x811c9dc5u;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    h = (h ^ w[i]) * 0x9e3779b1u;
+    h ^= h >> 15;
+  }
+  return h;
+}
+
+// Groups of at least this many planes are searched by the cull.
+constexpr uint32_t kGroupSearch = 8;
+
+// One thread per plane; thread 0 clears the control block.  With group (a
+// launch of one block, at most kGroupMaxPlanes planes) the planes are also
+// ordered by (hash of the group key, o[2], index): each plane counts the
+// planes before it in that order (its position), those with a smaller hash
+// (its group's first position) and those with its hash (the group's size).
+// Every plane then checks that its key equals that of its group's first
+// plane; if two keys ever share a hash, the cull tests every plane instead.
+__global__ __launch_bounds__(256) void k_init(ug_planes pl, const PlaneInt* __restrict__ pint,
+                                              PlaneConst* __restrict__ pc, PlaneCull* __restrict__ pcf,
+                                              PlaneGroups* __restrict__ pg, int group, Ctrl* __restrict__ ctrl) {
+  __shared__ PlaneCull s_q[kGroupMaxPlanes];
+  __shared__ unsigned long long s_hz[kGroupMaxPlanes];  // hash << 32 | order bits of o[2]
+  __shared__ uint32_t s_first[kGroupMaxPlanes];         // plane at each group's first position
+  __shared__ uint32_t s_big, s_bad;
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid == 0) {
+    ctrl->n_rec = 0;
+    ctrl->n_key = 0;
+    ctrl->n_eval = 0;
+    ctrl->n_exec = 0;
+    ctrl->flags = 0;
+    ctrl->n_rec_eff = 0;
+    ctrl->n_key_eff = 0;
+  }
+  const int p = (int)gid;
+  const bool mine = p < pl.p;
+  PlaneCull q{};
+  if (mine) q = plane_setup(pl, pint, p, pc, pcf);
+  if (!group) {  // uniform (a launch argument)
+    if (gid == 0) pg->use = 0u;
+    return;
+  }
+  const uint32_t h = group_key_hash(q);
+  const unsigned long long hz = (unsigned long long)h << 32 | float_order(q.o[2]);
+  if (mine) {
+    s_q[p] = q;
+    s_hz[p] = hz;
+  }
+  if (threadIdx.x == 0) {
+    s_big = 0u;
+    s_bad = 0u;
+  }
+  __syncthreads();
+  uint32_t rank = 0u, below = 0u, same = 0u;
+  if (mine) {
+    for (int j = 0; j < pl.p; ++j) {  // the same j in every lane: broadcast reads
+      const unsigned long long o = s_hz[j];
+      rank += (o < hz || (o == hz && j < p)) ? 1u : 0u;
+      const uint32_t oh = (uint32_t)(o >> 32);
+      below += oh < h ? 1u : 0u;
+      same += oh == h ? 1u : 0u;
+    }
+    pg->perm[rank] = (uint32_t)p;
+    pg->oz[rank] = q.o[2];
+    pg->end[rank] = below + same;
+    if (rank == below) s_first[below] = (uint32_t)p;
+    if (q.valid && same >= kGroupSearch) atomicOr(&s_big, 1u);
+  }
+  __syncthreads();
+  if (mine && !group_key_eq(q, s_q[s_first[below]])) atomicOr(&s_bad, 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) pg->use = (s_big && !s_bad) ? 1u : 0u;
 }
 
 // Conservative float pre-test of Phase 1: false only if the exact (double)
 // test surely rejects the pair.  The float m3 is off by at most a few ulps of
 // sum |r3_i (mu_i - o_i)|, the float Sigma'_33 by a few ulps relative; the
 // margins below are ten times larger.
-__device__ __forceinline__ bool cull_maybe(const GaussT<float>& G, const PlaneCull& P, float chi2) {
+// Split in two: Sigma'_33 depends on the plane through r3 only, so planes
+// sharing r3 share it.
+__device__ __forceinline__ float cull_s33(const GaussT<float>& G, const PlaneCull& P) {
+  float g3[3];
+  fsub(G, P.r3[0], P.r3[1], P.r3[2], g3);
+  return g3[0] * g3[0] + g3[1] * g3[1] + g3[2] * g3[2];
+}
+__device__ __forceinline__ bool cull_test(const GaussT<float>& G, const PlaneCull& P, float S33, float chi2) {
   const float d0 = G.mu[0] - P.o[0], d1 = G.mu[1] - P.o[1], d2 = G.mu[2] - P.o[2];
   const float m3 = P.r3[0] * d0 + P.r3[1] * d1 + P.r3[2] * d2;
   const float slack = 2e-6f * (fabsf(P.r3[0] * d0) + fabsf(P.r3[1] * d1) + fabsf(P.r3[2] * d2));
-  float g3[3];
-  fsub(G, P.r3[0], P.r3[1], P.r3[2], g3);
-  const float S33 = g3[0] * g3[0] + g3[1] * g3[1] + g3[2] * g3[2];
   const float a = fmaxf(fabsf(m3) - slack, 0.f);
   return a * a <= chi2 * S33 * 1.0002f;  // false for NaN as well
+}
+__device__ __forceinline__ bool cull_maybe(const GaussT<float>& G, const PlaneCull& P, float chi2) {
+  return cull_test(G, P, cull_s33(G, P), chi2);
+}
+
+// Sorted positions [lo, hi) of a plane group (planes sharing r3, o[0] and
+// o[1], sorted by o[2]; P0 one of them) outside which cull_maybe rejects G.
+// It accepts only if |m3| - slack <= sqrt(chi2 S33 1.0002) up to float
+// rounding, where |m3| >= |r3_2 d2| - A with A = |r3_0 d0| + |r3_1 d1| (the
+// same for the whole group) and slack <= 2e-6 (A + |r3_2 d2|), so
+// |mu_2 - o_2| <= (sqrt(chi2 S33 1.0002) + A) (1 + 3e-6) / |r3_2|; the factors
+// below widen that well beyond every rounding of this bound, and an infinite
+// or undefined bound (no cut-off, r3_2 = 0) keeps the whole group.
+__device__ __forceinline__ void group_window(const GaussT<float>& G, const PlaneCull& P0, float S33, float chi2,
+                                             const float* oz, int& lo, int& hi) {
+  const float d0 = G.mu[0] - P0.o[0], d1 = G.mu[1] - P0.o[1];
+  const float A = fabsf(P0.r3[0] * d0) + fabsf(P0.r3[1] * d1);
+  const float D = (sqrtf(chi2 * S33 * 1.0002f) + A) * 1.001f / fabsf(P0.r3[2]);
+  const float mu = G.mu[2];
+  const float Dw = D * 1.001f + 1e-6f * fabsf(mu);
+  if (!(Dw <= FLT_MAX)) return;
+  const float vlo = mu - Dw, vhi = mu + Dw;
+  int a = lo, b = hi;  // first position with oz >= vlo
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (oz[m] < vlo) a = m + 1; else b = m;
+  }
+  int c = a, d = hi;  // first position with oz > vhi
+  while (c < d) {
+    const int m = (c + d) >> 1;
+    if (oz[m] <= vhi) c = m + 1; else d = m;
+  }
+  lo = a;
+  hi = c;
 }
 
 // ---------------------------------------------------------------- block scan
@@ -144,10 +265,23 @@ __device__ __forceinline__ unsigned long long block_prefix(const uint32_t* __res
 // one bit per (Gaussian, plane), 64 planes per word.
 template <int LPG>
 __global__ __launch_bounds__(256) void k_cull_count(ug_gaussians g, const PlaneCull* __restrict__ pcf,
-                                                    RenderParams rp, int gpb, uint32_t* __restrict__ cnt_rec,
+                                                    const PlaneGroups* __restrict__ pg, RenderParams rp, int gpb,
+                                                    uint32_t* __restrict__ cnt_rec,
                                                     unsigned long long* __restrict__ accbits,
                                                     uint32_t* __restrict__ blk_tot, Ctrl* __restrict__ ctrl) {
   __shared__ uint32_t s_tot;
+  // grouped planes (one lane per Gaussian): each group is searched for the
+  // window of planes the pre-test can accept, and only those are tested
+  __shared__ uint16_t s_perm[kGroupMaxPlanes], s_end[kGroupMaxPlanes];
+  __shared__ float s_oz[kGroupMaxPlanes];
+  const bool grouped = LPG == 1 && pg->use != 0u;  // uniform
+  if (grouped) {
+    for (int j = (int)threadIdx.x; j < rp.p; j += 256) {
+      s_perm[j] = (uint16_t)pg->perm[j];
+      s_end[j] = (uint16_t)pg->end[j];
+      s_oz[j] = pg->oz[j];
+    }
+  }
   if (threadIdx.x == 0) s_tot = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     for (int p = 0; p < rp.p; ++p)
@@ -169,6 +303,42 @@ __global__ __launch_bounds__(256) void k_cull_count(ug_gaussians g, const PlaneC
     if (has && sub == 0 && !G.finite) atomicOr(&ctrl->flags, kFlagNonfinite);
     const bool live = has && G.finite;
     uint32_t count = 0;
+    if (grouped) {
+      // at most 256 planes: four acceptance words, the word of plane q picked
+      // by compares (no indexed register array)
+      unsigned long long w0 = 0ull, w1 = 0ull, w2 = 0ull, w3 = 0ull;
+      if (live) {
+        for (int i = 0; i < rp.p;) {  // uniform: the groups in order
+          const int e = min(max((int)s_end[i], i + 1), rp.p);  // a group ends past its start
+          // the group's shared constants; each plane differs only in o[2]
+          PlaneCull pf = pcf[s_perm[i]];
+          const float S33 = cull_s33(G, pf);
+          int lo = i, hi = pf.valid ? e : i;
+          if ((uint32_t)(e - i) >= kGroupSearch) group_window(G, pf, S33, rp.chi2, s_oz, lo, hi);
+          for (int j = lo; j < hi; ++j) {
+            const int q = s_perm[j];
+            pf.o[2] = s_oz[j];
+            if (cull_test(G, pf, S33, rp.chi2)) {
+              const unsigned long long bit = 1ull << (q & 63);
+              const int w = q >> 6;
+              w0 |= w == 0 ? bit : 0ull;
+              w1 |= w == 1 ? bit : 0ull;
+              w2 |= w == 2 ? bit : 0ull;
+              w3 |= w == 3 ? bit : 0ull;
+            }
+          }
+          i = e;
+        }
+      }
+      if (has) {
+        for (int c = 0; c < nch; ++c)
+          accbits[(size_t)gi * nch + c] = c == 0 ? w0 : (c == 1 ? w1 : (c == 2 ? w2 : w3));
+        count = (uint32_t)(__popcll(w0) + __popcll(w1) + __popcll(w2) + __popcll(w3));
+        cnt_rec[gi] = count;
+        mine += count;
+      }
+      continue;
+    }
     for (int c = 0; c < nch; ++c) {
       const int pend = min(64, rp.p - c * 64);
       unsigned long long bits = 0;
@@ -680,25 +850,28 @@ uint32_t record_blocks(uint32_t rec_cap) {
   return nb < 1 ? 1 : nb;
 }
 
-hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, PlaneCull* pcf, Ctrl* ctrl,
-                       hipStream_t s) {
-  const uint32_t blocks = ((uint32_t)pl.p + 255) / 256;
-  hipLaunchKernelGGL(k_init, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, pl, pint, pc, pcf, ctrl);
+hipError_t launch_init(const ug_planes& pl, const PlaneInt* pint, PlaneConst* pc, PlaneCull* pcf, PlaneGroups* pg,
+                       bool group, Ctrl* ctrl, hipStream_t s) {
+  const bool grp = group && pl.p >= 1 && pl.p <= kGroupMaxPlanes;  // one block
+  const uint32_t blocks = grp ? 1u : ((uint32_t)pl.p + 255) / 256;
+  hipLaunchKernelGGL(k_init, dim3(blocks < 1 ? 1 : blocks), dim3(256), 0, s, pl, pint, pc, pcf, pg, grp ? 1 : 0,
+                     ctrl);
   return hipGetLastError();
 }
 
 size_t accbits_words(int n, int p) { return (size_t)n * (size_t)((p + 63) / 64); }
 
-hipError_t launch_cull_count(const ug_gaussians& g, const PlaneCull* pcf, const RenderParams& rp, uint32_t* cnt_rec,
-                             unsigned long long* accbits, uint32_t* blk_tot, Ctrl* ctrl, hipStream_t s) {
+hipError_t launch_cull_count(const ug_gaussians& g, const PlaneCull* pcf, const PlaneGroups* pg,
+                             const RenderParams& rp, uint32_t* cnt_rec, unsigned long long* accbits, uint32_t* blk_tot,
+                             Ctrl* ctrl, hipStream_t s) {
   const uint32_t nb = cull_blocks(rp.n, rp.p);
   if (nb == 0) return hipGetLastError();  // no Gaussians: the zeroed totals stand
   const int gpb = cull_gpb(rp.n, rp.p);
   switch (cull_lpg_log2(rp.n, rp.p)) {
 #define UG_CULL(L)                                                                                              \
   case L:                                                                                                       \
-    hipLaunchKernelGGL(k_cull_count<(1 << L)>, dim3(nb), dim3(256), 0, s, g, pcf, rp, gpb, cnt_rec, accbits, \
-                       blk_tot, ctrl);                                                                          \
+    hipLaunchKernelGGL(k_cull_count<(1 << L)>, dim3(nb), dim3(256), 0, s, g, pcf, pg, rp, gpb, cnt_rec, accbits, \
+                       blk_tot, ctrl);                                                                              \
     break;
     UG_CULL(0)
     UG_CULL(1)

@@ -62,7 +62,7 @@ def _create(L, n=10, wh=((16, 16),), **kw):
 
 @pytest.mark.parametrize("kw", [dict(n=-1), dict(wh=((0, 5),)), dict(wh=((40000, 5),)), dict(beta=0.0),
                                 dict(beta=float("nan")), dict(chi2=-1.0), dict(chi2=float("nan")),
-                                dict(bg_alpha=0.0), dict(box_mode=7), dict(flags=4), dict(flags=16), dict(tile_w=12),
+                                dict(bg_alpha=0.0), dict(box_mode=7), dict(flags=4), dict(flags=32), dict(tile_w=12),
                                 dict(flags=8, tile_w=32, tile_h=32, lds_batch=256),
                                 dict(lds_batch=48), dict(tile_w=8, tile_h=8, px_per_lane=2),
                                 dict(bg_color=float("inf")),

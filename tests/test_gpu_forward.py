@@ -262,6 +262,50 @@ def test_binning_keys_and_ranges(R):
             print((tw, th, bm), "keys", n, "records", len(recs))
 
 
+def test_cull_plane_groups_equal_per_plane_cull(R):
+    """Planes that differ only in the origin's third coordinate are culled by
+    searching each group for the window of planes the pre-test can accept;
+    the records, the sorted keys and the image equal those of the per-plane
+    cull (UG_FLAG_CULL_EACH_PLANE) bit for bit.  Planes: an axial stack in
+    shuffled order with repeated heights, a tilted stack (one rotation and
+    origin x, y; heights varied), and single oblique planes; with a cut-off
+    in both box modes and without one.  The grouped image is also checked
+    against the oracle on sampled pixels."""
+    from tests.parity import reference_points
+    import oracle
+    g = synth.make_gaussians(3000, 95, (0, 0, 0), (1, 1, 1), (0.005, 0.05), aniso_max=6.0, opacity="random")
+    rng = np.random.default_rng(96)
+    frames, origins = [], []
+    for zz in rng.permutation(np.concatenate([np.linspace(0.02, 0.98, 40), [0.5, 0.5, 0.25]])):
+        frames.append(np.eye(3))
+        origins.append((0.5, 0.5, zz))
+    tilt = synth.axis_angle((1.0, 0.3, 0.0), 0.5)
+    for zz in rng.uniform(0.1, 0.9, 20):
+        frames.append(tilt)
+        origins.append((0.45, 0.55, zz))
+    for _ in range(5):
+        frames.append(synth.axis_angle(rng.standard_normal(3), rng.uniform(0.2, 3.0)))
+        origins.append(rng.uniform(0.3, 0.7, 3))
+    P = len(frames)
+    pl = synth.pack_planes(frames, origins, [(1 / 48, 1 / 48)] * P, [(48, 48)] * P)
+    each = R._lib.UG_FLAG_CULL_EACH_PLANE
+    for kw in (dict(box_mode=1), dict(box_mode=2), dict(box_mode=1, chi2=math.inf)):
+        img_g, plan_g = _render(R, g, pl, R.Params(**kw))
+        img_e, plan_e = _render(R, g, pl, R.Params(flags=each, **kw))
+        rg, re_ = plan_g.debug_records(), plan_e.debug_records()
+        assert rg.size == re_.size and rg.tobytes() == re_.tobytes()
+        for a, b in zip(plan_g.debug_keys(), plan_e.debug_keys()):
+            assert np.array_equal(a, b)
+        assert np.array_equal(img_g.view(np.uint32), img_e.view(np.uint32))
+        print(kw, "records", rg.size)
+        if kw.get("chi2") is None:
+            pix = synth.sample_pixels(pl, 1500, 97)
+            offs = pl.pixel_offsets()
+            flat = offs[pix[:, 0]] + pix[:, 2] * pl.wh[pix[:, 0], 0] + pix[:, 1]
+            ref, _ = reference_points(g, oracle.plane_points(pl, pix), plan_g.params)
+            check_image(img_g[flat], g, pl, plan_g.params, pix=pix, ref=ref)
+
+
 def test_emission_layout_small_and_whole_plane_records(R):
     """Key emission for rounds of 256 records of a few keys each (512 small
     Gaussians) and rounds of tens of thousands (256 that cover the whole
