@@ -144,6 +144,7 @@ __global__ __launch_bounds__(256) void k_init(ug_planes pl, const PlaneInt* __re
   __syncthreads();
   uint32_t rank = 0u, below = 0u, same = 0u;
   if (mine) {
+#pragma unroll 8
     for (int j = 0; j < pl.p; ++j) {  // the same j in every lane: broadcast reads
       const unsigned long long o = s_hz[j];
       rank += (o < hz || (o == hz && j < p)) ? 1u : 0u;
