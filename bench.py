@@ -368,10 +368,11 @@ def main():
     sizes = dict(n=g.n, p=pl.p, r=n_rec, k=n_key, t=plan.num_tiles, m=int(pl.npix), passes=passes,
                  w=(pl.p + 63) // 64, rows=params.box_mode == 2, g_sort=g_sort, dslots=dslots)
     kernels = {}
+    cull_grouped = cull_searches_groups(pl, params, g.n)
     for nm, (ms, n) in stages.items():
         avg = ms / max(n, 1)
         row = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps, "avg_launch_ms": avg}
-        if nm in FLOPS_PER_PAIR or nm == "cull_count":
+        if nm in FLOPS_PER_PAIR or (nm == "cull_count" and not cull_grouped):
             if nm == "cull_count":
                 flop = FLOPS_PER_CULL_TEST * g.n * pl.p
                 work = f"{FLOPS_PER_CULL_TEST} flop x {g.n} x {pl.p} (Gaussian, plane) tests per launch"
@@ -388,6 +389,8 @@ def main():
             ach = nbytes / (avg / 1e3) / 1e9
             row.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                        work=f"{nbytes} algorithmic bytes per launch")
+            if nm == "cull_count":
+                row["work"] += " (grouped search over parallel slices: not N x P tests)"
         kernels[nm] = row
     dom_name = max(kernels, key=lambda nm: kernels[nm]["ms_per_step"])
     d = kernels[dom_name]
@@ -715,6 +718,31 @@ def replay_ms(fn, warmup, steps):
     t1.record()
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
+
+
+def cull_searches_groups(pl, params, n) -> bool:
+    """Whether the Phase-1 cull takes its grouped search (the library's rule,
+    restated on the host): at most 256 planes, one lane per Gaussian (the
+    cull splits planes over lanes while n x lanes < 2^18), the per-plane flag
+    unset, and at least eight valid planes sharing the bits of the normal row
+    of R^-1 (computed as the library does, FP64 adjugate over determinant,
+    then float) and of the origin's x and y.  Then the cull tests only the
+    planes inside each Gaussian's window and its flop count is not N x P."""
+    from paper_2505_05643_amd._lib import UG_FLAG_CULL_EACH_PLANE
+    if pl.p > 256 or pl.p < 8 or (params.flags & UG_FLAG_CULL_EACH_PLANE):
+        return False
+    if pl.p > 1 and n < (1 << 18):
+        return False
+    groups = {}
+    for q in range(pl.p):
+        a, b, c, d, e, f, g_, h, i = (float(x) for x in pl.rot[q].astype(np.float64))
+        det = a * (e * i - f * h) + b * (-(d * i - f * g_)) + c * (d * h - e * g_)
+        if not (np.isfinite(det) and det > 0):
+            continue
+        r3 = np.array([(d * h - e * g_) / det, -(a * h - b * g_) / det, (a * e - b * d) / det], dtype=np.float32)
+        key = (r3.tobytes(), pl.origin[q, 0].tobytes(), pl.origin[q, 1].tobytes())
+        groups[key] = groups.get(key, 0) + 1
+    return max(groups.values(), default=0) >= 8
 
 
 def plan_bits(plan) -> int:
