@@ -213,6 +213,7 @@ struct Footprint {
   RecAcc acc;
   RecGeo geo;
   uint32_t keys;
+  uint32_t spans[kRowSpans];  // ROWS mode: as in Rec
 };
 
 // Column ranges of the record's ellipse over bands of pixel rows.  The
@@ -335,8 +336,11 @@ __device__ __forceinline__ bool rows_span(const BandPrep& bp, int ty, int TW, in
 }
 
 // Key count of a ROWS-mode record over its tile rectangle (rows_span summed
-// over its tile rows).
-__device__ __forceinline__ uint32_t rows_count(const RecAcc& ra, const RecGeo& geo, int W, int H, int TW, int TH) {
+// over its tile rows), and the spans of its first kRowSpans tile rows.
+__device__ __forceinline__ uint32_t rows_count(const RecAcc& ra, const RecGeo& geo, int W, int H, int TW, int TH,
+                                               uint32_t (&spans)[kRowSpans]) {
+#pragma unroll
+  for (int i = 0; i < kRowSpans; ++i) spans[i] = kNoSpan;
   const int umin = geo.tx0 * TW;
   const int umax = min(geo.tx1 * TW + TW - 1, W - 1);
   BandPrep bp;
@@ -344,7 +348,13 @@ __device__ __forceinline__ uint32_t rows_count(const RecAcc& ra, const RecGeo& g
   uint32_t keys = 0;
   for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
     int tx0, tx1;
-    if (rows_span(bp, ty, TW, TH, H, umin, umax, tx0, tx1)) keys += (uint32_t)(tx1 - tx0 + 1);
+    if (rows_span(bp, ty, TW, TH, H, umin, umax, tx0, tx1)) {
+      keys += (uint32_t)(tx1 - tx0 + 1);
+      const int i = ty - geo.ty0;
+#pragma unroll
+      for (int k = 0; k < kRowSpans; ++k)
+        if (i == k) spans[k] = (uint32_t)tx0 | (uint32_t)tx1 << 16;
+    }
   }
   return keys;
 }
@@ -431,7 +441,7 @@ __device__ __forceinline__ bool make_footprint(const GaussIn& G, const PlaneCons
   f.geo.ty0 = (uint16_t)tile_of(vlo, TH);
   f.geo.ty1 = (uint16_t)tile_of(vhi, TH);
   if (box_mode == UG_BOX_ROWS) {
-    f.keys = rows_count(f.acc, f.geo, PI.W, PI.H, TW, TH);
+    f.keys = rows_count(f.acc, f.geo, PI.W, PI.H, TW, TH, f.spans);
   } else {
     f.keys = (uint32_t)(f.geo.tx1 - f.geo.tx0 + 1) * (uint32_t)(f.geo.ty1 - f.geo.ty0 + 1);
   }

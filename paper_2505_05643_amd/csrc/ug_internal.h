@@ -122,11 +122,17 @@ static_assert(sizeof(RecGeo) == 16, "RecGeo layout");
 
 // A record as stored: both parts in one 64-byte slot, so the accumulate
 // kernels' gathers (one record per key, in tile order: random in record
-// order) fetch one 64-byte segment per key instead of two.
+// order) fetch one 64-byte segment per key instead of two.  The slot's last
+// 16 bytes carry, for ROWS-mode binning, the tile span of each of the
+// record's first kRowSpans tile rows as counted by the record kernel
+// (tx0 | tx1 << 16; kNoSpan for a row the ellipse misses), so the emission
+// reuses them instead of recomputing them; unused in the other modes.
+constexpr int kRowSpans = 4;
+constexpr uint32_t kNoSpan = 1u;  // tx0 = 1 > tx1 = 0
 struct Rec {
   RecAcc acc;
   RecGeo geo;
-  uint32_t pad[4];
+  uint32_t spans[kRowSpans];
 };
 static_assert(sizeof(Rec) == 64, "Rec layout");
 

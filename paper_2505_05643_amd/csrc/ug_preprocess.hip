@@ -421,8 +421,8 @@ __device__ __forceinline__ uint32_t record_rpb_dev(uint32_t nrec, uint32_t grid)
   const uint32_t per = (rounds + grid - 1u) / grid;
   return (per < 1u ? 1u : per) * 256u;
 }
-__device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, const PlaneInt& PI, int box_mode,
-                                          int TW, int TH, uint32_t r, uint32_t e, uint32_t e_end,
+__device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, const uint4& spans, const PlaneInt& PI,
+                                          int box_mode, int TW, int TH, uint32_t r, uint32_t e, uint32_t e_end,
                                           uint32_t* __restrict__ key_tile, uint32_t* __restrict__ rec_of_key) {
   const int mshift = key_mask_shift(TW, TH);
   const int umin = geo.tx0 * TW;
@@ -432,7 +432,18 @@ __device__ __forceinline__ void emit_keys(const RecAcc& ra, const RecGeo& geo, c
   if (box_mode == UG_BOX_ROWS && !ok) return;
   for (int ty = geo.ty0; ty <= geo.ty1; ++ty) {
     int tx0 = geo.tx0, tx1 = geo.tx1;
-    if (box_mode == UG_BOX_ROWS && !rows_span(bp, ty, TW, TH, PI.H, umin, umax, tx0, tx1)) continue;
+    if (box_mode == UG_BOX_ROWS) {
+      // the record kernel's span for the first kRowSpans rows, else recomputed
+      const int i = ty - (int)geo.ty0;
+      if (i < kRowSpans) {
+        const uint32_t w = i == 0 ? spans.x : (i == 1 ? spans.y : (i == 2 ? spans.z : spans.w));
+        tx0 = (int)(w & 0xffffu);
+        tx1 = (int)(w >> 16);
+        if (tx0 > tx1) continue;
+      } else if (!rows_span(bp, ty, TW, TH, PI.H, umin, umax, tx0, tx1)) {
+        continue;
+      }
+    }
     int bua[kMaxBands], buz[kMaxBands];
     if (ok) {
       band_ranges(bp, ty, TH, PI.H, umin, umax, bua, buz);
@@ -492,6 +503,7 @@ __global__ __launch_bounds__(STAGE ? 512 : 256) void k_record(ug_gaussians g, co
   if (threadIdx.x == 0) s_tot = 0;
   __syncthreads();
   const double chi2 = (double)rp.chi2;
+  const bool rows = rp.box_mode == UG_BOX_ROWS && !rp.box_support;  // the records carry their row spans
   uint32_t mine = 0;
   const uint32_t r_end = min(r_begin + rpb, nrec);
   for (uint32_t r = r_begin + threadIdx.x; r < r_end; r += NT) {
@@ -517,6 +529,7 @@ __global__ __launch_bounds__(STAGE ? 512 : 256) void k_record(ug_gaussians g, co
     }
     recs[r].acc = f.acc;
     recs[r].geo = f.geo;
+    if (rows) *reinterpret_cast<uint4*>(recs[r].spans) = make_uint4(f.spans[0], f.spans[1], f.spans[2], f.spans[3]);
     rec_nkey[r] = f.keys;
     mine += f.keys;
   }
@@ -553,11 +566,13 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
   uint32_t pl, nk;
   RecAcc ra;
   RecGeo ge;
+  uint4 sp;
   {
     const uint32_t rl = act ? r : r_end - 1u;
     pl = rec_pair[rl].y;
     ra = recs[rl].acc;
     ge = recs[rl].geo;
+    sp = *reinterpret_cast<const uint4*>(recs[rl].spans);
     nk = act ? rec_nkey[rl] : 0u;
   }
   unsigned long long carry = block_prefix(blk_tot, blockIdx.x, s_sh);
@@ -569,6 +584,7 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
     const uint32_t pln = rec_pair[rl].y;
     const RecAcc ran = recs[rl].acc;
     const RecGeo gen = recs[rl].geo;
+    const uint4 spn = *reinterpret_cast<const uint4*>(recs[rl].spans);
     const uint32_t nkl = rec_nkey[rl];
     const uint32_t nkn = actn ? nkl : 0u;
     unsigned long long tot;
@@ -577,7 +593,7 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
     if (act) {
       rec_koff[r] = (uint32_t)(koff < rp.key_cap ? koff : rp.key_cap);
       if (nk > 0 && koff + nk <= rp.key_cap)
-        emit_keys(ra, ge, PI, rp.box_mode, rp.tile_w, rp.tile_h, r, (uint32_t)koff, (uint32_t)(koff + nk),
+        emit_keys(ra, ge, sp, PI, rp.box_mode, rp.tile_w, rp.tile_h, r, (uint32_t)koff, (uint32_t)(koff + nk),
                   key_tile, rec_of_key);
     }
     r = rn;
@@ -585,6 +601,7 @@ __global__ __launch_bounds__(256) void k_emit(const PlaneInt* __restrict__ pint,
     nk = nkn;
     ra = ran;
     ge = gen;
+    sp = spn;
     PI = pint[pln];
   }
   if (blockIdx.x == nact - 1 && threadIdx.x == 0) {
