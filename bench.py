@@ -764,9 +764,9 @@ def kernel_bytes(name, n, p, r, k, t, m, passes, w, rows, g_sort, dslots) -> int
     if name == "cull_write":
         return 4 * n + 8 * n * w + 8 * n + 8 * r
     if name == "record":
-        return 8 * r + 44 * n + 52 * r
+        return 8 * r + 44 * n + 52 * r + (16 * r if rows else 0)
     if name == "emit":
-        return 4 * r + 16 * r + (32 * r if rows else 0) + 4 * r + 8 * k
+        return 4 * r + 16 * r + (48 * r if rows else 0) + 4 * r + 8 * k
     if name == "sort_hist":
         return 4 * k
     if name == "sort_scan":
