@@ -726,7 +726,7 @@ def cull_searches_groups(pl, params, n) -> bool:
     cull splits planes over lanes while n x lanes < 2^18), the per-plane flag
     unset, and at least eight valid planes sharing the bits of the normal row
     of R^-1 (computed as the library does, FP64 adjugate over determinant,
-    then float) and of the origin's x and y.  Then the cull tests only the
+    then float, with -0 as +0) and of the origin's x and y.  Then the cull tests only the
     planes inside each Gaussian's window and its flop count is not N x P."""
     from paper_2505_05643_amd._lib import UG_FLAG_CULL_EACH_PLANE
     if pl.p > 256 or pl.p < 8 or (params.flags & UG_FLAG_CULL_EACH_PLANE):
@@ -740,6 +740,7 @@ def cull_searches_groups(pl, params, n) -> bool:
         if not (np.isfinite(det) and det > 0):
             continue
         r3 = np.array([(d * h - e * g_) / det, -(a * h - b * g_) / det, (a * e - b * d) / det], dtype=np.float32)
+        r3 = r3 + np.float32(0.0)  # -0 as +0, as the library keys it
         key = (r3.tobytes(), pl.origin[q, 0].tobytes(), pl.origin[q, 1].tobytes())
         groups[key] = groups.get(key, 0) + 1
     return max(groups.values(), default=0) >= 8

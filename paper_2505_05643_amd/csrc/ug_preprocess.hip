@@ -62,7 +62,7 @@ __device__ __forceinline__ PlaneCull plane_setup(const ug_planes& pl, const Plan
   PlaneCull q;
   for (int k = 0; k < 3; ++k) {
     q.o[k] = pl.origin[3 * p + k];
-    q.r3[k] = (float)c.rinv[6 + k];
+    q.r3[k] = (float)c.rinv[6 + k] + 0.f;  // -0 as +0 (same test; one group key per normal)
   }
   q.valid = c.valid;
   q.pad = 0;

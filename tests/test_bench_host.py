@@ -30,3 +30,41 @@ def test_sources_digest_is_stable_and_covers_the_kernels():
 def test_plan_ppl_default():
     assert bench.plan_ppl(_params(ppl=0, tw=32)) == 4
     assert bench.plan_ppl(_params(ppl=2)) == 2
+
+
+def test_stored_traffic_is_calibrated_on_the_copy_probe():
+    """The committed counter summaries scale FETCH_SIZE and WRITE_SIZE by what
+    the same counters read for a plain copy of known size; on this GPU that is
+    about 2 and 1.  A summary calibrated on some other kernel would carry
+    factors thousands of times larger and per-launch bytes beyond any HBM."""
+    import json
+    for k in (1, 4):
+        with open(bench.traffic_file(k)) as f:
+            line = next(ln for ln in f if ln.startswith("traffic-json: "))
+        rec = json.loads(line[len("traffic-json: "):])
+        assert 1.5 < rec["fetch_scale"] < 2.5 and 0.75 < rec["write_scale"] < 1.5, rec
+        assert rec["bytes_per_launch"] and max(rec["bytes_per_launch"].values()) < 64e9
+
+
+def test_cull_group_rule():
+    """The benchmark's restatement of when the Phase-1 cull searches plane
+    groups: planes sharing the normal row of R^-1 and the origin's x and y,
+    eight or more of them, at most 256 planes, one lane per Gaussian, and
+    the per-plane flag unset."""
+    import numpy as np
+    from paper_2505_05643_amd import synth
+    from paper_2505_05643_amd._lib import UG_FLAG_CULL_EACH_PLANE
+    p4 = synth.config_planes(4)
+    assert bench.cull_searches_groups(p4, _params(flags=0), 1_000_000)
+    assert not bench.cull_searches_groups(p4, _params(flags=UG_FLAG_CULL_EACH_PLANE), 1_000_000)
+    assert not bench.cull_searches_groups(p4, _params(flags=0), 50_000)  # several lanes per Gaussian
+    for k in (0, 1, 2, 3):
+        assert not bench.cull_searches_groups(synth.config_planes(k), _params(flags=0), 1_000_000)
+    # same normal, in-plane rotations differing: still one group
+    frames = [synth.frame_from_normal((0.0, 0.0, 1.0), a) for a in np.linspace(0.0, 3.0, 10)]
+    pl = synth.pack_planes(frames, [(0.5, 0.5, z) for z in np.linspace(0.1, 0.9, 10)], [(0.01, 0.01)] * 10,
+                           [(32, 32)] * 10)
+    assert bench.cull_searches_groups(pl, _params(flags=0), 1_000_000)
+    # origins differing in x: no group
+    pl.origin[:, 0] = np.linspace(0.1, 0.9, 10)
+    assert not bench.cull_searches_groups(pl, _params(flags=0), 1_000_000)

@@ -268,7 +268,8 @@ def test_cull_plane_groups_equal_per_plane_cull(R):
     the records, the sorted keys and the image equal those of the per-plane
     cull (UG_FLAG_CULL_EACH_PLANE) bit for bit.  Planes: an axial stack in
     shuffled order with repeated heights, a tilted stack (one rotation and
-    origin x, y; heights varied), and single oblique planes; with a cut-off
+    origin x, y; heights varied), a stack of one normal turned to different
+    in-plane angles, and single oblique planes; with a cut-off
     in both box modes and without one.  The grouped image is also checked
     against the oracle on sampled pixels."""
     from tests.parity import reference_points
@@ -283,6 +284,9 @@ def test_cull_plane_groups_equal_per_plane_cull(R):
     for zz in rng.uniform(0.1, 0.9, 20):
         frames.append(tilt)
         origins.append((0.45, 0.55, zz))
+    for zz, ang in zip(rng.uniform(0.1, 0.9, 12), np.linspace(0.1, 3.0, 12)):  # one normal, turned in-plane
+        frames.append(synth.frame_from_normal((0.0, 0.0, 1.0), ang))
+        origins.append((0.52, 0.48, zz))
     for _ in range(5):
         frames.append(synth.axis_angle(rng.standard_normal(3), rng.uniform(0.2, 3.0)))
         origins.append(rng.uniform(0.3, 0.7, 3))
